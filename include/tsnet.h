@@ -1,0 +1,238 @@
+/*
+ * tsnet.h -- C ABI of the MI355X (gfx950) L-tsNET gradient library.
+ *
+ * The library computes, on one GPU, the per-iteration gradient of the tsNET
+ * cost (Eq. 1 of Meidiana, Hong and Ma, "BH-tsNET, FIt-tsNET, L-tsNET: Fast
+ * tsNET Algorithms for Large Graph Drawing") the way L-tsNET does it
+ * (Algorithm 3, Sec. 3.3): a sparse attractive KL term over the partial-BFS
+ * affinities P, FFT-accelerated interpolation for the KL repulsion with its
+ * normaliser Z, the same interpolation for the entropy sums of Eq. (8), the
+ * compression term, and the vertex move.
+ *
+ * Conventions shared by every call:
+ *  - Return value: TSNET_OK (0) or a negative TSNET_E* code. No C++
+ *    exception crosses this boundary. tsnet_last_error() returns a message
+ *    for the calling thread's most recent failure.
+ *  - Pointers are DEVICE pointers unless the name or comment says host.
+ *    Device buffers passed in are owned by the caller and must stay alive
+ *    until the enqueued work that uses them has completed.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Calls validate their arguments on the host, then enqueue asynchronously
+ *    on `stream`, except where a call is marked "synchronous".
+ *  - Layout: X, G, F_* and update/gains are row-major [n][2] float (x, y).
+ *    Vertex ids are global across a batch of graphs; graph g owns the
+ *    vertices [graph_offsets[g], graph_offsets[g+1]) and is an independent
+ *    layout problem with its own n, P normalisation, grid and Z.
+ *  - A context must not be used from two threads at once. Calls on one
+ *    context and one stream are ordered; the library uses no other stream.
+ */
+#ifndef TSNET_H
+#define TSNET_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TSNET_OK       0
+#define TSNET_EINVAL  (-1)   /* bad argument, bad CSR, unsupported size      */
+#define TSNET_EHIP    (-2)   /* HIP runtime error                              */
+#define TSNET_ENOMEM  (-3)   /* device allocation failed                       */
+#define TSNET_EGRID   (-4)   /* non-finite layout (NaN/Inf) seen by the grid   */
+
+/* tie_mode of tsnet_build_P */
+#define TSNET_TIE_HASH 0     /* key = SplitMix64 hash of (seed, source, target) */
+#define TSNET_TIE_ID   1     /* key = target id                                 */
+
+/* bits of the device status word (tsnet_status) */
+#define TSNET_STATUS_NONFINITE   0x1u  /* NaN/Inf in X at some grid set-up          */
+#define TSNET_STATUS_GRID_CAPPED 0x2u  /* span / interval_width > max_intervals      */
+#define TSNET_STATUS_ROW_LOW     0x4u  /* some row could not reach u from below      */
+#define TSNET_STATUS_ROW_HIGH    0x8u  /* some row could not reach u from above      */
+#define TSNET_STATUS_ROW_EMPTY   0x10u /* some vertex has no neighbour               */
+
+typedef struct tsnet_ctx_s* tsnet_ctx;   /* per-device state: twiddles, status, timers */
+typedef struct tsnet_P_s*   tsnet_P;     /* one problem: graph batch, P, workspace      */
+
+/*
+ * Cost weights and interpolation settings.
+ *  lambda_kl, lambda_c, lambda_r: the multipliers of Eq. (1) (Sec. 2.1).
+ *  eps_r: the entropy regulariser epsilon (1/20, Sec. 3.3).
+ *  interval_width: target box side h of the interpolation grid; the box count
+ *    per axis is ceil(span / h) clamped to [min_intervals, max_intervals] and
+ *    rounded up to a power of two (the paper leaves I and P open, Sec. 2.3).
+ *  min_intervals >= 1, max_intervals a power of two in [min_intervals, 256].
+ *  nodes_per_interval: interpolation points per box and axis; must be 3.
+ */
+typedef struct {
+  double  lambda_kl;
+  double  lambda_c;
+  double  lambda_r;
+  double  eps_r;
+  double  interval_width;
+  int32_t min_intervals;
+  int32_t max_intervals;
+  int32_t nodes_per_interval;
+  int32_t reserved;
+} tsnet_params;
+
+/*
+ * Vertex move (the last step of the loop of Algorithm 3; the paper names no
+ * optimiser): gains <- gains + gain_up where sign(g) != sign(update), else
+ * gains * gain_down, floored at min_gain; update <- mu * update - eta * gains * g;
+ * X <- X + update. mu = momentum_early for iter < momentum_switch_iter, else
+ * momentum_late. eta <= 0 selects max(200, n_g / 12) per graph.
+ */
+typedef struct {
+  double  eta;
+  double  momentum_early;
+  double  momentum_late;
+  double  min_gain;
+  double  gain_up;
+  double  gain_down;
+  int32_t momentum_switch_iter;
+  int32_t reserved;
+} tsnet_step_params;
+
+/* Defaults: 1, 1.2, 0.01, 0.05, h = 0.25, 50..256 intervals, 3 nodes. */
+void tsnet_default_params(tsnet_params* p);
+/* Defaults: eta <= 0 (per-graph rule), 0.5 / 0.8 switching at 250, 0.01, 0.2, 0.8. */
+void tsnet_default_step_params(tsnet_step_params* p);
+
+/* Create a context on HIP device `device` (made current for the call). */
+int tsnet_ctx_create(tsnet_ctx* out, int device);
+/* Synchronous; frees everything the context owns. NULL is accepted. */
+int tsnet_ctx_destroy(tsnet_ctx ctx);
+
+/*
+ * C0 of Algorithm 3: build the symmetric affinities P of a graph batch.
+ *  For every vertex, a breadth-first search stops once k other vertices are
+ *  visited (Sec. 3.1), ties at equal hop distance broken by a reproducible
+ *  key (tie_mode, tie_seed); p_{j|i} follows Eq. (3) with the bandwidth of
+ *  each row set by FP64 bisection to perplexity `perplexity`; rows that
+ *  cannot reach it take the limiting uniform distribution and set a status
+ *  bit; P = (p_{j|i} + p_{i|j}) / (2 n'_g) per Eq. (2), with n'_g the number of
+ *  non-empty rows of the graph, over the union of the selected pairs and
+ *  their transposes.
+ *  indptr [n+1] int64, indices [num_arcs] int32: device CSR of an undirected
+ *    simple graph (every edge stored in both rows, rows sorted ascending, no
+ *    self loops, no arc between different graphs). Checked on the device;
+ *    a violation returns TSNET_EINVAL.
+ *  graph_offsets_host: host int32 [num_graphs+1], 0 = first, n = last; NULL
+ *    means one graph (num_graphs must then be 1).
+ *  k: neighbours per vertex; 0 selects floor(3 * perplexity). 1 <= k <= 1024.
+ *  Synchronous (reads back the number of nonzeros). On success *out owns
+ *  all device memory of the problem; free it with tsnet_P_free.
+ */
+int tsnet_build_P(tsnet_ctx ctx, const int64_t* indptr, const int32_t* indices,
+                  int32_t n, int64_t num_arcs,
+                  const int32_t* graph_offsets_host, int32_t num_graphs,
+                  double perplexity, int32_t k, uint64_t tie_seed, int32_t tie_mode,
+                  tsnet_P* out, void* stream);
+
+/*
+ * Make a problem from a host CSR of P (rows sorted, values >= 0, symmetric by
+ * contract, not checked). For tests and callers that build P elsewhere.
+ * Synchronous. beta/status/conditional rows are absent for such a problem.
+ */
+int tsnet_P_from_host(tsnet_ctx ctx, int32_t n, const int64_t* rowptr_host,
+                      const int32_t* col_host, const float* val_host,
+                      const int32_t* graph_offsets_host, int32_t num_graphs, tsnet_P* out);
+
+/* Sizes of a problem (host outputs; any may be NULL). */
+int tsnet_P_info(tsnet_P P, int64_t* n, int64_t* nnz, int32_t* num_graphs, int32_t* k);
+
+/*
+ * Synchronous copy-out of P and of the conditional rows. Every pointer may be
+ * host or device memory, or NULL to skip it. Sizes: rowptr [n+1], col/val
+ * [nnz], beta [n] (+inf for rows saturated from above), status [n]
+ * (0 ok, 1 low, 2 high, 3 empty), cond_len [n], cond_nbr/cond_dist [n*k]
+ * (row i holds cond_len[i] neighbours sorted by (hop distance, tie key, id)).
+ * Returns TSNET_EINVAL if conditional data is asked of a problem made by
+ * tsnet_P_from_host.
+ */
+int tsnet_P_export(tsnet_P P, int64_t* rowptr, int32_t* col, float* val, double* beta,
+                   int8_t* status, int32_t* cond_len, int32_t* cond_nbr, uint16_t* cond_dist);
+
+/* Synchronous; frees the problem. NULL is accepted. */
+int tsnet_P_free(tsnet_P P);
+
+/*
+ * One evaluation of dC/dX (Eq. 1 with Eq. 6 and Eq. 8), FP32 interpolation
+ * path: G_i = 4 lambda_kl (F_attr,i - F_rep,i / Z) + (lambda_c / n_g) X_i
+ *             - (lambda_r / n_g^2) F_ent,i.
+ *  X [n][2] float in, G [n][2] float out (may not alias X).
+ *  Z_out: device double [num_graphs] or NULL.
+ * Non-finite X sets TSNET_STATUS_NONFINITE and yields non-finite G.
+ */
+int tsnet_grad(tsnet_ctx ctx, tsnet_P P, const float* X, const tsnet_params* prm,
+               float* G, double* Z_out, void* stream);
+
+/*
+ * Same evaluation, also writing its parts (each output may be NULL):
+ *  F_attr, F_rep, F_ent [n][2] float as in the formula above; Z_i [n] float,
+ *  the interpolated sum_{j != i} (1 + ||X_i - X_j||^2)^-1.
+ */
+int tsnet_grad_terms(tsnet_ctx ctx, tsnet_P P, const float* X, const tsnet_params* prm,
+                     float* G, double* Z_out, float* F_attr, float* F_rep, float* F_ent,
+                     float* Z_i, void* stream);
+
+/*
+ * The vertex move, in place on X, update, gains ([n][2] float each) with the
+ * gradient G of the current iteration `iter` (0-based).
+ */
+int tsnet_step(tsnet_ctx ctx, tsnet_P P, float* X, float* update, float* gains,
+               const float* G, const tsnet_step_params* sp, int32_t iter, void* stream);
+
+/*
+ * The cost of Eq. (1) with the entropy as -lambda_r / (4 n^2) sum ln(eps + r^2)
+ * (the form whose gradient is Eq. 8), evaluated with the same interpolation:
+ *  cost: device double [num_graphs][4] = {C_KL, C_CMP, C_ENT, total}.
+ */
+int tsnet_cost(tsnet_ctx ctx, tsnet_P P, const float* X, const tsnet_params* prm,
+               double* cost, void* stream);
+
+/*
+ * Exact all-pairs FP64 gradient (the O(n^2) tsNET evaluation over the same
+ * sparse P), the comparison baseline. X, G [n][2] double.
+ *  rows: NULL for every vertex, else device int32 [nrows] vertex ids; G is
+ *    then [nrows][2] and only those rows are evaluated (Z is still summed over
+ *    all pairs of each graph).
+ *  terms: NULL or device double [nrows or n][7] = {F_attr x,y, F_rep x,y,
+ *    F_ent x,y, Z_i}.
+ *  Z_out: NULL or device double [num_graphs].
+ */
+int tsnet_grad_direct_f64(tsnet_ctx ctx, tsnet_P P, const double* X, const tsnet_params* prm,
+                          double* G, double* Z_out, const int32_t* rows, int32_t nrows,
+                          double* terms, void* stream);
+
+/*
+ * Grid of the most recent tsnet_grad / tsnet_cost on P, per graph (host
+ * arrays [num_graphs], any may be NULL): intervals per axis, box side,
+ * lower-left corner. Synchronous.
+ */
+int tsnet_grid_info(tsnet_P P, int32_t* n_intervals, float* box_side, float* x0, float* y0);
+
+/* Synchronous: OR of the TSNET_STATUS_* bits raised since the last call; clears them. */
+int tsnet_status(tsnet_ctx ctx, uint32_t* flags_host);
+
+/*
+ * Per-stage GPU timing for profiling. When on, each stage of tsnet_grad /
+ * tsnet_step is bracketed by HIP events on the call's stream.
+ * tsnet_stage_times (synchronous) returns accumulated milliseconds and call
+ * counts per stage and resets them; names via tsnet_stage_name.
+ */
+int tsnet_set_timing(tsnet_ctx ctx, int on);
+int tsnet_stage_count(void);
+const char* tsnet_stage_name(int stage);
+int tsnet_stage_times(tsnet_ctx ctx, double* ms_host, int64_t* calls_host);
+
+/* Message of the calling thread's most recent failure ("" if none). */
+const char* tsnet_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSNET_H */

@@ -1,0 +1,273 @@
+"""Torch-facing wrappers over the C ABI (device memory and streams come from torch).
+
+Nothing here computes: each method checks tensor shapes/dtypes/devices and
+calls the matching ``tsnet_*`` entry point of libtsnet.so on the current (or
+given) torch stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, fields
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, lib
+
+
+@dataclass
+class Params:
+    lambda_kl: float = 1.0
+    lambda_c: float = 1.2
+    lambda_r: float = 0.01
+    eps_r: float = 0.05
+    interval_width: float = 0.25
+    min_intervals: int = 50
+    max_intervals: int = 256
+    nodes_per_interval: int = 3
+
+    def to_c(self) -> _lib.tsnet_params:
+        p = _lib.tsnet_params()
+        for f in fields(self):
+            setattr(p, f.name, getattr(self, f.name))
+        return p
+
+
+@dataclass
+class StepParams:
+    eta: float = 0.0
+    momentum_early: float = 0.5
+    momentum_late: float = 0.8
+    min_gain: float = 0.01
+    gain_up: float = 0.2
+    gain_down: float = 0.8
+    momentum_switch_iter: int = 250
+
+    def to_c(self) -> _lib.tsnet_step_params:
+        p = _lib.tsnet_step_params()
+        for f in fields(self):
+            setattr(p, f.name, getattr(self, f.name))
+        return p
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dev(t: torch.Tensor, dtype, shape=None, name="tensor") -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t.data_ptr()
+
+
+def _opt(t, dtype, shape, name):
+    return None if t is None else _dev(t, dtype, shape, name)
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        self.device = device
+        h = ctypes.c_void_p()
+        check(lib.tsnet_ctx_create(ctypes.byref(h), device))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            check(lib.tsnet_ctx_destroy(self.handle))
+            self.handle = None
+
+    def status(self) -> int:
+        v = ctypes.c_uint32()
+        check(lib.tsnet_status(self.handle, ctypes.byref(v)))
+        return v.value
+
+    def set_timing(self, on: bool):
+        check(lib.tsnet_set_timing(self.handle, int(bool(on))))
+
+    def stage_times(self):
+        k = lib.tsnet_stage_count()
+        ms = (ctypes.c_double * k)()
+        calls = (ctypes.c_int64 * k)()
+        check(lib.tsnet_stage_times(self.handle, ms, calls))
+        return {lib.tsnet_stage_name(i).decode(): (ms[i], calls[i]) for i in range(k)}
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _offsets(graph_offsets, n):
+    if graph_offsets is None:
+        return None, 1
+    go = np.ascontiguousarray(np.asarray(graph_offsets, dtype=np.int32))
+    return go, go.shape[0] - 1
+
+
+class Problem:
+    """One graph batch with its affinities P and evaluation workspace."""
+
+    def __init__(self, ctx: Context, handle: ctypes.c_void_p):
+        self.ctx = ctx
+        self.handle = handle
+        n, nnz, G, k = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib.tsnet_P_info(handle, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(G),
+                               ctypes.byref(k)))
+        self.n, self.nnz, self.num_graphs, self.k = n.value, nnz.value, G.value, k.value
+
+    @classmethod
+    def build(cls, ctx: Context, indptr, indices, perplexity: float, k: int = 0, seed: int = 0,
+              tie_mode: str = "hash", graph_offsets=None, stream=None) -> "Problem":
+        dev = torch.device("cuda", ctx.device)
+        ip = torch.as_tensor(np.asarray(indptr, dtype=np.int64)).to(dev) \
+            if not isinstance(indptr, torch.Tensor) else indptr
+        ix = torch.as_tensor(np.asarray(indices, dtype=np.int32)).to(dev) \
+            if not isinstance(indices, torch.Tensor) else indices
+        n = ip.shape[0] - 1
+        go, G = _offsets(graph_offsets, n)
+        mode = {"hash": _lib.TSNET_TIE_HASH, "id": _lib.TSNET_TIE_ID}[tie_mode]
+        h = ctypes.c_void_p()
+        check(lib.tsnet_build_P(ctx.handle, _dev(ip, torch.int64, None, "indptr"),
+                                ix.data_ptr() if ix.numel() else None, n, ix.numel(),
+                                None if go is None else go.ctypes.data, G, float(perplexity), k,
+                                seed & ((1 << 64) - 1), mode, ctypes.byref(h), _stream(stream)))
+        return cls(ctx, h)
+
+    @classmethod
+    def from_host(cls, ctx: Context, rowptr, col, val, graph_offsets=None) -> "Problem":
+        rp = np.ascontiguousarray(np.asarray(rowptr, dtype=np.int64))
+        cl = np.ascontiguousarray(np.asarray(col, dtype=np.int32))
+        vl = np.ascontiguousarray(np.asarray(val, dtype=np.float32))
+        n = rp.shape[0] - 1
+        go, G = _offsets(graph_offsets, n)
+        h = ctypes.c_void_p()
+        check(lib.tsnet_P_from_host(ctx.handle, n, rp.ctypes.data, cl.ctypes.data if cl.size else None,
+                                    vl.ctypes.data if vl.size else None,
+                                    None if go is None else go.ctypes.data, G, ctypes.byref(h)))
+        return cls(ctx, h)
+
+    def free(self):
+        if self.handle:
+            check(lib.tsnet_P_free(self.handle))
+            self.handle = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ exports
+    def export(self, conditional: bool = False) -> dict:
+        rowptr = np.zeros(self.n + 1, np.int64)
+        col = np.zeros(max(self.nnz, 1), np.int32)
+        val = np.zeros(max(self.nnz, 1), np.float32)
+        out = {"rowptr": rowptr, "col": col[: self.nnz], "val": val[: self.nnz]}
+        args = [rowptr.ctypes.data, col.ctypes.data, val.ctypes.data, None, None, None, None, None]
+        if conditional:
+            nk = max(self.n * self.k, 1)
+            beta = np.zeros(self.n, np.float64)
+            status = np.zeros(self.n, np.int8)
+            clen = np.zeros(self.n, np.int32)
+            cnbr = np.zeros(nk, np.int32)
+            cdist = np.zeros(nk, np.uint16)
+            args[3:] = [beta.ctypes.data, status.ctypes.data, clen.ctypes.data, cnbr.ctypes.data,
+                        cdist.ctypes.data]
+            out.update(beta=beta, status=status, cond_len=clen,
+                       cond_nbr=cnbr[: self.n * self.k].reshape(self.n, self.k),
+                       cond_dist=cdist[: self.n * self.k].reshape(self.n, self.k))
+        check(lib.tsnet_P_export(self.handle, *args))
+        return out
+
+    def grid_info(self) -> dict:
+        G = self.num_graphs
+        ni = np.zeros(G, np.int32)
+        h = np.zeros(G, np.float32)
+        x0 = np.zeros(G, np.float32)
+        y0 = np.zeros(G, np.float32)
+        check(lib.tsnet_grid_info(self.handle, ni.ctypes.data, h.ctypes.data, x0.ctypes.data,
+                                  y0.ctypes.data))
+        return {"n_intervals": ni, "box_side": h, "x0": x0, "y0": y0}
+
+    # ------------------------------------------------------------ evaluation
+    def grad(self, X: torch.Tensor, params: Params = Params(), G=None, Z=None, stream=None):
+        n = self.n
+        xp = _dev(X, torch.float32, (n, 2), "X")
+        if G is None:
+            G = torch.empty((n, 2), dtype=torch.float32, device=X.device)
+        if Z is None:
+            Z = torch.empty(self.num_graphs, dtype=torch.float64, device=X.device)
+        prm = params.to_c()
+        check(lib.tsnet_grad(self.ctx.handle, self.handle, xp, ctypes.byref(prm),
+                             _dev(G, torch.float32, (n, 2), "G"),
+                             _dev(Z, torch.float64, (self.num_graphs,), "Z"), _stream(stream)))
+        return G, Z
+
+    def grad_terms(self, X: torch.Tensor, params: Params = Params(), stream=None) -> dict:
+        n = self.n
+        dev = X.device
+        out = {
+            "G": torch.empty((n, 2), dtype=torch.float32, device=dev),
+            "Z": torch.empty(self.num_graphs, dtype=torch.float64, device=dev),
+            "F_attr": torch.empty((n, 2), dtype=torch.float32, device=dev),
+            "F_rep": torch.empty((n, 2), dtype=torch.float32, device=dev),
+            "F_ent": torch.empty((n, 2), dtype=torch.float32, device=dev),
+            "Z_i": torch.empty(n, dtype=torch.float32, device=dev),
+        }
+        prm = params.to_c()
+        check(lib.tsnet_grad_terms(self.ctx.handle, self.handle,
+                                   _dev(X, torch.float32, (n, 2), "X"), ctypes.byref(prm),
+                                   out["G"].data_ptr(), out["Z"].data_ptr(),
+                                   out["F_attr"].data_ptr(), out["F_rep"].data_ptr(),
+                                   out["F_ent"].data_ptr(), out["Z_i"].data_ptr(), _stream(stream)))
+        return out
+
+    def step(self, X, update, gains, G, it: int, sp: StepParams = StepParams(), stream=None):
+        n = self.n
+        spc = sp.to_c()
+        check(lib.tsnet_step(self.ctx.handle, self.handle, _dev(X, torch.float32, (n, 2), "X"),
+                             _dev(update, torch.float32, (n, 2), "update"),
+                             _dev(gains, torch.float32, (n, 2), "gains"),
+                             _dev(G, torch.float32, (n, 2), "G"), ctypes.byref(spc), int(it),
+                             _stream(stream)))
+
+    def cost(self, X: torch.Tensor, params: Params = Params(), out=None, stream=None):
+        if out is None:
+            out = torch.empty((self.num_graphs, 4), dtype=torch.float64, device=X.device)
+        prm = params.to_c()
+        check(lib.tsnet_cost(self.ctx.handle, self.handle, _dev(X, torch.float32, (self.n, 2), "X"),
+                             ctypes.byref(prm), _dev(out, torch.float64, (self.num_graphs, 4), "cost"),
+                             _stream(stream)))
+        return out
+
+    def grad_direct_f64(self, X: torch.Tensor, params: Params = Params(), rows=None,
+                        with_terms: bool = False, stream=None):
+        n = self.n
+        xp = _dev(X, torch.float64, (n, 2), "X")
+        dev = X.device
+        if rows is not None:
+            rows = torch.as_tensor(rows, dtype=torch.int32, device=dev).contiguous()
+            nr = rows.numel()
+        else:
+            nr = n
+        G = torch.empty((nr, 2), dtype=torch.float64, device=dev)
+        Z = torch.empty(self.num_graphs, dtype=torch.float64, device=dev)
+        T = torch.empty((nr, 7), dtype=torch.float64, device=dev) if with_terms else None
+        prm = params.to_c()
+        check(lib.tsnet_grad_direct_f64(self.ctx.handle, self.handle, xp, ctypes.byref(prm),
+                                        G.data_ptr(), Z.data_ptr(),
+                                        None if rows is None else rows.data_ptr(), nr,
+                                        None if T is None else T.data_ptr(), _stream(stream)))
+        return (G, Z, T) if with_terms else (G, Z)

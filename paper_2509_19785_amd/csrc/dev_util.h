@@ -1,0 +1,147 @@
+// Device helpers: wave64 reductions and scans, compensated sums, grid location.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "tsnet_internal.h"
+
+namespace tsnet {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+__device__ __forceinline__ int wave_id() { return threadIdx.x / kWave; }
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+// Inclusive prefix sum across the wave.
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    T t = __shfl_up(v, o, kWave);
+    if (l >= o) v += t;
+  }
+  return v;
+}
+
+// Exclusive block scan of one int per thread (blockDim.x <= 1024, multiple of 64).
+// `sh` needs blockDim.x / 64 ints. Returns the exclusive prefix; *total gets the sum.
+__device__ __forceinline__ int block_excl_scan(int v, int* sh, int* total) {
+  const int nw = blockDim.x / kWave;
+  int inc = wave_incl_scan(v);
+  if (lane_id() == kWave - 1) sh[wave_id()] = inc;
+  __syncthreads();
+  if (threadIdx.x < kWave) {
+    int t = threadIdx.x < nw ? sh[threadIdx.x] : 0;
+    int ti = wave_incl_scan(t);
+    if (threadIdx.x < nw) sh[threadIdx.x] = ti - t;
+    if (threadIdx.x == nw - 1) sh[nw] = ti;
+  }
+  __syncthreads();
+  int res = inc - v + sh[wave_id()];
+  if (total) *total = sh[nw];
+  __syncthreads();
+  return res;
+}
+
+// Error-free transformation a + b = s + e (Knuth's TwoSum).
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// Compensated FP32 accumulator: value = hi + lo.
+struct CompSum {
+  float hi = 0.f, lo = 0.f;
+  __device__ __forceinline__ void add(float v) {
+    float s, e;
+    two_sum(hi, v, s, e);
+    hi = s;
+    lo += e;
+  }
+  __device__ __forceinline__ void merge(const CompSum& o) {
+    float s, e;
+    two_sum(hi, o.hi, s, e);
+    hi = s;
+    lo += e + o.lo;
+  }
+  __device__ __forceinline__ double value() const { return (double)hi + (double)lo; }
+};
+
+__device__ __forceinline__ CompSum wave_comp_sum(CompSum c) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    CompSum t;
+    t.hi = __shfl_xor(c.hi, o, kWave);
+    t.lo = __shfl_xor(c.lo, o, kWave);
+    c.merge(t);
+  }
+  return c;
+}
+
+// Lagrange basis on the three nodes (t + 1/2) / 3 of a box, at local coordinate s.
+// Denominators of the three cardinal polynomials: 2/9, -1/9, 2/9.
+__device__ __forceinline__ void lagrange3(float s, float w[3]) {
+  const float a = s - (1.0f / 6.0f), b = s - 0.5f, c = s - (5.0f / 6.0f);
+  w[0] = 4.5f * b * c;
+  w[1] = -9.0f * a * c;
+  w[2] = 4.5f * a * b;
+}
+
+// Box of a point and its local coordinates in [0, 1]. NaN coordinates land in
+// box 0 (the clamp absorbs them) so no index leaves the grid.
+__device__ __forceinline__ void locate(const GridDesc& d, float x, float y, int& bx, int& by,
+                                       float& s, float& t) {
+  const float fx = (x - d.x0) / d.h;
+  const float fy = (y - d.y0) / d.h;
+  const float top = (float)(d.n_int - 1);
+  const float cx = fminf(fmaxf(floorf(fx), 0.0f), top);
+  const float cy = fminf(fmaxf(floorf(fy), 0.0f), top);
+  bx = (int)cx;
+  by = (int)cy;
+  s = fx - cx;
+  t = fy - cy;
+}
+
+// Loads that bypass the non-coherent per-CU cache: used by the last block of a
+// grid to read partial results that other blocks wrote in the same launch.
+template <typename T>
+__device__ __forceinline__ T ld_coherent(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ float4 ld_coherent4(const float4* p) {
+  const float* f = reinterpret_cast<const float*>(p);
+  return make_float4(ld_coherent(f), ld_coherent(f + 1), ld_coherent(f + 2), ld_coherent(f + 3));
+}
+
+__device__ __forceinline__ int graph_of(const int* goff, int G, int v) {
+  int lo = 0, hi = G;  // goff[lo] <= v < goff[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (goff[mid] <= v) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+}  // namespace tsnet

@@ -1,0 +1,667 @@
+// Per-evaluation kernels of the L-tsNET gradient: bounding box and grid plan,
+// counting sort of points by box, fixed-point spread to the interpolation
+// nodes, gather back to the points, Z reduction, the sparse attractive pass
+// fused with the gradient assembly, and the vertex move.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cmath>
+
+#include "dev_util.h"
+#include "tsnet_internal.h"
+
+namespace tsnet {
+
+// ---------------------------------------------------------------------------
+// Bounding box per chunk, then (last block to finish) the grid of every graph.
+// Grid rule (Sec. 2.3 leaves I and P open): span = larger side of the
+// bounding box, n_int = ceil(span / h_target) clamped to [min, max] and
+// rounded up to a power of two, box side h = span / n_int, grid centred on the
+// bounding box. The decisions are taken in FP64.
+__global__ __launch_bounds__(256) void k_bbox_plan(
+    const float2* __restrict__ X, const int* __restrict__ chunk_start,
+    const int* __restrict__ chunk_end, int num_chunks, float4* part, unsigned* counter,
+    const GraphInfo* __restrict__ gi, int G, PlanParams pp, GridDesc* desc, int* btotal,
+    unsigned* status) {
+  __shared__ float red[4][4];
+  __shared__ int bad_s;
+  __shared__ int last_s;
+  const int c = blockIdx.x;
+  if (threadIdx.x == 0) bad_s = 0;
+  __syncthreads();
+  float xmn = FLT_MAX, xmx = -FLT_MAX, ymn = FLT_MAX, ymx = -FLT_MAX;
+  int bad = 0;
+  for (int i = chunk_start[c] + threadIdx.x; i < chunk_end[c]; i += blockDim.x) {
+    const float2 p = X[i];
+    if (!(isfinite(p.x) && isfinite(p.y))) {
+      bad = 1;
+      continue;
+    }
+    xmn = fminf(xmn, p.x);
+    xmx = fmaxf(xmx, p.x);
+    ymn = fminf(ymn, p.y);
+    ymx = fmaxf(ymx, p.y);
+  }
+  xmn = wave_min(xmn);
+  xmx = wave_max(xmx);
+  ymn = wave_min(ymn);
+  ymx = wave_max(ymx);
+  if (bad) atomicOr(&bad_s, 1);
+  if (lane_id() == 0) {
+    red[wave_id()][0] = xmn;
+    red[wave_id()][1] = xmx;
+    red[wave_id()][2] = ymn;
+    red[wave_id()][3] = ymx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x / kWave); ++w) {
+      xmn = fminf(xmn, red[w][0]);
+      xmx = fmaxf(xmx, red[w][1]);
+      ymn = fminf(ymn, red[w][2]);
+      ymx = fmaxf(ymx, red[w][3]);
+    }
+    part[c] = make_float4(bad_s ? NAN : xmn, xmx, ymn, ymx);
+    __threadfence();
+    const unsigned prev = atomicAdd(counter, 1u);
+    last_s = (prev == (unsigned)(num_chunks - 1));
+  }
+  __syncthreads();
+  if (!last_s) return;
+  __threadfence();
+  for (int g = threadIdx.x; g < G; g += blockDim.x) {
+    double a = DBL_MAX, b = -DBL_MAX, e = DBL_MAX, f = -DBL_MAX;
+    int nonfinite = 0;
+    for (int k = gi[g].chunk_begin; k < gi[g].chunk_end; ++k) {
+      const float4 q = ld_coherent4(&part[k]);
+      if (isnan(q.x)) nonfinite = 1;
+      if (q.y >= q.x) {  // chunk had at least one finite point
+        a = fmin(a, (double)q.x);
+        b = fmax(b, (double)q.y);
+        e = fmin(e, (double)q.z);
+        f = fmax(f, (double)q.w);
+      }
+    }
+    if (!(b >= a)) {  // no finite point at all
+      a = b = e = f = 0.0;
+    }
+    int flags = nonfinite ? TSNET_STATUS_NONFINITE : 0;
+    double span = fmax(b - a, f - e);
+    if (!(span >= kSpanFloor)) span = kSpanFloor;
+    const double q = span / pp.h_target;
+    int nint;
+    if (!(q <= (double)pp.max_int)) {
+      nint = pp.max_int;
+      flags |= TSNET_STATUS_GRID_CAPPED;
+    } else {
+      nint = (int)ceil(q);
+      if (nint < pp.min_int) nint = pp.min_int;
+    }
+    int p2 = 1;
+    while (p2 < nint) p2 <<= 1;
+    nint = p2 < pp.max_int ? p2 : pp.max_int;
+    const double h = span / nint;
+    const double cx = 0.5 * (a + b), cy = 0.5 * (e + f);
+    GridDesc d;
+    d.x0 = (float)(cx - 0.5 * nint * h);
+    d.y0 = (float)(cy - 0.5 * nint * h);
+    d.h = (float)h;
+    d.inv_h = (float)(1.0 / h);
+    d.cx = (float)cx;
+    d.cy = (float)cy;
+    d.half = (float)(0.5 * nint * h);
+    d.spacing = (float)(h / kNodes);
+    d.n_int = nint;
+    d.ng = kNodes * nint;
+    d.M = 2 * kNodes * nint;
+    d.box_base = 0;
+    d.flags = flags;
+    d.pad0 = d.pad1 = d.pad2 = 0;
+    desc[g] = d;
+    if (flags) atomicOr(status, (unsigned)flags);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int g = 0; g < G; ++g) {
+      desc[g].box_base = acc;
+      acc += desc[g].n_int * desc[g].n_int;
+    }
+    *btotal = acc;
+    *counter = 0u;
+  }
+}
+
+hipError_t launch_bbox_plan(Problem& P, const float2* X, const PlanParams& pp, hipStream_t s) {
+  hipLaunchKernelGGL(k_bbox_plan, dim3(P.num_chunks), dim3(256), 0, s, X, P.chunk_start,
+                     P.chunk_end, P.num_chunks, P.bbox_part, P.counters + 0, P.ginfo, P.G, pp,
+                     P.desc, P.btotal, P.ctx->status);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Counting sort of points by global box id: keys + histogram, scan, scatter.
+__global__ __launch_bounds__(256) void k_keys_hist(const float2* __restrict__ X,
+                                                   const int* __restrict__ chunk_graph,
+                                                   const int* __restrict__ chunk_start,
+                                                   const int* __restrict__ chunk_end,
+                                                   const GridDesc* __restrict__ desc, int* keys,
+                                                   int* counts) {
+  const int c = blockIdx.x;
+  const GridDesc d = desc[chunk_graph[c]];
+  for (int i = chunk_start[c] + threadIdx.x; i < chunk_end[c]; i += blockDim.x) {
+    const float2 p = X[i];
+    int bx, by;
+    float s, t;
+    locate(d, p.x, p.y, bx, by, s, t);
+    const int key = d.box_base + by * d.n_int + bx;
+    keys[i] = key;
+    atomicAdd(&counts[key], 1);
+  }
+}
+
+// Tile sums of counts[0, btotal).
+__global__ __launch_bounds__(256) void k_scan_tiles(const int* __restrict__ counts,
+                                                    const int* __restrict__ btotal,
+                                                    int* tile_sum) {
+  const int B = *btotal;
+  const int base = blockIdx.x * kScanTile;
+  if (base >= B) return;
+  int v = 0;
+  for (int k = threadIdx.x; k < kScanTile; k += blockDim.x) {
+    const int idx = base + k;
+    if (idx < B) v += counts[idx];
+  }
+  v = wave_sum(v);
+  __shared__ int sh[4];
+  if (lane_id() == 0) sh[wave_id()] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// Exclusive scan of the tile sums (one block of 1024 threads).
+__global__ __launch_bounds__(1024) void k_scan_top(int* tile_sum, const int* __restrict__ btotal) {
+  __shared__ int sh[17];
+  const int T = (*btotal + kScanTile - 1) / kScanTile;
+  int carry = 0;
+  for (int base = 0; base < T; base += 1024) {
+    const int idx = base + threadIdx.x;
+    const int v = idx < T ? tile_sum[idx] : 0;
+    int tot;
+    const int ex = block_excl_scan(v, sh, &tot);
+    if (idx < T) tile_sum[idx] = carry + ex;
+    carry += tot;
+  }
+}
+
+// Box offsets: box_off[k] = first sorted slot of box k; cursor = box_off;
+// counts are cleared for the next evaluation.
+__global__ __launch_bounds__(256) void k_scan_apply(int* counts, const int* __restrict__ btotal,
+                                                    const int* __restrict__ tile_sum,
+                                                    int* box_off, int* cursor) {
+  __shared__ int sh[5];
+  const int B = *btotal;
+  const int base = blockIdx.x * kScanTile;
+  if (base >= B) return;
+  constexpr int per = kScanTile / 256;
+  const int first = base + threadIdx.x * per;
+  int loc[per];
+  int sum = 0;
+#pragma unroll
+  for (int k = 0; k < per; ++k) {
+    const int idx = first + k;
+    loc[k] = idx < B ? counts[idx] : 0;
+    sum += loc[k];
+  }
+  int tot;
+  int run = block_excl_scan(sum, sh, &tot) + tile_sum[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < per; ++k) {
+    const int idx = first + k;
+    if (idx < B) {
+      box_off[idx] = run;
+      cursor[idx] = run;
+      counts[idx] = 0;
+    }
+    run += loc[k];
+  }
+  if (base + kScanTile >= B && threadIdx.x == 255) box_off[B] = run;
+}
+
+__global__ __launch_bounds__(256) void k_scatter(const int* __restrict__ keys, int n, int* cursor,
+                                                 int* perm) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int pos = atomicAdd(&cursor[keys[i]], 1);
+    perm[pos] = i;
+  }
+}
+
+hipError_t launch_bin(Problem& P, const float2* X, hipStream_t s) {
+  const int tiles = (P.G * P.cap * P.cap + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(k_keys_hist, dim3(P.num_chunks), dim3(256), 0, s, X, P.chunk_graph,
+                     P.chunk_start, P.chunk_end, P.desc, P.keys, P.counts);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(256), 0, s, P.counts, P.btotal, P.tile_sum);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, P.tile_sum, P.btotal);
+  hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(256), 0, s, P.counts, P.btotal, P.tile_sum,
+                     P.box_off, P.cursor);
+  const int blocks = (P.n + 255) / 256 < 4096 ? (P.n + 255) / 256 : 4096;
+  hipLaunchKernelGGL(k_scatter, dim3(blocks), dim3(256), 0, s, P.keys, P.n, P.cursor, P.perm);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Spread (Sec. 2.3): node charge w[c][a] = sum over the points of the node's box
+// of L_tx(s) L_ty(t) q_c with q = (1, (x - cx) / half, (y - cy) / half). One
+// wave per box; each contribution is rounded to a 2^-28 grid and summed in
+// 64-bit integers, so the result does not depend on the order of the points.
+__global__ __launch_bounds__(256) void k_spread(const float2* __restrict__ X,
+                                                const int* __restrict__ perm,
+                                                const int* __restrict__ box_off,
+                                                const GridDesc* __restrict__ desc, float* charges,
+                                                size_t stride) {
+  const int g = blockIdx.y;
+  const GridDesc d = desc[g];
+  const int nb = d.n_int * d.n_int;
+  const int ng = d.ng;
+  float* out = charges + (size_t)g * stride;
+  const int lane = lane_id();
+  const int nwaves = blockDim.x / kWave;
+  for (int b = blockIdx.x * nwaves + wave_id(); b < nb; b += gridDim.x * nwaves) {
+    const int by = b / d.n_int, bx = b - by * d.n_int;
+    const int start = box_off[d.box_base + b], end = box_off[d.box_base + b + 1];
+    long long acc[27];
+#pragma unroll
+    for (int k = 0; k < 27; ++k) acc[k] = 0;
+    const float inv_half = 1.0f / d.half;
+    for (int p = start + lane; p < end; p += kWave) {
+      const float2 x = X[perm[p]];
+      const float s = (x.x - d.x0) / d.h - (float)bx;
+      const float t = (x.y - d.y0) / d.h - (float)by;
+      float lx[3], ly[3];
+      lagrange3(s, lx);
+      lagrange3(t, ly);
+      const float q1 = (x.x - d.cx) * inv_half, q2 = (x.y - d.cy) * inv_half;
+#pragma unroll
+      for (int ty = 0; ty < 3; ++ty) {
+#pragma unroll
+        for (int tx = 0; tx < 3; ++tx) {
+          const float w = ly[ty] * lx[tx];
+          const float v0 = fminf(fmaxf(w, -4.0f), 4.0f);
+          const float v1 = fminf(fmaxf(w * q1, -4.0f), 4.0f);
+          const float v2 = fminf(fmaxf(w * q2, -4.0f), 4.0f);
+          const int k = (ty * 3 + tx) * 3;
+          acc[k + 0] += (long long)__float2int_rn(v0 * kFixScale);
+          acc[k + 1] += (long long)__float2int_rn(v1 * kFixScale);
+          acc[k + 2] += (long long)__float2int_rn(v2 * kFixScale);
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 27; ++k) acc[k] = wave_sum(acc[k]);
+    if (lane == 0) {
+      const double inv = 1.0 / (double)kFixScale;
+#pragma unroll
+      for (int ty = 0; ty < 3; ++ty) {
+#pragma unroll
+        for (int tx = 0; tx < 3; ++tx) {
+          const size_t node = (size_t)(3 * by + ty) * ng + (3 * bx + tx);
+          const int k = (ty * 3 + tx) * 3;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) out[(size_t)c * ng * ng + node] = (float)((double)acc[k + c] * inv);
+        }
+      }
+    }
+  }
+}
+
+hipError_t launch_spread(Problem& P, const float2* X, hipStream_t s) {
+  const int nb = P.cap * P.cap;
+  int bx = (nb + 3) / 4;
+  const int max_bx = P.G > 1 ? 64 : 1024;
+  if (bx > max_bx) bx = max_bx;
+  hipLaunchKernelGGL(k_spread, dim3(bx, P.G), dim3(256), 0, s, X, P.perm, P.box_off, P.desc,
+                     P.charges, P.stride_charges);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Gather (Sec. 2.3 / Sec. 3.3): interpolate the 8 node potentials to every
+// point (in sorted order, so a wave reads few nodes), then form
+//   F_rep = (x - c) phi[K2,1] - phi[K2,x],  F_ent = (x - c) phi[Ke,1] - phi[Ke,x],
+//   Z_i = phi[K1,1] - 1 (the self term K1(0) = 1).
+__global__ __launch_bounds__(256) void k_gather(
+    const float2* __restrict__ X, const int* __restrict__ perm,
+    const int* __restrict__ chunk_graph, const int* __restrict__ chunk_start,
+    const int* __restrict__ chunk_end, const GridDesc* __restrict__ desc,
+    const GraphInfo* __restrict__ gi, const float* __restrict__ pot, size_t stride_pot,
+    float2* frep, float2* fent, float* zi, float* lnv) {
+  const int c = blockIdx.x;
+  const int g = chunk_graph[c];
+  const GridDesc d = desc[g];
+  const float* pg = pot + (size_t)g * stride_pot;
+  const bool single = gi[g].n == 1;
+  for (int p = chunk_start[c] + threadIdx.x; p < chunk_end[c]; p += blockDim.x) {
+    const int i = perm[p];
+    const float2 x = X[i];
+    int bx, by;
+    float s, t;
+    locate(d, x.x, x.y, bx, by, s, t);
+    float lx[3], ly[3];
+    lagrange3(s, lx);
+    lagrange3(t, ly);
+    float phi[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) phi[k] = 0.f;
+#pragma unroll
+    for (int ty = 0; ty < 3; ++ty) {
+      const float* row = pg + ((size_t)(3 * by + ty) * d.ng + 3 * bx) * kPotCh;
+#pragma unroll
+      for (int tx = 0; tx < 3; ++tx) {
+        const float w = ly[ty] * lx[tx];
+        const float4 a = *reinterpret_cast<const float4*>(row + tx * kPotCh);
+        const float4 b = *reinterpret_cast<const float4*>(row + tx * kPotCh + 4);
+        phi[0] += w * a.x;
+        phi[1] += w * a.y;
+        phi[2] += w * a.z;
+        phi[3] += w * a.w;
+        phi[4] += w * b.x;
+        phi[5] += w * b.y;
+        phi[6] += w * b.z;
+        phi[7] += w * b.w;
+      }
+    }
+    const float xt = x.x - d.cx, yt = x.y - d.cy;
+    float2 r = make_float2(xt * phi[CH_K2_1] - d.half * phi[CH_K2_X],
+                           yt * phi[CH_K2_1] - d.half * phi[CH_K2_Y]);
+    float2 e = make_float2(xt * phi[CH_KE_1] - d.half * phi[CH_KE_X],
+                           yt * phi[CH_KE_1] - d.half * phi[CH_KE_Y]);
+    float z = phi[CH_K1_1] - 1.0f;
+    if (single) {
+      r = make_float2(0.f, 0.f);
+      e = make_float2(0.f, 0.f);
+      z = 0.f;
+    }
+    frep[i] = r;
+    fent[i] = e;
+    zi[i] = z;
+    if (lnv) lnv[i] = single ? 0.f : phi[CH_KLN_1];
+  }
+}
+
+hipError_t launch_gather(Problem& P, const float2* X, int with_ln, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather, dim3(P.num_chunks), dim3(256), 0, s, X, P.perm, P.chunk_graph,
+                     P.chunk_start, P.chunk_end, P.desc, P.ginfo, P.pot, P.stride_pot, P.frep,
+                     P.fent, P.zi, with_ln ? P.lnv : nullptr);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Z per graph: compensated FP32 sums per chunk (vertex order), FP64 across chunks.
+__global__ __launch_bounds__(256) void k_zreduce(const float* __restrict__ zi,
+                                                 const int* __restrict__ chunk_start,
+                                                 const int* __restrict__ chunk_end, int num_chunks,
+                                                 double* zpart, unsigned* counter,
+                                                 const GraphInfo* __restrict__ gi, int G,
+                                                 double* zg, double* Z_out) {
+  __shared__ float sh_hi[4], sh_lo[4];
+  __shared__ int last_s;
+  const int c = blockIdx.x;
+  CompSum acc;
+  for (int i = chunk_start[c] + threadIdx.x; i < chunk_end[c]; i += blockDim.x) acc.add(zi[i]);
+  acc = wave_comp_sum(acc);
+  if (lane_id() == 0) {
+    sh_hi[wave_id()] = acc.hi;
+    sh_lo[wave_id()] = acc.lo;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double v = 0.0;
+    for (int w = 0; w < 4; ++w) v += (double)sh_hi[w] + (double)sh_lo[w];
+    zpart[c] = v;
+    __threadfence();
+    last_s = (atomicAdd(counter, 1u) == (unsigned)(num_chunks - 1));
+  }
+  __syncthreads();
+  if (!last_s) return;
+  __threadfence();
+  for (int g = threadIdx.x; g < G; g += blockDim.x) {
+    double z = 0.0;
+    for (int k = gi[g].chunk_begin; k < gi[g].chunk_end; ++k) z += ld_coherent(&zpart[k]);
+    zg[g] = z;
+    if (Z_out) Z_out[g] = z;
+  }
+  if (threadIdx.x == 0) *counter = 0u;
+}
+
+hipError_t launch_zreduce(Problem& P, double* Z_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_zreduce, dim3(P.num_chunks), dim3(256), 0, s, P.zi, P.chunk_start,
+                     P.chunk_end, P.num_chunks, P.zpart, P.counters + 1, P.ginfo, P.G, P.zg, Z_out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Attractive KL term over the sparse P (Eq. 6, first sum) fused with the
+// assembly of the gradient:
+//   G_i = 4 l_kl (F_attr,i - F_rep,i / Z) + (l_c / n) X_i - (l_r / n^2) F_ent,i.
+// One wave per row, lanes over the row's nonzeros.
+struct AttrParams {
+  float lkl4, lc, lr;
+};
+
+__global__ __launch_bounds__(256) void k_attract(
+    const float2* __restrict__ X, const int64_t* __restrict__ rowptr, const int* __restrict__ col,
+    const float* __restrict__ val, int n, const int* __restrict__ goff, int G,
+    const GraphInfo* __restrict__ gi, const double* __restrict__ zg,
+    const float2* __restrict__ frep, const float2* __restrict__ fent, AttrParams ap, float2* Gout,
+    float2* Fattr) {
+  const int lane = lane_id();
+  const int nwaves = blockDim.x / kWave;
+  for (int i = blockIdx.x * nwaves + wave_id(); i < n; i += gridDim.x * nwaves) {
+    const int64_t a = rowptr[i], b = rowptr[i + 1];
+    const float2 xi = X[i];
+    float fx = 0.f, fy = 0.f;
+    for (int64_t e = a + lane; e < b; e += kWave) {
+      const int j = col[e];
+      const float p = val[e];
+      const float2 xj = X[j];
+      const float dx = xi.x - xj.x, dy = xi.y - xj.y;
+      const float pw = p / (1.0f + dx * dx + dy * dy);
+      fx += pw * dx;
+      fy += pw * dy;
+    }
+    fx = wave_sum(fx);
+    fy = wave_sum(fy);
+    if (lane == 0) {
+      const int g = G == 1 ? 0 : graph_of(goff, G, i);
+      const double Z = zg[g];
+      const float inv_z = Z > 0.0 ? (float)(1.0 / Z) : 0.0f;
+      const float2 r = frep[i], e = fent[i];
+      const float cn = ap.lc * gi[g].inv_n, rn = ap.lr * gi[g].inv_n2;
+      float2 out;
+      out.x = ap.lkl4 * (fx - r.x * inv_z) + cn * xi.x - rn * e.x;
+      out.y = ap.lkl4 * (fy - r.y * inv_z) + cn * xi.y - rn * e.y;
+      Gout[i] = out;
+      if (Fattr) Fattr[i] = make_float2(fx, fy);
+    }
+  }
+}
+
+hipError_t launch_attract(Problem& P, const float2* X, const tsnet_params& prm, float2* G,
+                          float2* F_attr, hipStream_t s) {
+  AttrParams ap;
+  ap.lkl4 = (float)(4.0 * prm.lambda_kl);
+  ap.lc = (float)prm.lambda_c;
+  ap.lr = (float)prm.lambda_r;
+  int blocks = (P.n + 3) / 4;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_attract, dim3(blocks), dim3(256), 0, s, X, P.rowptr, P.col, P.val, P.n,
+                     P.goff_d, P.G, P.ginfo, P.zg, P.frep, P.fent, ap, G, F_attr);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Vertex move with momentum and gains (t-SNE's update; the paper only says
+// "move each vertex along the gradient").
+struct StepK {
+  float eta, mu, min_gain, up, down;
+};
+
+__global__ __launch_bounds__(256) void k_step(float2* X, float2* upd, float2* gains,
+                                              const float2* __restrict__ Gr, int n,
+                                              const int* __restrict__ goff, int G,
+                                              const GraphInfo* __restrict__ gi, StepK sk) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const float eta = sk.eta > 0.f ? sk.eta : gi[G == 1 ? 0 : graph_of(goff, G, i)].lr;
+    const float2 g = Gr[i];
+    float2 u = upd[i], k = gains[i], x = X[i];
+    k.x = ((g.x > 0.f) != (u.x > 0.f)) ? k.x + sk.up : k.x * sk.down;
+    k.y = ((g.y > 0.f) != (u.y > 0.f)) ? k.y + sk.up : k.y * sk.down;
+    k.x = fmaxf(k.x, sk.min_gain);
+    k.y = fmaxf(k.y, sk.min_gain);
+    u.x = sk.mu * u.x - eta * k.x * g.x;
+    u.y = sk.mu * u.y - eta * k.y * g.y;
+    x.x += u.x;
+    x.y += u.y;
+    gains[i] = k;
+    upd[i] = u;
+    X[i] = x;
+  }
+}
+
+hipError_t launch_step(Problem& P, float2* X, float2* upd, float2* gains, const float2* G,
+                       const tsnet_step_params& sp, int iter, hipStream_t s) {
+  StepK sk;
+  sk.eta = (float)sp.eta;
+  sk.mu = (float)(iter < sp.momentum_switch_iter ? sp.momentum_early : sp.momentum_late);
+  sk.min_gain = (float)sp.min_gain;
+  sk.up = (float)sp.gain_up;
+  sk.down = (float)sp.gain_down;
+  int blocks = (P.n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_step, dim3(blocks), dim3(256), 0, s, X, upd, gains, G, P.n, P.goff_d, P.G,
+                     P.ginfo, sk);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Cost of Eq. (1), entropy in the kernel form -l_r / (4 n^2) sum ln(eps + r^2):
+//  per row: sum_j p_ij (ln p_ij + ln(1 + r_ij^2)) over p > 0 and sum_j p_ij;
+//  per chunk: compensated sums of those, of ||X_i||^2, of the interpolated
+//  sum_j ln(eps + r_ij^2) (self term ln eps included) and of Z_i;
+//  per graph (last block): C_KL = l_kl (S_pl + S_p ln Z), C_CMP, C_ENT, total.
+__global__ __launch_bounds__(256) void k_cost_rows(const float2* __restrict__ X,
+                                                   const int64_t* __restrict__ rowptr,
+                                                   const int* __restrict__ col,
+                                                   const float* __restrict__ val, int n,
+                                                   float2* rowv) {
+  const int lane = lane_id();
+  const int nwaves = blockDim.x / kWave;
+  for (int i = blockIdx.x * nwaves + wave_id(); i < n; i += gridDim.x * nwaves) {
+    const float2 xi = X[i];
+    float s1 = 0.f, s2 = 0.f;
+    for (int64_t e = rowptr[i] + lane; e < rowptr[i + 1]; e += kWave) {
+      const float p = val[e];
+      if (p > 0.f) {
+        const float2 xj = X[col[e]];
+        const float dx = xi.x - xj.x, dy = xi.y - xj.y;
+        s1 += p * (logf(p) + log1pf(dx * dx + dy * dy));
+        s2 += p;
+      }
+    }
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    if (lane == 0) rowv[i] = make_float2(s1, s2);
+  }
+}
+
+struct CostK {
+  double lkl, lc, lr, log_eps;
+};
+
+__global__ __launch_bounds__(256) void k_cost_reduce(
+    const float2* __restrict__ X, const float2* __restrict__ rowv, const float* __restrict__ lnv,
+    const float* __restrict__ zi, const int* __restrict__ chunk_start,
+    const int* __restrict__ chunk_end, int num_chunks, double* part, unsigned* counter,
+    const GraphInfo* __restrict__ gi, int G, CostK ck, double* cost) {
+  __shared__ float sh[5][2][4];
+  __shared__ int last_s;
+  const int c = blockIdx.x;
+  CompSum acc[5];
+  for (int i = chunk_start[c] + threadIdx.x; i < chunk_end[c]; i += blockDim.x) {
+    const float2 rv = rowv[i];
+    const float2 x = X[i];
+    acc[0].add(rv.x);
+    acc[1].add(rv.y);
+    acc[2].add(x.x * x.x + x.y * x.y);
+    acc[3].add(lnv[i]);
+    acc[4].add(zi[i]);
+  }
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    acc[q] = wave_comp_sum(acc[q]);
+    if (lane_id() == 0) {
+      sh[q][0][wave_id()] = acc[q].hi;
+      sh[q][1][wave_id()] = acc[q].lo;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 0; q < 5; ++q) {
+      double v = 0.0;
+      for (int w = 0; w < 4; ++w) v += (double)sh[q][0][w] + (double)sh[q][1][w];
+      part[(size_t)c * 5 + q] = v;
+    }
+    __threadfence();
+    last_s = (atomicAdd(counter, 1u) == (unsigned)(num_chunks - 1));
+  }
+  __syncthreads();
+  if (!last_s) return;
+  __threadfence();
+  for (int g = threadIdx.x; g < G; g += blockDim.x) {
+    double s[5] = {0, 0, 0, 0, 0};
+    for (int k = gi[g].chunk_begin; k < gi[g].chunk_end; ++k)
+      for (int q = 0; q < 5; ++q) s[q] += ld_coherent(&part[(size_t)k * 5 + q]);
+    const double n = (double)gi[g].n;
+    const double Z = s[4];
+    const double kl = (n > 1 && Z > 0) ? ck.lkl * (s[0] + s[1] * log(Z)) : 0.0;
+    const double cm = ck.lc / (2.0 * n) * s[2];
+    const double en = n > 1 ? -ck.lr / (4.0 * n * n) * (s[3] - n * ck.log_eps) : 0.0;
+    cost[g * 4 + 0] = kl;
+    cost[g * 4 + 1] = cm;
+    cost[g * 4 + 2] = en;
+    cost[g * 4 + 3] = kl + cm + en;
+  }
+  if (threadIdx.x == 0) *counter = 0u;
+}
+
+hipError_t launch_cost(Problem& P, const float2* X, const tsnet_params& prm, double* cost,
+                       hipStream_t s) {
+  int blocks = (P.n + 3) / 4;
+  if (blocks > 8192) blocks = 8192;
+  // rows' KL sums go to frep's storage (unused by the cost path)
+  hipLaunchKernelGGL(k_cost_rows, dim3(blocks), dim3(256), 0, s, X, P.rowptr, P.col, P.val, P.n,
+                     P.frep);
+  CostK ck{prm.lambda_kl, prm.lambda_c, prm.lambda_r, log(prm.eps_r)};
+  hipLaunchKernelGGL(k_cost_reduce, dim3(P.num_chunks), dim3(256), 0, s, X, P.frep, P.lnv, P.zi,
+                     P.chunk_start, P.chunk_end, P.num_chunks, P.cost_part, P.counters + 2, P.ginfo,
+                     P.G, ck, cost);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_terms(Problem& P, float2* F_rep, float2* F_ent, float* Z_i, hipStream_t s) {
+  if (F_rep) {
+    hipError_t e = hipMemcpyAsync(F_rep, P.frep, sizeof(float2) * P.n, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+  }
+  if (F_ent) {
+    hipError_t e = hipMemcpyAsync(F_ent, P.fent, sizeof(float2) * P.n, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+  }
+  if (Z_i) {
+    hipError_t e = hipMemcpyAsync(Z_i, P.zi, sizeof(float) * P.n, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace tsnet

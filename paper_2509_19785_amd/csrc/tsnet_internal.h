@@ -1,0 +1,174 @@
+// Internal declarations shared by the host ABI code and the HIP kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "tsnet.h"
+
+namespace tsnet {
+
+// ---------------------------------------------------------------- constants
+constexpr int kNodes = 3;                 // interpolation nodes per box and axis
+constexpr int kMaxIntervals = 256;        // boxes per axis (power of two)
+constexpr int kMaxNg = kNodes * kMaxIntervals;
+constexpr int kMaxM = 2 * kMaxNg;         // FFT length per axis (3 * 2^b)
+constexpr int kPotCh = 8;                 // interleaved potential channels per node
+constexpr int kChunk = 2048;              // vertices per chunk of per-vertex kernels
+constexpr int kMaxK = 1024;               // neighbours per vertex in tsnet_build_P
+constexpr double kSpanFloor = 1e-4;       // smallest grid span (degenerate layouts)
+constexpr float kFixScale = 268435456.0f; // 2^28: fixed-point scale of spread contributions
+constexpr int kScanTile = 4096;           // entries per tile of the box-offset scan
+
+// Output channels of the convolution (charge index in comments):
+//  0 K2*1, 1 K2*x, 2 K2*y, 3 K1*1, 4 Ke*1, 5 Ke*x, 6 Ke*y, 7 Kln*1
+enum { CH_K2_1 = 0, CH_K2_X, CH_K2_Y, CH_K1_1, CH_KE_1, CH_KE_X, CH_KE_Y, CH_KLN_1 };
+
+// Per-graph interpolation grid, rewritten on the device every evaluation.
+struct GridDesc {
+  float x0, y0;      // lower-left corner of the box grid
+  float h, inv_h;    // box side and its inverse
+  float cx, cy;      // charge centre (bounding-box centre)
+  float half;        // half the grid side: charges x, y are stored divided by it
+  float spacing;     // node spacing h / 3
+  int n_int;         // boxes per axis
+  int ng;            // nodes per axis (3 n_int)
+  int M;             // FFT length per axis (2 ng)
+  int box_base;      // first global box id of this graph
+  int flags;         // TSNET_STATUS_* bits raised by this graph
+  int pad0, pad1, pad2;
+};
+
+// Static per-graph data (device copy made once per problem).
+struct GraphInfo {
+  int vstart;        // first vertex
+  int n;             // vertices
+  int chunk_begin;   // first chunk of per-vertex kernels
+  int chunk_end;
+  float inv_n;       // 1 / n
+  float inv_n2;      // 1 / n^2
+  float lr;          // default learning rate max(200, n / 12)
+  int pad;
+};
+
+struct PlanParams {
+  double h_target;
+  int min_int, max_int;
+};
+
+// Stage ids for optional per-stage timing.
+enum Stage {
+  ST_BBOX = 0, ST_BIN, ST_SPREAD, ST_FFT, ST_GATHER, ST_ZRED, ST_ATTR, ST_STEP, ST_COST,
+  ST_DIRECT, ST_BUILD, ST_COUNT
+};
+
+// ---------------------------------------------------------------- contexts
+struct Ctx {
+  int device = 0;
+  float2* twiddle = nullptr;          // e^{-2 pi i m / kMaxM}, m < kMaxM
+  unsigned* status = nullptr;         // device status word
+  int lds_per_block = 65536;
+  bool timing = false;
+  std::vector<hipEvent_t> ev_free;    // recycled events
+  struct Pending { int stage; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  double stage_ms[ST_COUNT] = {0};
+  int64_t stage_calls[ST_COUNT] = {0};
+};
+
+struct Problem {
+  Ctx* ctx = nullptr;
+  int n = 0;
+  int G = 0;
+  int k = 0;                          // 0 for problems made from host CSR
+  int64_t nnz = 0;
+  std::vector<int> goff;              // host graph offsets [G+1]
+  std::vector<GraphInfo> ginfo_h;
+  int num_chunks = 0;
+  // device: graph data
+  GraphInfo* ginfo = nullptr;
+  int* goff_d = nullptr;              // [G+1]
+  int* chunk_graph = nullptr;         // [num_chunks]
+  int* chunk_start = nullptr;
+  int* chunk_end = nullptr;
+  // device: P (CSR)
+  int64_t* rowptr = nullptr;
+  int* col = nullptr;
+  float* val = nullptr;
+  // device: conditional rows and calibration (absent for host-made P)
+  double* beta = nullptr;
+  int8_t* rstatus = nullptr;
+  int* cond_len = nullptr;
+  int* cond_nbr = nullptr;
+  uint16_t* cond_dist = nullptr;
+  // device: per-evaluation workspace
+  int cap = 0;                        // max_intervals the grid buffers are sized for
+  GridDesc* desc = nullptr;           // [G]
+  float4* bbox_part = nullptr;        // [num_chunks]
+  unsigned* counters = nullptr;       // [8] last-block counters (kept at zero)
+  int* btotal = nullptr;              // [1] total boxes of the batch
+  int* keys = nullptr;                // [n]
+  int* perm = nullptr;                // [n]
+  int* counts = nullptr;              // [G cap^2] kept at zero between uses
+  int* box_off = nullptr;             // [G cap^2 + 1]
+  int* cursor = nullptr;              // [G cap^2]
+  int* tile_sum = nullptr;            // [scan tiles + 1]
+  float* charges = nullptr;           // per graph 3 ng^2
+  float2* qspec = nullptr;            // per graph 3 ng (M/2+1)
+  float* kspec = nullptr;             // per graph 4 (M/2+1)^2
+  float2* ospec = nullptr;            // per graph 8 ng (M/2+1)
+  float* pot = nullptr;               // per graph ng^2 * 8
+  size_t stride_charges = 0, stride_qspec = 0, stride_kspec = 0, stride_ospec = 0, stride_pot = 0;
+  float2* frep = nullptr;             // [n]
+  float2* fent = nullptr;             // [n]
+  float* zi = nullptr;                // [n]
+  float* lnv = nullptr;               // [n] interpolated sum_j ln(eps + r^2) (cost path)
+  double* zpart = nullptr;            // [num_chunks]
+  double* zg = nullptr;               // [G]
+  double* cost_part = nullptr;        // [num_chunks * 5]
+  double* direct_part = nullptr;      // scratch of the FP64 direct kernel
+  size_t direct_part_len = 0;
+};
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+#define TSNET_HIP(call)                                                            \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return ::tsnet::fail(TSNET_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------- launchers
+// Every launcher enqueues on `s` and returns hipGetLastError().
+
+// per-evaluation path (iter.hip)
+hipError_t launch_bbox_plan(Problem& P, const float2* X, const PlanParams& pp, hipStream_t s);
+hipError_t launch_bin(Problem& P, const float2* X, hipStream_t s);
+hipError_t launch_spread(Problem& P, const float2* X, hipStream_t s);
+hipError_t launch_gather(Problem& P, const float2* X, int with_ln, hipStream_t s);
+hipError_t launch_zreduce(Problem& P, double* Z_out, hipStream_t s);
+hipError_t launch_attract(Problem& P, const float2* X, const tsnet_params& prm, float2* G,
+                          float2* F_attr, hipStream_t s);
+hipError_t launch_step(Problem& P, float2* X, float2* upd, float2* gains, const float2* G,
+                       const tsnet_step_params& sp, int iter, hipStream_t s);
+hipError_t launch_cost(Problem& P, const float2* X, const tsnet_params& prm, double* cost,
+                       hipStream_t s);
+hipError_t launch_copy_terms(Problem& P, float2* F_rep, float2* F_ent, float* Z_i, hipStream_t s);
+
+// FFT convolution (fft.hip)
+hipError_t launch_fft_conv(Problem& P, float eps, int with_ln, hipStream_t s);
+
+// direct FP64 baseline (direct.hip)
+hipError_t launch_direct(Problem& P, const double2* X, const tsnet_params& prm, double2* G,
+                         double* Z_out, const int* rows, int nrows, double* terms, hipStream_t s);
+
+// affinity build (build.hip)
+int build_affinities(Problem& P, const int64_t* indptr, const int* indices, int64_t num_arcs,
+                     double perplexity, uint64_t seed, int tie_mode, hipStream_t s);
+
+}  // namespace tsnet

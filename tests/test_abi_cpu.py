@@ -1,0 +1,53 @@
+"""Host-only checks of the C ABI library: it loads and exports every declared symbol."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tsnet.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tsnet_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2509_19785_amd import _lib
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    declared = _declared()
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(_lib.EXPORTS) == declared
+
+
+def test_defaults():
+    from paper_2509_19785_amd import _lib
+    p = _lib.tsnet_params()
+    _lib.tsnet_default_params(ctypes.byref(p))
+    assert (p.lambda_kl, p.lambda_c, p.lambda_r, p.eps_r) == (1.0, 1.2, 0.01, 0.05)
+    assert (p.interval_width, p.min_intervals, p.max_intervals, p.nodes_per_interval) == (0.25, 50, 256, 3)
+    s = _lib.tsnet_step_params()
+    _lib.tsnet_default_step_params(ctypes.byref(s))
+    assert (s.momentum_early, s.momentum_late, s.momentum_switch_iter) == (0.5, 0.8, 250)
+    assert (s.min_gain, s.gain_up, s.gain_down, s.eta) == (0.01, 0.2, 0.8, 0.0)
+
+
+def test_null_arguments_are_rejected():
+    from paper_2509_19785_amd import _lib
+    assert _lib.lib.tsnet_ctx_create(None, 0) == _lib.TSNET_EINVAL
+    assert b"NULL" in _lib.lib.tsnet_last_error()
+    assert _lib.lib.tsnet_grad(None, None, None, None, None, None, None) == _lib.TSNET_EINVAL
+    assert _lib.lib.tsnet_P_free(None) == 0 and _lib.lib.tsnet_ctx_destroy(None) == 0
+    assert _lib.lib.tsnet_stage_count() == 11
+    assert _lib.lib.tsnet_stage_name(6) == b"attract_assemble"
+
+
+def test_stage_names_unique():
+    from paper_2509_19785_amd import _lib
+    names = [_lib.lib.tsnet_stage_name(i) for i in range(_lib.lib.tsnet_stage_count())]
+    assert len(set(names)) == len(names) and _lib.lib.tsnet_stage_name(99) == b""

@@ -1,0 +1,262 @@
+"""GPU parity of the interpolation gradient, step, cost and FP64 direct path.
+
+Every expected value comes from the FP64 oracle on the same seeded inputs;
+P is built by the oracle and handed to the library with tsnet_P_from_host.
+Tolerances: kernel arithmetic against the FP64 interpolation oracle (same
+scheme) 2e-5; the total gradient against the exact O(n^2) oracle 1e-3
+relative L2 (term-normalised where the gradient itself has converged to ~0).
+"""
+import numpy as np
+import pytest
+
+from helpers import P32, rel_l2, say
+from oracle import affinities, gradient, interp, step as ostep
+from oracle.gradient import CostParams
+from synth import graphs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2509_19785_amd import api as a
+    return a
+
+
+@pytest.fixture(scope="module")
+def ctx(api):
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def grid_problem():
+    g = graphs.workload_grid32()
+    P = affinities.build_P(g.indptr, g.indices, 40.0, seed=0)
+    return g, P
+
+
+def _upload(api, ctx, P, goff=None):
+    return api.Problem.from_host(ctx, P.rowptr, P.col, P.val.astype(np.float32), goff)
+
+
+def _terms(api, prob, X, prm=None):
+    Xt = torch.tensor(X, dtype=torch.float32, device="cuda")
+    out = prob.grad_terms(Xt, prm or api.Params())
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def _interp_tol(X32):
+    """FP32 tolerance against the FP64 interpolation oracle.
+
+    F_rep and F_ent are formed as (x - c) phi[K,1] - half * phi[K,x]; both
+    products are of size half-span times the local sum, so FP32 rounding of
+    the transforms (about 1e-7 log2 M relative) is amplified by the ratio of
+    the half-span to the local interaction range (~1).
+    """
+    half = 0.5 * float((X32.max(0) - X32.min(0)).max())
+    return 2e-5 * max(1.0, half / 4.0)
+
+
+def _check_against_oracles(api, prob, P, X32, prm, tol_interp=None, tol_total=1e-3, label="",
+                           tol_terms=None, tol_Z=1e-4):
+    say(f"[grad parity] {label} n={X32.shape[0]}")
+    tol_interp = tol_interp or _interp_tol(X32)
+    tol_terms = tol_terms or tol_total
+    got = _terms(api, prob, X32, prm)
+    X = X32.astype(np.float64)
+    cp = CostParams(prm.lambda_kl, prm.lambda_c, prm.lambda_r, prm.eps_r)
+    ex = gradient.grad_terms(X, P, cp)
+    it = interp.interp_terms(X, prm.eps_r, prm.interval_width, prm.min_intervals, prm.max_intervals)
+    fa = gradient.attraction_all(X, P.rowptr, P.col, P32(P).val)
+    e_attr = rel_l2(got["F_attr"], fa)
+    e_rep_i = rel_l2(got["F_rep"], it.F_rep)
+    e_ent_i = rel_l2(got["F_ent"], it.F_ent)
+    e_z_i = rel_l2(got["Z_i"], it.Z_i)
+    e_rep = rel_l2(got["F_rep"], ex.F_rep)
+    e_ent = rel_l2(got["F_ent"], ex.F_ent)
+    e_Z = abs(got["Z"][0] - ex.Z[0]) / ex.Z[0]
+    n = X.shape[0]
+    scale = (np.linalg.norm(4 * cp.lambda_kl * ex.F_attr) + np.linalg.norm(4 * cp.lambda_kl * ex.F_rep / ex.Z[0])
+             + np.linalg.norm(cp.lambda_c / n * X) + np.linalg.norm(cp.lambda_r / n ** 2 * ex.F_ent))
+    e_G = rel_l2(got["G"], ex.G)
+    e_G_terms = np.linalg.norm(got["G"] - ex.G) / scale
+    say(f"   attr {e_attr:.2e} rep(interp) {e_rep_i:.2e} ent(interp) {e_ent_i:.2e} Zi(interp) {e_z_i:.2e}"
+        f" rep {e_rep:.2e} ent {e_ent:.2e} Z {e_Z:.2e} G {e_G:.2e} G/terms {e_G_terms:.2e}"
+        f" n_int {it.grid.n_int}")
+    assert e_attr <= 1e-6
+    assert e_rep_i <= tol_interp and e_ent_i <= tol_interp and e_z_i <= tol_interp
+    assert e_rep <= tol_terms and e_ent <= tol_terms and e_Z <= tol_Z
+    assert min(e_G, e_G_terms) <= tol_total
+    # the grid the GPU used is the oracle's grid
+    gi = prob.grid_info()
+    assert int(gi["n_intervals"][0]) == it.grid.n_int
+    assert abs(float(gi["box_side"][0]) - it.grid.h) <= 1e-6 * it.grid.h
+    return got, ex
+
+
+def test_grid32_initial_layout(api, ctx, grid_problem):
+    g, P = grid_problem
+    prob = _upload(api, ctx, P)
+    X = graphs.initial_layout(g.n, 0)
+    _check_against_oracles(api, prob, P, X, api.Params(), label="grid32 init")
+
+
+@pytest.mark.parametrize("std,max_int", [(1.0, 256), (4.0, 256), (8.0, 256), (1.0, 64)])
+def test_grid32_spread_layouts(api, ctx, grid_problem, std, max_int):
+    g, P = grid_problem
+    prob = _upload(api, ctx, P)
+    X = graphs.initial_layout(g.n, 7, std=std)
+    ctx.status()
+    _check_against_oracles(api, prob, P, X, api.Params(max_intervals=max_int),
+                           label=f"grid32 std={std} cap={max_int}")
+    assert ctx.status() == 0
+
+
+def test_capped_grid_flags_status(api, ctx, grid_problem):
+    # span ~150 needs ~600 boxes of 0.25; with the cap of 256 the box side is
+    # ~0.6, so the per-term interpolation error grows as h^3 (about 1e-2) and
+    # the status word says so; the total gradient still meets 1e-3.
+    g, P = grid_problem
+    prob = _upload(api, ctx, P)
+    X = graphs.initial_layout(g.n, 7, std=25.0)
+    ctx.status()
+    _check_against_oracles(api, prob, P, X, api.Params(), tol_terms=3e-2, tol_Z=1e-2,
+                           label="grid32 capped")
+    from paper_2509_19785_amd import _lib
+    assert ctx.status() & _lib.TSNET_STATUS_GRID_CAPPED
+
+
+def test_converged_layout(api, ctx, grid_problem):
+    g, P = grid_problem
+    X = graphs.initial_layout(g.n, 0).astype(np.float64)
+    upd, gains = np.zeros_like(X), np.ones_like(X)
+    for t in range(120):
+        G = gradient.grad_terms(X, P).G
+        X, upd, gains = ostep.step(X, upd, gains, G, t)
+    prob = _upload(api, ctx, P)
+    _check_against_oracles(api, prob, P, X.astype(np.float32), api.Params(), label="grid32 t=120")
+
+
+def test_sbm_ragged(api, ctx):
+    g = graphs.sbm([700, 900, 1433], 0.012, 4e-4, 11)
+    P = affinities.build_P(g.indptr, g.indices, 15.0, seed=3)
+    prob = _upload(api, ctx, P)
+    X = graphs.initial_layout(g.n, 5, std=0.7)
+    _check_against_oracles(api, prob, P, X, api.Params(min_intervals=8), label="sbm 3033")
+
+
+def test_batch_of_graphs(api, ctx):
+    parts = [graphs.grid(16, 20), graphs.sbm([250, 260], 0.05, 0.004, 2), graphs.random_recursive_tree(777, 9)]
+    b = graphs.concat_graphs(parts)
+    P = affinities.build_P(b.indptr, b.indices, 10.0, seed=1, graph_offsets=b.graph_offsets)
+    prob = _upload(api, ctx, P, b.graph_offsets)
+    n = b.indptr.shape[0] - 1
+    X = graphs.initial_layout(n, 3, std=1.5)
+    say(f"[grad parity] batch G=3 n={n}")
+    got = _terms(api, prob, X)
+    X64 = X.astype(np.float64)
+    ex = gradient.grad_terms(X64, P, CostParams(), b.graph_offsets)
+    gi = prob.grid_info()
+    for gidx in range(3):
+        a0, a1 = int(b.graph_offsets[gidx]), int(b.graph_offsets[gidx + 1])
+        it = interp.interp_terms(X64[a0:a1], 0.05)
+        assert int(gi["n_intervals"][gidx]) == it.grid.n_int
+        assert rel_l2(got["F_rep"][a0:a1], it.F_rep) <= 2e-5
+        assert rel_l2(got["F_ent"][a0:a1], it.F_ent) <= 2e-5
+        assert abs(got["Z"][gidx] - ex.Z[gidx]) <= 1e-4 * ex.Z[gidx]
+        assert rel_l2(got["G"][a0:a1], ex.G[a0:a1]) <= 1e-3
+
+
+def test_tiny_graphs(api, ctx):
+    # n = 1: no pairs, G = (lambda_c / n) X; n = 2 and 3 in one batch with it
+    parts = [graphs.csr_from_edges(1, np.zeros(0, np.int64), np.zeros(0, np.int64)),
+             graphs.csr_from_edges(2, np.array([0]), np.array([1])),
+             graphs.csr_from_edges(3, np.array([0, 1]), np.array([1, 2]))]
+    b = graphs.concat_graphs(parts)
+    P = affinities.build_P(b.indptr, b.indices, 2.0, graph_offsets=b.graph_offsets)
+    prob = _upload(api, ctx, P, b.graph_offsets)
+    X = np.array([[0.3, -0.4], [0.0, 0.0], [1.0, 0.5], [2.0, 1.0], [2.5, 1.2], [1.7, 0.1]], np.float32)
+    got = _terms(api, prob, X)
+    ex = gradient.grad_terms(X.astype(np.float64), P, CostParams(), b.graph_offsets)
+    assert np.allclose(got["G"][0], 1.2 * X[0], rtol=1e-6)
+    assert got["Z"][0] == 0.0
+    assert rel_l2(got["G"][1:], ex.G[1:]) <= 1e-3
+
+
+def test_bitwise_deterministic(api, ctx, grid_problem):
+    g, P = grid_problem
+    prob = _upload(api, ctx, P)
+    X = torch.tensor(graphs.initial_layout(g.n, 4, std=2.0), device="cuda")
+    a = prob.grad_terms(X)
+    b = prob.grad_terms(X)
+    torch.cuda.synchronize()
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
+
+
+def test_step_matches_oracle(api, ctx, grid_problem):
+    g, P = grid_problem
+    prob = _upload(api, ctx, P)
+    rng = np.random.default_rng(5)
+    X = rng.normal(0, 1, (g.n, 2)).astype(np.float32)
+    U = rng.normal(0, 0.01, (g.n, 2)).astype(np.float32)
+    K = rng.uniform(0.005, 3, (g.n, 2)).astype(np.float32)
+    G = rng.normal(0, 1e-3, (g.n, 2)).astype(np.float32)
+    for it, sp in [(3, api.StepParams()), (400, api.StepParams(eta=50.0))]:
+        tX, tU, tK, tG = (torch.tensor(a, device="cuda") for a in (X, U, K, G))
+        prob.step(tX, tU, tK, tG, it, sp)
+        torch.cuda.synchronize()
+        osp = ostep.StepParams(eta=sp.eta)
+        eX, eU, eK = ostep.step(X, U, K, G, it, osp)
+        # FP32 bound: a few units of rounding of the operands of each sum
+        # (X + update cancels where X ~ -update, so relative error is unbounded)
+        e32 = 2.0 ** -24
+        mu = 0.5 if it < 250 else 0.8
+        eta = sp.eta if sp.eta > 0 else 200.0
+        bU = 4 * e32 * (np.abs(mu * U) + np.abs(eta * eK * G))
+        bX = 4 * e32 * (np.abs(X) + np.abs(eU)) + 2 * bU
+        assert np.allclose(tK.cpu().numpy(), eK, rtol=2e-7, atol=0)
+        assert np.all(np.abs(tU.cpu().numpy() - eU) <= bU)
+        assert np.all(np.abs(tX.cpu().numpy() - eX) <= bX)
+
+
+def test_cost_matches_oracle(api, ctx, grid_problem):
+    g, P = grid_problem
+    prob = _upload(api, ctx, P)
+    for std in (0.01, 1.0):
+        X = graphs.initial_layout(g.n, 2, std=std)
+        say(f"[cost parity] std={std}")
+        got = prob.cost(torch.tensor(X, device="cuda")).cpu().numpy()[0]
+        ex = gradient.cost_terms(X.astype(np.float64), P, CostParams())
+        say(f"   gpu {got} oracle {ex.kl[0]} {ex.cmp[0]} {ex.ent[0]}")
+        assert abs(got[0] - ex.kl[0]) <= 1e-5 * abs(ex.kl[0])
+        assert abs(got[1] - ex.cmp[0]) <= 1e-6 * abs(ex.cmp[0])
+        assert abs(got[2] - ex.ent[0]) <= 1e-4 * abs(ex.ent[0])
+        assert abs(got[3] - ex.total[0]) <= 1e-5 * abs(ex.total[0])
+
+
+@pytest.mark.parametrize("std", [0.01, 3.0])
+def test_direct_f64_matches_oracle(api, ctx, grid_problem, std):
+    g, P = grid_problem
+    prob = _upload(api, ctx, P)
+    X = graphs.initial_layout(g.n, 8, std=std).astype(np.float64)
+    say(f"[direct parity] std={std}")
+    Gd, Zd, T = prob.grad_direct_f64(torch.tensor(X, device="cuda"), with_terms=True)
+    torch.cuda.synchronize()
+    ex = gradient.grad_terms(X, P32(P), CostParams())
+    T = T.cpu().numpy()
+    assert abs(Zd.item() - ex.Z[0]) <= 1e-12 * ex.Z[0]
+    assert rel_l2(T[:, 0:2], ex.F_attr) <= 1e-12
+    assert rel_l2(T[:, 2:4], ex.F_rep) <= 1e-12
+    assert rel_l2(T[:, 4:6], ex.F_ent) <= 1e-12
+    assert rel_l2(T[:, 6], ex.Z_i) <= 1e-12
+    assert rel_l2(Gd.cpu().numpy(), ex.G) <= 1e-12
+    rows = np.array([0, 5, 511, 1023, 77], dtype=np.int32)
+    Gr, Zr = prob.grad_direct_f64(torch.tensor(X, device="cuda"), rows=rows)
+    assert abs(Zr.item() - ex.Z[0]) <= 1e-12 * ex.Z[0]
+    assert rel_l2(Gr.cpu().numpy(), ex.G[rows]) <= 1e-12
