@@ -218,12 +218,14 @@ int tsnet_grid_info(tsnet_P P, int32_t* n_intervals, float* box_side, float* x0,
 int tsnet_status(tsnet_ctx ctx, uint32_t* flags_host);
 
 /*
- * Per-stage GPU timing for profiling. When on, each stage of tsnet_grad /
- * tsnet_step is bracketed by HIP events on the call's stream.
- * tsnet_stage_times (synchronous) returns accumulated milliseconds and call
- * counts per stage and resets them; names via tsnet_stage_name.
+ * Per-stage GPU timing for profiling. stage_mask has bit s set for every
+ * stage s (0 <= s < tsnet_stage_count()) to be bracketed by HIP events on the
+ * call's stream; 0 turns timing off. tsnet_stage_times (synchronous) returns
+ * accumulated milliseconds and call counts per stage ([tsnet_stage_count()]
+ * host arrays, either may be NULL) and resets them; names via
+ * tsnet_stage_name.
  */
-int tsnet_set_timing(tsnet_ctx ctx, int on);
+int tsnet_set_timing(tsnet_ctx ctx, uint32_t stage_mask);
 int tsnet_stage_count(void);
 const char* tsnet_stage_name(int stage);
 int tsnet_stage_times(tsnet_ctx ctx, double* ms_host, int64_t* calls_host);

@@ -98,7 +98,7 @@ _SIGS = {
                                      _vp]),
     "tsnet_grid_info": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "tsnet_status": (_i32, [_vp, _P(ctypes.c_uint32)]),
-    "tsnet_set_timing": (_i32, [_vp, _i32]),
+    "tsnet_set_timing": (_i32, [_vp, ctypes.c_uint32]),
     "tsnet_stage_count": (_i32, []),
     "tsnet_stage_name": (ctypes.c_char_p, [_i32]),
     "tsnet_stage_times": (_i32, [_vp, _vp, _vp]),

@@ -92,8 +92,17 @@ class Context:
         check(lib.tsnet_status(self.handle, ctypes.byref(v)))
         return v.value
 
-    def set_timing(self, on: bool):
-        check(lib.tsnet_set_timing(self.handle, int(bool(on))))
+    def set_timing(self, stages=None):
+        """Time the named stages with HIP events (None or [] = off, "all" = every stage)."""
+        k = lib.tsnet_stage_count()
+        names = [lib.tsnet_stage_name(i).decode() for i in range(k)]
+        if stages == "all":
+            mask = (1 << k) - 1
+        else:
+            mask = 0
+            for s in stages or []:
+                mask |= 1 << names.index(s)
+        check(lib.tsnet_set_timing(self.handle, mask))
 
     def stage_times(self):
         k = lib.tsnet_stage_count()

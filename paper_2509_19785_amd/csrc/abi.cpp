@@ -59,7 +59,7 @@ struct StageScope {
   hipStream_t s;
   hipEvent_t a = nullptr;
   StageScope(Ctx& c_, int st_, hipStream_t s_) : c(c_), st(st_), s(s_) {
-    if (!c.timing) return;
+    if (!(c.timing & (1u << st))) return;
     a = take_event();
     if (a) (void)hipEventRecord(a, s);
   }
@@ -74,7 +74,7 @@ struct StageScope {
     return e;
   }
   ~StageScope() {
-    if (!c.timing || !a) return;
+    if (!a) return;
     hipEvent_t b = take_event();
     if (!b) {
       c.ev_free.push_back(a);
@@ -625,9 +625,9 @@ int tsnet_status(tsnet_ctx ctx, uint32_t* flags_host) {
   return TSNET_OK;
 }
 
-int tsnet_set_timing(tsnet_ctx ctx, int on) {
+int tsnet_set_timing(tsnet_ctx ctx, uint32_t stage_mask) {
   if (!ctx) return fail(TSNET_EINVAL, "ctx is NULL");
-  ctx->c.timing = on != 0;
+  ctx->c.timing = stage_mask & ((1u << ST_COUNT) - 1u);
   return TSNET_OK;
 }
 

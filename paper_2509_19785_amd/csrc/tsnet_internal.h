@@ -71,7 +71,7 @@ struct Ctx {
   float2* twiddle = nullptr;          // e^{-2 pi i m / kMaxM}, m < kMaxM
   unsigned* status = nullptr;         // device status word
   int lds_per_block = 65536;
-  bool timing = false;
+  uint32_t timing = 0;                // bit s: time stage s
   std::vector<hipEvent_t> ev_free;    // recycled events
   struct Pending { int stage; hipEvent_t a, b; };
   std::vector<Pending> pending;
