@@ -101,10 +101,7 @@ static int collect_times(Ctx& c) {
 
 // ---------------------------------------------------------------- problems
 static void free_grid(Problem& P) {
-  dfree(P.counts);
   dfree(P.box_off);
-  dfree(P.cursor);
-  dfree(P.tile_sum);
   dfree(P.charges);
   dfree(P.qspec);
   dfree(P.kspec);
@@ -133,7 +130,19 @@ static void free_problem(Problem& P) {
   dfree(P.counters);
   dfree(P.btotal);
   dfree(P.keys);
+  dfree(P.keys_tmp);
+  dfree(P.perm_tmp);
+  dfree(P.perm_tmp2);
+  dfree(P.skeys);
   dfree(P.perm);
+  dfree(P.xs);
+  dfree(P.bin_hist);
+  dfree(P.bin_tsum);
+  dfree(P.head_box);
+  dfree(P.tail_box);
+  dfree(P.head_val);
+  dfree(P.tail_val);
+  dfree(P.row_order);
   dfree(P.frep);
   dfree(P.fent);
   dfree(P.zi);
@@ -188,11 +197,21 @@ static int init_problem(Ctx& c, Problem& P, int n, const int32_t* goff_host, int
   }
   P.num_chunks = (int)cg.size();
   const int nc = P.num_chunks;
+  const size_t tiles = ((size_t)n + kBinTileH - 1) / kBinTileH;
+  const size_t ranges = ((size_t)n + kSpreadRange - 1) / kSpreadRange;
   if ((rc = dmalloc(&P.ginfo, G, "ginfo")) || (rc = dmalloc(&P.goff_d, G + 1, "goff")) ||
       (rc = dmalloc(&P.chunk_graph, nc, "chunks")) || (rc = dmalloc(&P.chunk_start, nc, "chunks")) ||
       (rc = dmalloc(&P.chunk_end, nc, "chunks")) || (rc = dmalloc(&P.desc, G, "desc")) ||
       (rc = dmalloc(&P.bbox_part, nc, "bbox")) || (rc = dmalloc(&P.counters, 8, "counters")) ||
       (rc = dmalloc(&P.btotal, 1, "btotal")) || (rc = dmalloc(&P.keys, n, "keys")) ||
+      (rc = dmalloc(&P.keys_tmp, n, "keys")) || (rc = dmalloc(&P.perm_tmp, n, "perm")) ||
+      (rc = dmalloc(&P.perm_tmp2, n, "perm")) || (rc = dmalloc(&P.skeys, n, "keys")) ||
+      (rc = dmalloc(&P.xs, n, "xs")) ||
+      (rc = dmalloc(&P.bin_hist, (size_t)256 * tiles + 1, "hist")) ||
+      (rc = dmalloc(&P.bin_tsum, (size_t)256 * tiles / 2048 + 8, "hist")) ||
+      (rc = dmalloc(&P.head_box, ranges, "ranges")) || (rc = dmalloc(&P.tail_box, ranges, "ranges")) ||
+      (rc = dmalloc(&P.head_val, ranges * 27, "ranges")) ||
+      (rc = dmalloc(&P.tail_val, ranges * 27, "ranges")) ||
       (rc = dmalloc(&P.perm, n, "perm")) || (rc = dmalloc(&P.frep, n, "frep")) ||
       (rc = dmalloc(&P.fent, n, "fent")) || (rc = dmalloc(&P.zi, n, "zi")) ||
       (rc = dmalloc(&P.lnv, n, "lnv")) || (rc = dmalloc(&P.zpart, nc, "zpart")) ||
@@ -220,11 +239,9 @@ static int ensure_grid(Problem& P, int cap) {
   P.stride_ospec = 8 * ng * Mh;
   P.stride_pot = ng * ng * kPotCh;
   const size_t boxes = (size_t)P.G * cap * cap;
-  if (boxes >= (size_t)1 << 31) return fail(TSNET_EINVAL, "too many interpolation boxes in batch");
-  const size_t tiles = (boxes + kScanTile - 1) / kScanTile + 1;
+  if (boxes >= (size_t)1 << 30) return fail(TSNET_EINVAL, "too many interpolation boxes in batch");
   int rc;
-  if ((rc = dmalloc(&P.counts, boxes, "counts")) || (rc = dmalloc(&P.box_off, boxes + 1, "box_off")) ||
-      (rc = dmalloc(&P.cursor, boxes, "cursor")) || (rc = dmalloc(&P.tile_sum, tiles, "tiles")) ||
+  if ((rc = dmalloc(&P.box_off, boxes + 1, "box_off")) ||
       (rc = dmalloc(&P.charges, P.stride_charges * P.G, "charges")) ||
       (rc = dmalloc(&P.qspec, P.stride_qspec * P.G, "qspec")) ||
       (rc = dmalloc(&P.kspec, P.stride_kspec * P.G, "kspec")) ||
@@ -233,9 +250,15 @@ static int ensure_grid(Problem& P, int cap) {
     free_grid(P);
     return rc;
   }
-  TSNET_HIP(hipMemset(P.counts, 0, sizeof(int) * boxes));
   P.cap = cap;
   return TSNET_OK;
+}
+
+// Layouts derived from P once it exists.
+static int finish_problem(Problem& P, hipStream_t s) {
+  if (P.nnz >= ((int64_t)1 << 31)) return fail(TSNET_EINVAL, "P has more than 2^31 nonzeros");
+  (void)s;
+  return build_row_order(P);
 }
 
 static int check_params(const tsnet_params* p) {
@@ -431,6 +454,7 @@ int tsnet_build_P(tsnet_ctx ctx, const int64_t* indptr, const int32_t* indices, 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     StageScope t(ctx->c, ST_BUILD, s);
     rc = build_affinities(P->p, indptr, indices, num_arcs, perplexity, tie_seed, tie_mode, s);
+    if (!rc) rc = finish_problem(P->p, s);
   }
   if (rc) {
     std::string msg = g_err;
@@ -479,6 +503,10 @@ int tsnet_P_from_host(tsnet_ctx ctx, int32_t n, const int64_t* rowptr_host,
     if (e == hipSuccess && nnz > 0)
       e = hipMemcpy(P->p.val, val_host, sizeof(float) * nnz, hipMemcpyHostToDevice);
     if (e != hipSuccess) rc = fail(TSNET_EHIP, std::string("copy P: ") + hipGetErrorString(e));
+  }
+  if (!rc) {
+    P->p.nnz = nnz;
+    rc = finish_problem(P->p, nullptr);
   }
   if (rc) {
     std::string msg = g_err;

@@ -1,7 +1,7 @@
 // Per-evaluation kernels of the L-tsNET gradient: bounding box and grid plan,
-// counting sort of points by box, fixed-point spread to the interpolation
-// nodes, gather back to the points, Z reduction, the sparse attractive pass
-// fused with the gradient assembly, and the vertex move.
+// gather of the node potentials back to the points, Z reduction, the vertex
+// move and the cost. Binning and spread live in bin.hip, the attraction in
+// attract.hip, the convolution in fft.hip.
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -69,24 +69,32 @@ __global__ __launch_bounds__(256) void k_bbox_plan(
   __syncthreads();
   if (!last_s) return;
   __threadfence();
-  for (int g = threadIdx.x; g < G; g += blockDim.x) {
-    double a = DBL_MAX, b = -DBL_MAX, e = DBL_MAX, f = -DBL_MAX;
+  // one wave per graph: lanes stride over the graph's chunks
+  for (int g = wave_id(); g < G; g += blockDim.x / kWave) {
+    float a = FLT_MAX, b = -FLT_MAX, e = FLT_MAX, f = -FLT_MAX;
     int nonfinite = 0;
-    for (int k = gi[g].chunk_begin; k < gi[g].chunk_end; ++k) {
+    for (int k = gi[g].chunk_begin + lane_id(); k < gi[g].chunk_end; k += kWave) {
       const float4 q = ld_coherent4(&part[k]);
       if (isnan(q.x)) nonfinite = 1;
       if (q.y >= q.x) {  // chunk had at least one finite point
-        a = fmin(a, (double)q.x);
-        b = fmax(b, (double)q.y);
-        e = fmin(e, (double)q.z);
-        f = fmax(f, (double)q.w);
+        a = fminf(a, q.x);
+        b = fmaxf(b, q.y);
+        e = fminf(e, q.z);
+        f = fmaxf(f, q.w);
       }
     }
-    if (!(b >= a)) {  // no finite point at all
-      a = b = e = f = 0.0;
+    a = wave_min(a);
+    b = wave_max(b);
+    e = wave_min(e);
+    f = wave_max(f);
+    nonfinite = __any(nonfinite);
+    if (lane_id() != 0) continue;
+    double da = a, db = b, de = e, df = f;
+    if (!(db >= da)) {  // no finite point at all
+      da = db = de = df = 0.0;
     }
     int flags = nonfinite ? TSNET_STATUS_NONFINITE : 0;
-    double span = fmax(b - a, f - e);
+    double span = fmax(db - da, df - de);
     if (!(span >= kSpanFloor)) span = kSpanFloor;
     const double q = span / pp.h_target;
     int nint;
@@ -101,7 +109,7 @@ __global__ __launch_bounds__(256) void k_bbox_plan(
     while (p2 < nint) p2 <<= 1;
     nint = p2 < pp.max_int ? p2 : pp.max_int;
     const double h = span / nint;
-    const double cx = 0.5 * (a + b), cy = 0.5 * (e + f);
+    const double cx = 0.5 * (da + db), cy = 0.5 * (de + df);
     GridDesc d;
     d.x0 = (float)(cx - 0.5 * nint * h);
     d.y0 = (float)(cy - 0.5 * nint * h);
@@ -140,197 +148,14 @@ hipError_t launch_bbox_plan(Problem& P, const float2* X, const PlanParams& pp, h
 }
 
 // ---------------------------------------------------------------------------
-// Counting sort of points by global box id: keys + histogram, scan, scatter.
-__global__ __launch_bounds__(256) void k_keys_hist(const float2* __restrict__ X,
-                                                   const int* __restrict__ chunk_graph,
-                                                   const int* __restrict__ chunk_start,
-                                                   const int* __restrict__ chunk_end,
-                                                   const GridDesc* __restrict__ desc, int* keys,
-                                                   int* counts) {
-  const int c = blockIdx.x;
-  const GridDesc d = desc[chunk_graph[c]];
-  for (int i = chunk_start[c] + threadIdx.x; i < chunk_end[c]; i += blockDim.x) {
-    const float2 p = X[i];
-    int bx, by;
-    float s, t;
-    locate(d, p.x, p.y, bx, by, s, t);
-    const int key = d.box_base + by * d.n_int + bx;
-    keys[i] = key;
-    atomicAdd(&counts[key], 1);
-  }
-}
-
-// Tile sums of counts[0, btotal).
-__global__ __launch_bounds__(256) void k_scan_tiles(const int* __restrict__ counts,
-                                                    const int* __restrict__ btotal,
-                                                    int* tile_sum) {
-  const int B = *btotal;
-  const int base = blockIdx.x * kScanTile;
-  if (base >= B) return;
-  int v = 0;
-  for (int k = threadIdx.x; k < kScanTile; k += blockDim.x) {
-    const int idx = base + k;
-    if (idx < B) v += counts[idx];
-  }
-  v = wave_sum(v);
-  __shared__ int sh[4];
-  if (lane_id() == 0) sh[wave_id()] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) tile_sum[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
-}
-
-// Exclusive scan of the tile sums (one block of 1024 threads).
-__global__ __launch_bounds__(1024) void k_scan_top(int* tile_sum, const int* __restrict__ btotal) {
-  __shared__ int sh[17];
-  const int T = (*btotal + kScanTile - 1) / kScanTile;
-  int carry = 0;
-  for (int base = 0; base < T; base += 1024) {
-    const int idx = base + threadIdx.x;
-    const int v = idx < T ? tile_sum[idx] : 0;
-    int tot;
-    const int ex = block_excl_scan(v, sh, &tot);
-    if (idx < T) tile_sum[idx] = carry + ex;
-    carry += tot;
-  }
-}
-
-// Box offsets: box_off[k] = first sorted slot of box k; cursor = box_off;
-// counts are cleared for the next evaluation.
-__global__ __launch_bounds__(256) void k_scan_apply(int* counts, const int* __restrict__ btotal,
-                                                    const int* __restrict__ tile_sum,
-                                                    int* box_off, int* cursor) {
-  __shared__ int sh[5];
-  const int B = *btotal;
-  const int base = blockIdx.x * kScanTile;
-  if (base >= B) return;
-  constexpr int per = kScanTile / 256;
-  const int first = base + threadIdx.x * per;
-  int loc[per];
-  int sum = 0;
-#pragma unroll
-  for (int k = 0; k < per; ++k) {
-    const int idx = first + k;
-    loc[k] = idx < B ? counts[idx] : 0;
-    sum += loc[k];
-  }
-  int tot;
-  int run = block_excl_scan(sum, sh, &tot) + tile_sum[blockIdx.x];
-#pragma unroll
-  for (int k = 0; k < per; ++k) {
-    const int idx = first + k;
-    if (idx < B) {
-      box_off[idx] = run;
-      cursor[idx] = run;
-      counts[idx] = 0;
-    }
-    run += loc[k];
-  }
-  if (base + kScanTile >= B && threadIdx.x == 255) box_off[B] = run;
-}
-
-__global__ __launch_bounds__(256) void k_scatter(const int* __restrict__ keys, int n, int* cursor,
-                                                 int* perm) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const int pos = atomicAdd(&cursor[keys[i]], 1);
-    perm[pos] = i;
-  }
-}
-
-hipError_t launch_bin(Problem& P, const float2* X, hipStream_t s) {
-  const int tiles = (P.G * P.cap * P.cap + kScanTile - 1) / kScanTile;
-  hipLaunchKernelGGL(k_keys_hist, dim3(P.num_chunks), dim3(256), 0, s, X, P.chunk_graph,
-                     P.chunk_start, P.chunk_end, P.desc, P.keys, P.counts);
-  hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(256), 0, s, P.counts, P.btotal, P.tile_sum);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, P.tile_sum, P.btotal);
-  hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(256), 0, s, P.counts, P.btotal, P.tile_sum,
-                     P.box_off, P.cursor);
-  const int blocks = (P.n + 255) / 256 < 4096 ? (P.n + 255) / 256 : 4096;
-  hipLaunchKernelGGL(k_scatter, dim3(blocks), dim3(256), 0, s, P.keys, P.n, P.cursor, P.perm);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Spread (Sec. 2.3): node charge w[c][a] = sum over the points of the node's box
-// of L_tx(s) L_ty(t) q_c with q = (1, (x - cx) / half, (y - cy) / half). One
-// wave per box; each contribution is rounded to a 2^-28 grid and summed in
-// 64-bit integers, so the result does not depend on the order of the points.
-__global__ __launch_bounds__(256) void k_spread(const float2* __restrict__ X,
-                                                const int* __restrict__ perm,
-                                                const int* __restrict__ box_off,
-                                                const GridDesc* __restrict__ desc, float* charges,
-                                                size_t stride) {
-  const int g = blockIdx.y;
-  const GridDesc d = desc[g];
-  const int nb = d.n_int * d.n_int;
-  const int ng = d.ng;
-  float* out = charges + (size_t)g * stride;
-  const int lane = lane_id();
-  const int nwaves = blockDim.x / kWave;
-  for (int b = blockIdx.x * nwaves + wave_id(); b < nb; b += gridDim.x * nwaves) {
-    const int by = b / d.n_int, bx = b - by * d.n_int;
-    const int start = box_off[d.box_base + b], end = box_off[d.box_base + b + 1];
-    long long acc[27];
-#pragma unroll
-    for (int k = 0; k < 27; ++k) acc[k] = 0;
-    const float inv_half = 1.0f / d.half;
-    for (int p = start + lane; p < end; p += kWave) {
-      const float2 x = X[perm[p]];
-      const float s = (x.x - d.x0) / d.h - (float)bx;
-      const float t = (x.y - d.y0) / d.h - (float)by;
-      float lx[3], ly[3];
-      lagrange3(s, lx);
-      lagrange3(t, ly);
-      const float q1 = (x.x - d.cx) * inv_half, q2 = (x.y - d.cy) * inv_half;
-#pragma unroll
-      for (int ty = 0; ty < 3; ++ty) {
-#pragma unroll
-        for (int tx = 0; tx < 3; ++tx) {
-          const float w = ly[ty] * lx[tx];
-          const float v0 = fminf(fmaxf(w, -4.0f), 4.0f);
-          const float v1 = fminf(fmaxf(w * q1, -4.0f), 4.0f);
-          const float v2 = fminf(fmaxf(w * q2, -4.0f), 4.0f);
-          const int k = (ty * 3 + tx) * 3;
-          acc[k + 0] += (long long)__float2int_rn(v0 * kFixScale);
-          acc[k + 1] += (long long)__float2int_rn(v1 * kFixScale);
-          acc[k + 2] += (long long)__float2int_rn(v2 * kFixScale);
-        }
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < 27; ++k) acc[k] = wave_sum(acc[k]);
-    if (lane == 0) {
-      const double inv = 1.0 / (double)kFixScale;
-#pragma unroll
-      for (int ty = 0; ty < 3; ++ty) {
-#pragma unroll
-        for (int tx = 0; tx < 3; ++tx) {
-          const size_t node = (size_t)(3 * by + ty) * ng + (3 * bx + tx);
-          const int k = (ty * 3 + tx) * 3;
-#pragma unroll
-          for (int c = 0; c < 3; ++c) out[(size_t)c * ng * ng + node] = (float)((double)acc[k + c] * inv);
-        }
-      }
-    }
-  }
-}
-
-hipError_t launch_spread(Problem& P, const float2* X, hipStream_t s) {
-  const int nb = P.cap * P.cap;
-  int bx = (nb + 3) / 4;
-  const int max_bx = P.G > 1 ? 64 : 1024;
-  if (bx > max_bx) bx = max_bx;
-  hipLaunchKernelGGL(k_spread, dim3(bx, P.G), dim3(256), 0, s, X, P.perm, P.box_off, P.desc,
-                     P.charges, P.stride_charges);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
 // Gather (Sec. 2.3 / Sec. 3.3): interpolate the 8 node potentials to every
-// point (in sorted order, so a wave reads few nodes), then form
+// point in sorted order (coordinates and box ids come from the binning, so a
+// wave reads few nodes), then form
 //   F_rep = (x - c) phi[K2,1] - phi[K2,x],  F_ent = (x - c) phi[Ke,1] - phi[Ke,x],
-//   Z_i = phi[K1,1] - 1 (the self term K1(0) = 1).
+//   Z_i = phi[K1,1] - 1 (the self term K1(0) = 1),
+// and write them at the vertex of the slot.
 __global__ __launch_bounds__(256) void k_gather(
-    const float2* __restrict__ X, const int* __restrict__ perm,
+    const float2* __restrict__ xs, const int* __restrict__ skeys, const int* __restrict__ perm,
     const int* __restrict__ chunk_graph, const int* __restrict__ chunk_start,
     const int* __restrict__ chunk_end, const GridDesc* __restrict__ desc,
     const GraphInfo* __restrict__ gi, const float* __restrict__ pot, size_t stride_pot,
@@ -341,11 +166,11 @@ __global__ __launch_bounds__(256) void k_gather(
   const float* pg = pot + (size_t)g * stride_pot;
   const bool single = gi[g].n == 1;
   for (int p = chunk_start[c] + threadIdx.x; p < chunk_end[c]; p += blockDim.x) {
-    const int i = perm[p];
-    const float2 x = X[i];
-    int bx, by;
-    float s, t;
-    locate(d, x.x, x.y, bx, by, s, t);
+    const float2 x = xs[p];
+    const int local = skeys[p] - d.box_base;
+    const int by = local / d.n_int, bx = local - by * d.n_int;
+    const float s = (x.x - d.x0) / d.h - (float)bx;
+    const float t = (x.y - d.y0) / d.h - (float)by;
     float lx[3], ly[3];
     lagrange3(s, lx);
     lagrange3(t, ly);
@@ -381,6 +206,7 @@ __global__ __launch_bounds__(256) void k_gather(
       e = make_float2(0.f, 0.f);
       z = 0.f;
     }
+    const int i = perm[p];
     frep[i] = r;
     fent[i] = e;
     zi[i] = z;
@@ -389,9 +215,10 @@ __global__ __launch_bounds__(256) void k_gather(
 }
 
 hipError_t launch_gather(Problem& P, const float2* X, int with_ln, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather, dim3(P.num_chunks), dim3(256), 0, s, X, P.perm, P.chunk_graph,
-                     P.chunk_start, P.chunk_end, P.desc, P.ginfo, P.pot, P.stride_pot, P.frep,
-                     P.fent, P.zi, with_ln ? P.lnv : nullptr);
+  (void)X;
+  hipLaunchKernelGGL(k_gather, dim3(P.num_chunks), dim3(256), 0, s, P.xs, P.skeys, P.perm,
+                     P.chunk_graph, P.chunk_start, P.chunk_end, P.desc, P.ginfo, P.pot,
+                     P.stride_pot, P.frep, P.fent, P.zi, with_ln ? P.lnv : nullptr);
   return hipGetLastError();
 }
 
@@ -424,11 +251,14 @@ __global__ __launch_bounds__(256) void k_zreduce(const float* __restrict__ zi,
   __syncthreads();
   if (!last_s) return;
   __threadfence();
-  for (int g = threadIdx.x; g < G; g += blockDim.x) {
+  for (int g = wave_id(); g < G; g += blockDim.x / kWave) {
     double z = 0.0;
-    for (int k = gi[g].chunk_begin; k < gi[g].chunk_end; ++k) z += ld_coherent(&zpart[k]);
-    zg[g] = z;
-    if (Z_out) Z_out[g] = z;
+    for (int k = gi[g].chunk_begin + lane_id(); k < gi[g].chunk_end; k += kWave) z += ld_coherent(&zpart[k]);
+    z = wave_sum(z);
+    if (lane_id() == 0) {
+      zg[g] = z;
+      if (Z_out) Z_out[g] = z;
+    }
   }
   if (threadIdx.x == 0) *counter = 0u;
 }
@@ -436,66 +266,6 @@ __global__ __launch_bounds__(256) void k_zreduce(const float* __restrict__ zi,
 hipError_t launch_zreduce(Problem& P, double* Z_out, hipStream_t s) {
   hipLaunchKernelGGL(k_zreduce, dim3(P.num_chunks), dim3(256), 0, s, P.zi, P.chunk_start,
                      P.chunk_end, P.num_chunks, P.zpart, P.counters + 1, P.ginfo, P.G, P.zg, Z_out);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Attractive KL term over the sparse P (Eq. 6, first sum) fused with the
-// assembly of the gradient:
-//   G_i = 4 l_kl (F_attr,i - F_rep,i / Z) + (l_c / n) X_i - (l_r / n^2) F_ent,i.
-// One wave per row, lanes over the row's nonzeros.
-struct AttrParams {
-  float lkl4, lc, lr;
-};
-
-__global__ __launch_bounds__(256) void k_attract(
-    const float2* __restrict__ X, const int64_t* __restrict__ rowptr, const int* __restrict__ col,
-    const float* __restrict__ val, int n, const int* __restrict__ goff, int G,
-    const GraphInfo* __restrict__ gi, const double* __restrict__ zg,
-    const float2* __restrict__ frep, const float2* __restrict__ fent, AttrParams ap, float2* Gout,
-    float2* Fattr) {
-  const int lane = lane_id();
-  const int nwaves = blockDim.x / kWave;
-  for (int i = blockIdx.x * nwaves + wave_id(); i < n; i += gridDim.x * nwaves) {
-    const int64_t a = rowptr[i], b = rowptr[i + 1];
-    const float2 xi = X[i];
-    float fx = 0.f, fy = 0.f;
-    for (int64_t e = a + lane; e < b; e += kWave) {
-      const int j = col[e];
-      const float p = val[e];
-      const float2 xj = X[j];
-      const float dx = xi.x - xj.x, dy = xi.y - xj.y;
-      const float pw = p / (1.0f + dx * dx + dy * dy);
-      fx += pw * dx;
-      fy += pw * dy;
-    }
-    fx = wave_sum(fx);
-    fy = wave_sum(fy);
-    if (lane == 0) {
-      const int g = G == 1 ? 0 : graph_of(goff, G, i);
-      const double Z = zg[g];
-      const float inv_z = Z > 0.0 ? (float)(1.0 / Z) : 0.0f;
-      const float2 r = frep[i], e = fent[i];
-      const float cn = ap.lc * gi[g].inv_n, rn = ap.lr * gi[g].inv_n2;
-      float2 out;
-      out.x = ap.lkl4 * (fx - r.x * inv_z) + cn * xi.x - rn * e.x;
-      out.y = ap.lkl4 * (fy - r.y * inv_z) + cn * xi.y - rn * e.y;
-      Gout[i] = out;
-      if (Fattr) Fattr[i] = make_float2(fx, fy);
-    }
-  }
-}
-
-hipError_t launch_attract(Problem& P, const float2* X, const tsnet_params& prm, float2* G,
-                          float2* F_attr, hipStream_t s) {
-  AttrParams ap;
-  ap.lkl4 = (float)(4.0 * prm.lambda_kl);
-  ap.lc = (float)prm.lambda_c;
-  ap.lr = (float)prm.lambda_r;
-  int blocks = (P.n + 3) / 4;
-  if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(k_attract, dim3(blocks), dim3(256), 0, s, X, P.rowptr, P.col, P.val, P.n,
-                     P.goff_d, P.G, P.ginfo, P.zg, P.frep, P.fent, ap, G, F_attr);
   return hipGetLastError();
 }
 
@@ -617,10 +387,12 @@ __global__ __launch_bounds__(256) void k_cost_reduce(
   __syncthreads();
   if (!last_s) return;
   __threadfence();
-  for (int g = threadIdx.x; g < G; g += blockDim.x) {
+  for (int g = wave_id(); g < G; g += blockDim.x / kWave) {
     double s[5] = {0, 0, 0, 0, 0};
-    for (int k = gi[g].chunk_begin; k < gi[g].chunk_end; ++k)
+    for (int k = gi[g].chunk_begin + lane_id(); k < gi[g].chunk_end; k += kWave)
       for (int q = 0; q < 5; ++q) s[q] += ld_coherent(&part[(size_t)k * 5 + q]);
+    for (int q = 0; q < 5; ++q) s[q] = wave_sum(s[q]);
+    if (lane_id() != 0) continue;
     const double n = (double)gi[g].n;
     const double Z = s[4];
     const double kl = (n > 1 && Z > 0) ? ck.lkl * (s[0] + s[1] * log(Z)) : 0.0;

@@ -21,7 +21,8 @@ constexpr int kChunk = 2048;              // vertices per chunk of per-vertex ke
 constexpr int kMaxK = 1024;               // neighbours per vertex in tsnet_build_P
 constexpr double kSpanFloor = 1e-4;       // smallest grid span (degenerate layouts)
 constexpr float kFixScale = 268435456.0f; // 2^28: fixed-point scale of spread contributions
-constexpr int kScanTile = 4096;           // entries per tile of the box-offset scan
+constexpr int kBinTileH = 2048;           // points per tile of the binning radix sort
+constexpr int kSpreadRange = 256;         // sorted points per wave in the spread
 
 // Output channels of the convolution (charge index in comments):
 //  0 K2*1, 1 K2*x, 2 K2*y, 3 K1*1, 4 Ke*1, 5 Ke*x, 6 Ke*y, 7 Kln*1
@@ -98,6 +99,7 @@ struct Problem {
   int64_t* rowptr = nullptr;
   int* col = nullptr;
   float* val = nullptr;
+  int* row_order = nullptr;           // [n] rows by decreasing length (attraction order)
   // device: conditional rows and calibration (absent for host-made P)
   double* beta = nullptr;
   int8_t* rstatus = nullptr;
@@ -110,12 +112,20 @@ struct Problem {
   float4* bbox_part = nullptr;        // [num_chunks]
   unsigned* counters = nullptr;       // [8] last-block counters (kept at zero)
   int* btotal = nullptr;              // [1] total boxes of the batch
-  int* keys = nullptr;                // [n]
-  int* perm = nullptr;                // [n]
-  int* counts = nullptr;              // [G cap^2] kept at zero between uses
-  int* box_off = nullptr;             // [G cap^2 + 1]
-  int* cursor = nullptr;              // [G cap^2]
-  int* tile_sum = nullptr;            // [scan tiles + 1]
+  int* keys = nullptr;                // [n] box id of every vertex
+  int* keys_tmp = nullptr;            // [n] radix ping-pong
+  int* perm_tmp = nullptr;            // [n]
+  int* perm_tmp2 = nullptr;           // [n]
+  int* skeys = nullptr;               // [n] box ids in sorted order
+  int* perm = nullptr;                // [n] vertex of each sorted slot
+  float2* xs = nullptr;               // [n] X in sorted order
+  int* bin_hist = nullptr;            // [256 tiles + 1] digit counts, then offsets
+  int* bin_tsum = nullptr;            // scan scratch
+  int* head_box = nullptr;            // [spread ranges] box of the leading partial
+  int* tail_box = nullptr;            // [spread ranges] box of the trailing partial
+  long long* head_val = nullptr;      // [spread ranges][27]
+  long long* tail_val = nullptr;      // [spread ranges][27]
+  int* box_off = nullptr;             // [G cap^2 + 1] first sorted slot of every box
   float* charges = nullptr;           // per graph 3 ng^2
   float2* qspec = nullptr;            // per graph 3 ng (M/2+1)
   float* kspec = nullptr;             // per graph 4 (M/2+1)^2
@@ -146,7 +156,7 @@ int fail(int code, const std::string& msg);
 // ---------------------------------------------------------------- launchers
 // Every launcher enqueues on `s` and returns hipGetLastError().
 
-// per-evaluation path (iter.hip)
+// per-evaluation path (iter.hip, bin.hip, attract.hip)
 hipError_t launch_bbox_plan(Problem& P, const float2* X, const PlanParams& pp, hipStream_t s);
 hipError_t launch_bin(Problem& P, const float2* X, hipStream_t s);
 hipError_t launch_spread(Problem& P, const float2* X, hipStream_t s);
@@ -159,6 +169,9 @@ hipError_t launch_step(Problem& P, float2* X, float2* upd, float2* gains, const 
 hipError_t launch_cost(Problem& P, const float2* X, const tsnet_params& prm, double* cost,
                        hipStream_t s);
 hipError_t launch_copy_terms(Problem& P, float2* F_rep, float2* F_ent, float* Z_i, hipStream_t s);
+
+// visiting order of the attraction rows (attract.hip), built once per problem
+int build_row_order(Problem& P);
 
 // FFT convolution (fft.hip)
 hipError_t launch_fft_conv(Problem& P, float eps, int with_ln, hipStream_t s);
