@@ -62,7 +62,10 @@ typedef struct tsnet_P_s*   tsnet_P;     /* one problem: graph batch, P, workspa
  *  interval_width: target box side h of the interpolation grid; the box count
  *    per axis is ceil(span / h) clamped to [min_intervals, max_intervals] and
  *    rounded up to a power of two (the paper leaves I and P open, Sec. 2.3).
- *  min_intervals >= 1, max_intervals a power of two in [min_intervals, 256].
+ *  min_intervals >= 1, max_intervals a power of two in [min_intervals, 512].
+ *  The evaluation workspace is sized for max_intervals boxes per axis in
+ *  every graph of the problem (about 600 MB per graph at 512, 9.5 MB at 64),
+ *  so batches of many graphs should lower it.
  *  nodes_per_interval: interpolation points per box and axis; must be 3.
  */
 typedef struct {
@@ -95,7 +98,7 @@ typedef struct {
   int32_t reserved;
 } tsnet_step_params;
 
-/* Defaults: 1, 1.2, 0.01, 0.05, h = 0.25, 50..256 intervals, 3 nodes. */
+/* Defaults: 1, 1.2, 0.01, 0.05, h = 0.25, 50..512 intervals, 3 nodes. */
 void tsnet_default_params(tsnet_params* p);
 /* Defaults: eta <= 0 (per-graph rule), 0.5 / 0.8 switching at 250, 0.01, 0.2, 0.8. */
 void tsnet_default_step_params(tsnet_step_params* p);

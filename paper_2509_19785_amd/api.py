@@ -24,7 +24,7 @@ class Params:
     eps_r: float = 0.05
     interval_width: float = 0.25
     min_intervals: int = 50
-    max_intervals: int = 256
+    max_intervals: int = 512
     nodes_per_interval: int = 3
 
     def to_c(self) -> _lib.tsnet_params:

@@ -104,8 +104,11 @@ static void free_grid(Problem& P) {
   dfree(P.box_off);
   dfree(P.charges);
   dfree(P.qspec);
+  dfree(P.qspec_t);
   dfree(P.kspec);
+  dfree(P.kspec_t);
   dfree(P.ospec);
+  dfree(P.ospec_t);
   dfree(P.pot);
   P.cap = 0;
 }
@@ -244,8 +247,11 @@ static int ensure_grid(Problem& P, int cap) {
   if ((rc = dmalloc(&P.box_off, boxes + 1, "box_off")) ||
       (rc = dmalloc(&P.charges, P.stride_charges * P.G, "charges")) ||
       (rc = dmalloc(&P.qspec, P.stride_qspec * P.G, "qspec")) ||
+      (rc = dmalloc(&P.qspec_t, P.stride_qspec * P.G, "qspec")) ||
       (rc = dmalloc(&P.kspec, P.stride_kspec * P.G, "kspec")) ||
+      (rc = dmalloc(&P.kspec_t, P.stride_kspec * P.G, "kspec")) ||
       (rc = dmalloc(&P.ospec, P.stride_ospec * P.G, "ospec")) ||
+      (rc = dmalloc(&P.ospec_t, P.stride_ospec * P.G, "ospec")) ||
       (rc = dmalloc(&P.pot, P.stride_pot * P.G, "pot"))) {
     free_grid(P);
     return rc;
@@ -266,7 +272,7 @@ static int check_params(const tsnet_params* p) {
   if (p->nodes_per_interval != kNodes) return fail(TSNET_EINVAL, "nodes_per_interval must be 3");
   const int mx = p->max_intervals, mn = p->min_intervals;
   if (mx < 1 || mx > kMaxIntervals || (mx & (mx - 1)))
-    return fail(TSNET_EINVAL, "max_intervals must be a power of two in [1, 256]");
+    return fail(TSNET_EINVAL, "max_intervals must be a power of two in [1, 512]");
   if (mn < 1 || mn > mx) return fail(TSNET_EINVAL, "min_intervals must be in [1, max_intervals]");
   if (!(p->interval_width > 0) || !std::isfinite(p->interval_width))
     return fail(TSNET_EINVAL, "interval_width must be positive and finite");
@@ -364,7 +370,7 @@ void tsnet_default_params(tsnet_params* p) {
   p->eps_r = 0.05;
   p->interval_width = 0.25;
   p->min_intervals = 50;
-  p->max_intervals = 256;
+  p->max_intervals = 512;
   p->nodes_per_interval = 3;
 }
 

@@ -3,20 +3,29 @@
 //
 // Per graph the node grid is N_g x N_g (N_g = 3 n_int); the linear convolution
 // with each kernel is embedded in an M x M circulant, M = 2 N_g = 3 * 2^b. The
-// kernels are even in both axes, so their 2-D spectra are real.
+// kernels are even in both axes, so their 2-D spectra are real. Every
+// transform runs along contiguous memory; tiled transposes sit between the
+// row and column stages:
 //
-//  rows_fwd: real rows -> half spectra. Charge rows pack (q0 + i q1) and
-//            (q2 + i 0); kernel rows pack (K2 + i K1) and (Ke + i Kln) and are
-//            generated on the fly (rows r and M - r coincide, so M/2 + 1 rows).
-//  cols:     per frequency column: kernel columns (real, mirrored) -> real
-//            kernel spectra; each charge column -> spectrum; products; inverse
-//            column transforms of the 7 (8 with ln) outputs, rows < N_g kept.
-//  rows_inv: pairs of output channels share one complex inverse row transform
-//            (u + i v); the first N_g values of each row are the potentials,
-//            scaled by 1 / M^2, stored node-major with 8 channels per node.
+//  rows_fwd:  real rows -> half spectra Qr[c][y][kx] (charges 1, x, y packed
+//             as q0 + i q1 and q2) and Kr[k][y][kx] (kernels generated on the
+//             fly, packed as K2 + i K1 and Ke + i Kln; rows y and M - y
+//             coincide, so only y <= M/2).
+//  transpose: Qr -> Qt[c][kx][y], Kr -> Kt[k][kx][y].
+//  cols:      per frequency column kx: the mirrored kernel columns give the
+//             real kernel spectra (kept in registers); each charge column is
+//             transformed (kept in registers), multiplied by its kernels and
+//             transformed back; rows < N_g of the 7 (8 with ln) outputs go to
+//             Ot[o][kx][y].
+//  transpose: Ot -> Or[o][y][kx].
+//  rows_inv:  two output channels share one complex inverse row transform
+//             (u + i v); the first N_g values of each row, times 1 / M^2, are
+//             the node potentials, stored node-major with 8 channels per node.
 //
-// All transforms are one Stockham autosort FFT over LDS with radix-4 passes,
-// one radix-2 pass when b is odd, and a final radix-3 pass.
+// The transforms are one Stockham autosort FFT over LDS with radix-4 passes,
+// one radix-2 pass when b is odd, and a final radix-3 pass. Each block owns
+// two LDS buffers of kFftElems complex values (48 KB); sequences of length
+// M share a block kFftElems / M at a time.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -26,7 +35,10 @@
 
 namespace tsnet {
 
-constexpr int kFftLds = 65536;  // bytes of LDS per block for every FFT kernel
+constexpr int kFftElems = kMaxM;              // complex values per LDS buffer
+constexpr int kFftLds = 2 * kFftElems * 8;    // bytes of LDS per FFT block
+constexpr int kFftThreads = 256;
+constexpr int kPerThread = kFftElems / kFftThreads;  // register slots per thread
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -113,12 +125,15 @@ struct FftArgs {
   const float2* tw;
   const float* charges;
   size_t s_charges;
-  float2* qspec;
-  size_t s_qspec;
-  float* kspec;
-  size_t s_kspec;
-  float2* ospec;
-  size_t s_ospec;
+  float2* qr;   // [3][ng][Mh]
+  float2* qt;   // [3][Mh][ng]
+  size_t s_q;
+  float* kr;    // [4][Mh][Mh]
+  float* kt;    // [4][Mh][Mh] transposed
+  size_t s_k;
+  float2* ot;   // [8][Mh][ng]
+  float2* orr;  // [8][ng][Mh]
+  size_t s_o;
   float* pot;
   size_t s_pot;
   float eps;
@@ -126,76 +141,75 @@ struct FftArgs {
 };
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_fft_rows_fwd(FftArgs A) {
+// Row transforms of the charges and kernels. Sequence s of a graph:
+//   s < 2 ng:        charge row s / 2, part s % 2 (0: q0 + i q1, 1: q2)
+//   otherwise:       kernel row (s - 2 ng) / 2 in [0, M/2], part (0: K2 + i K1, 1: Ke + i Kln)
+__global__ __launch_bounds__(kFftThreads) void k_fft_rows_fwd(FftArgs A) {
   extern __shared__ float2 lds[];
   const int g = blockIdx.y;
   const GridDesc d = A.desc[g];
   const int M = d.M, ng = d.ng, Mh = M / 2 + 1;
-  const int capc = kFftLds / 16;  // complex values per ping-pong buffer
   float2* bufA = lds;
-  float2* bufB = lds + capc;
-  const int J = capc / (2 * M) > 0 ? capc / (2 * M) : 1;
-  const int jobs = ng + Mh;
+  float2* bufB = lds + kFftElems;
+  const int S = kFftElems / M;  // sequences per block iteration (>= 1)
+  const int nseq = 2 * ng + 2 * Mh;
   const float* ch = A.charges + (size_t)g * A.s_charges;
-  float2* qs = A.qspec + (size_t)g * A.s_qspec;
-  float* ks = A.kspec + (size_t)g * A.s_kspec;
+  float2* qs = A.qr + (size_t)g * A.s_q;
+  float* ks = A.kr + (size_t)g * A.s_k;
   const float sp = d.spacing;
-  for (int j0 = blockIdx.x * J; j0 < jobs; j0 += gridDim.x * J) {
-    const int nj = jobs - j0 < J ? jobs - j0 : J;
-    for (int idx = threadIdx.x; idx < nj * 2 * M; idx += blockDim.x) {
-      const int jl = idx / (2 * M);
-      const int rem = idx - jl * 2 * M;
-      const int sq = rem / M, x = rem - sq * M;
-      const int job = j0 + jl;
+  for (int s0 = blockIdx.x * S; s0 < nseq; s0 += gridDim.x * S) {
+    const int ns = nseq - s0 < S ? nseq - s0 : S;
+    for (int idx = threadIdx.x; idx < ns * M; idx += blockDim.x) {
+      const int sl = idx / M, x = idx - sl * M;
+      const int sq = s0 + sl;
       float2 v;
-      if (job < ng) {
-        const int ry = job;
+      if (sq < 2 * ng) {
+        const int ry = sq >> 1, part = sq & 1;
         if (x < ng) {
           const size_t o = (size_t)ry * ng + x;
-          v = sq == 0 ? make_float2(ch[o], ch[(size_t)ng * ng + o])
-                      : make_float2(ch[2 * (size_t)ng * ng + o], 0.f);
+          v = part == 0 ? make_float2(ch[o], ch[(size_t)ng * ng + o])
+                        : make_float2(ch[2 * (size_t)ng * ng + o], 0.f);
         } else {
           v = make_float2(0.f, 0.f);
         }
       } else {
-        const int ry = job - ng;
+        const int t = sq - 2 * ng;
+        const int ry = t >> 1, part = t & 1;
         const int xi = x < M - x ? x : M - x;
         const float dy = (float)ry * sp, dx = (float)xi * sp;
         const float r2 = dy * dy + dx * dx;
-        if (sq == 0) {
+        if (part == 0) {
           const float w = 1.0f / (1.0f + r2);
           v = make_float2(w * w, w);
         } else {
           v = make_float2(1.0f / (A.eps + r2), A.with_ln ? logf(A.eps + r2) : 0.f);
         }
       }
-      bufA[jl * 2 * M + sq * M + x] = v;
+      bufA[idx] = v;
     }
     __syncthreads();
-    const float2* res = block_fft(bufA, bufB, nj * 2, M, A.tw, -1);
-    for (int idx = threadIdx.x; idx < nj * Mh; idx += blockDim.x) {
-      const int jl = idx / Mh;
-      const int k = idx - jl * Mh;
+    const float2* res = block_fft(bufA, bufB, ns, M, A.tw, -1);
+    for (int idx = threadIdx.x; idx < ns * Mh; idx += blockDim.x) {
+      const int sl = idx / Mh, k = idx - sl * Mh;
       const int km = k == 0 ? 0 : M - k;
-      const float2* s0 = res + jl * 2 * M;
-      const float2* s1 = s0 + M;
-      const int job = j0 + jl;
-      const float2 a = s0[k], ar = s0[km];
-      if (job < ng) {
-        const int ry = job;
-        // Q0 = (A_k + conj A_{M-k}) / 2,  Q1 = -i (A_k - conj A_{M-k}) / 2
-        const float2 q0 = make_float2(0.5f * (a.x + ar.x), 0.5f * (a.y - ar.y));
-        const float2 q1 = make_float2(0.5f * (a.y + ar.y), -0.5f * (a.x - ar.x));
-        qs[((size_t)0 * ng + ry) * Mh + k] = q0;
-        qs[((size_t)1 * ng + ry) * Mh + k] = q1;
-        qs[((size_t)2 * ng + ry) * Mh + k] = s1[k];
+      const float2* z = res + sl * M;
+      const float2 a = z[k], ar = z[km];
+      const int sq = s0 + sl;
+      if (sq < 2 * ng) {
+        const int ry = sq >> 1, part = sq & 1;
+        if (part == 0) {
+          // Q0 = (A_k + conj A_{M-k}) / 2,  Q1 = -i (A_k - conj A_{M-k}) / 2
+          qs[((size_t)0 * ng + ry) * Mh + k] = make_float2(0.5f * (a.x + ar.x), 0.5f * (a.y - ar.y));
+          qs[((size_t)1 * ng + ry) * Mh + k] = make_float2(0.5f * (a.y + ar.y), -0.5f * (a.x - ar.x));
+        } else {
+          qs[((size_t)2 * ng + ry) * Mh + k] = a;
+        }
       } else {
-        const int ry = job - ng;
-        const float2 b = s1[k], br = s1[km];
-        ks[((size_t)0 * Mh + ry) * Mh + k] = 0.5f * (a.x + ar.x);
-        ks[((size_t)1 * Mh + ry) * Mh + k] = 0.5f * (a.y + ar.y);
-        ks[((size_t)2 * Mh + ry) * Mh + k] = 0.5f * (b.x + br.x);
-        ks[((size_t)3 * Mh + ry) * Mh + k] = 0.5f * (b.y + br.y);
+        const int t = sq - 2 * ng;
+        const int ry = t >> 1, part = t & 1;
+        // real spectra of the two packed even rows
+        ks[((size_t)(2 * part) * Mh + ry) * Mh + k] = 0.5f * (a.x + ar.x);
+        ks[((size_t)(2 * part + 1) * Mh + ry) * Mh + k] = 0.5f * (a.y + ar.y);
       }
     }
     __syncthreads();
@@ -203,72 +217,122 @@ __global__ __launch_bounds__(256) void k_fft_rows_fwd(FftArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_fft_cols(FftArgs A) {
+// Tiled transposes in[b][r][c] -> out[b][c][r], r < R, c < C (sizes per graph).
+template <typename T>
+__device__ __forceinline__ void transpose_tiles(const T* __restrict__ in, T* out, int R, int C,
+                                                int nb, T (*tile)[33]) {
+  const int tilesR = (R + 31) / 32, tilesC = (C + 31) / 32;
+  const int per = tilesR * tilesC;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads
+  for (int t = blockIdx.x; t < nb * per; t += gridDim.x) {
+    const int b = t / per, rem = t - b * per;
+    const int tr = rem / tilesC, tc = rem - tr * tilesC;
+    const T* ib = in + (size_t)b * R * C;
+    T* ob = out + (size_t)b * R * C;
+    for (int k = ty; k < 32; k += 8) {
+      const int r = tr * 32 + k, c = tc * 32 + tx;
+      if (r < R && c < C) tile[k][tx] = ib[(size_t)r * C + c];
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+      const int c = tc * 32 + k, r = tr * 32 + tx;
+      if (r < R && c < C) ob[(size_t)c * R + r] = tile[tx][k];
+    }
+    __syncthreads();
+  }
+}
+
+// which = 0: Qr -> Qt; 1: Kr -> Kt; 2: Ot -> Or
+__global__ __launch_bounds__(256) void k_fft_transpose(FftArgs A, int which) {
+  const int g = blockIdx.y;
+  const GridDesc d = A.desc[g];
+  const int ng = d.ng, Mh = d.M / 2 + 1;
+  if (which == 1) {
+    __shared__ float tf[32][33];
+    transpose_tiles<float>(A.kr + (size_t)g * A.s_k, A.kt + (size_t)g * A.s_k, Mh, Mh, 4, tf);
+  } else {
+    __shared__ float2 tc[32][33];
+    if (which == 0)
+      transpose_tiles<float2>(A.qr + (size_t)g * A.s_q, A.qt + (size_t)g * A.s_q, ng, Mh, 3, tc);
+    else
+      transpose_tiles<float2>(A.ot + (size_t)g * A.s_o, A.orr + (size_t)g * A.s_o, Mh, ng,
+                              A.with_ln ? 8 : 7, tc);
+  }
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kFftThreads) void k_fft_cols(FftArgs A) {
   extern __shared__ float2 lds[];
   const int g = blockIdx.y;
   const GridDesc d = A.desc[g];
   const int M = d.M, ng = d.ng, Mh = M / 2 + 1;
-  int nc = kFftLds / (40 * M);
-  if (nc < 1) nc = 1;
-  float* khat = reinterpret_cast<float*>(lds);           // [4][nc][M]
-  float2* B0 = lds + (size_t)2 * nc * M;                  // after 4 nc M floats
-  float2* B1 = B0 + (size_t)nc * M;
-  float2* B2 = B1 + (size_t)nc * M;
-  const float2* qs = A.qspec + (size_t)g * A.s_qspec;
-  const float* ks = A.kspec + (size_t)g * A.s_kspec;
-  float2* os = A.ospec + (size_t)g * A.s_ospec;
+  const int S = kFftElems / M;  // columns per block iteration
+  float2* B0 = lds;
+  float2* B1 = lds + kFftElems;
+  const float2* qt = A.qt + (size_t)g * A.s_q;
+  const float* kt = A.kt + (size_t)g * A.s_k;
+  float2* ot = A.ot + (size_t)g * A.s_o;
   const int nout0 = A.with_ln ? 4 : 3;
-  for (int c0 = blockIdx.x * nc; c0 < Mh; c0 += gridDim.x * nc) {
-    const int ncc = Mh - c0 < nc ? Mh - c0 : nc;
-    // kernel spectra: two packed real columns per transform
+  for (int c0 = blockIdx.x * S; c0 < Mh; c0 += gridDim.x * S) {
+    const int ncc = Mh - c0 < S ? Mh - c0 : S;
+    const int tot = ncc * M;
+    float kh[4][kPerThread];
+    // kernel spectra: two packed real columns per transform, kept in registers
     for (int pair = 0; pair < 2; ++pair) {
-      for (int idx = threadIdx.x; idx < ncc * M; idx += blockDim.x) {
-        const int y = idx / ncc, col = idx - y * ncc;
+      for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+        const int col = idx / M, y = idx - col * M;
         const int ry = y < M - y ? y : M - y;
-        const size_t o = (size_t)ry * Mh + c0 + col;
-        B0[col * M + y] = make_float2(ks[(size_t)(2 * pair) * Mh * Mh + o],
-                                      ks[(size_t)(2 * pair + 1) * Mh * Mh + o]);
+        const size_t o = (size_t)(c0 + col) * Mh + ry;
+        B0[idx] = make_float2(kt[(size_t)(2 * pair) * Mh * Mh + o], kt[(size_t)(2 * pair + 1) * Mh * Mh + o]);
       }
       __syncthreads();
       const float2* r = block_fft(B0, B1, ncc, M, A.tw, -1);
-      for (int idx = threadIdx.x; idx < ncc * M; idx += blockDim.x) {
-        const float2 v = r[idx];
-        khat[(size_t)(2 * pair) * nc * M + idx] = v.x;
-        khat[(size_t)(2 * pair + 1) * nc * M + idx] = v.y;
+#pragma unroll
+      for (int q = 0; q < kPerThread; ++q) {
+        const int idx = threadIdx.x + q * kFftThreads;
+        const float2 v = idx < tot ? r[idx] : make_float2(0.f, 0.f);
+        kh[2 * pair][q] = v.x;
+        kh[2 * pair + 1][q] = v.y;
       }
       __syncthreads();
     }
     for (int c = 0; c < 3; ++c) {
-      for (int idx = threadIdx.x; idx < ncc * M; idx += blockDim.x) {
-        const int y = idx / ncc, col = idx - y * ncc;
-        B0[col * M + y] = y < ng ? qs[((size_t)c * ng + y) * Mh + c0 + col] : make_float2(0.f, 0.f);
+      for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+        const int col = idx / M, y = idx - col * M;
+        B0[idx] = y < ng ? qt[((size_t)c * Mh + c0 + col) * ng + y] : make_float2(0.f, 0.f);
       }
       __syncthreads();
       const float2* Q = block_fft(B0, B1, ncc, M, A.tw, -1);
-      float2* fr = Q == B0 ? B1 : B0;
+      float2 qh[kPerThread];
+#pragma unroll
+      for (int q = 0; q < kPerThread; ++q) {
+        const int idx = threadIdx.x + q * kFftThreads;
+        qh[q] = idx < tot ? Q[idx] : make_float2(0.f, 0.f);
+      }
+      __syncthreads();
       const int nout = c == 0 ? nout0 : 2;
       for (int t = 0; t < nout; ++t) {
         int o, kk;
         if (c == 0) {
-          const int oo[4] = {CH_K2_1, CH_K1_1, CH_KE_1, CH_KLN_1};
-          const int kq[4] = {0, 1, 2, 3};
-          o = oo[t];
-          kk = kq[t];
+          o = t == 0 ? CH_K2_1 : (t == 1 ? CH_K1_1 : (t == 2 ? CH_KE_1 : CH_KLN_1));
+          kk = t;
         } else {
           o = t == 0 ? (c == 1 ? CH_K2_X : CH_K2_Y) : (c == 1 ? CH_KE_X : CH_KE_Y);
           kk = t == 0 ? 0 : 2;
         }
-        const float* kh = khat + (size_t)kk * nc * M;
-        for (int idx = threadIdx.x; idx < ncc * M; idx += blockDim.x) {
-          const float2 q = Q[idx];
-          const float kv = kh[idx];
-          fr[idx] = make_float2(kv * q.x, kv * q.y);
+#pragma unroll
+        for (int q = 0; q < kPerThread; ++q) {
+          const int idx = threadIdx.x + q * kFftThreads;
+          if (idx < tot) {
+            const float kv = kk == 0 ? kh[0][q] : (kk == 1 ? kh[1][q] : (kk == 2 ? kh[2][q] : kh[3][q]));
+            B0[idx] = make_float2(kv * qh[q].x, kv * qh[q].y);
+          }
         }
         __syncthreads();
-        const float2* r = block_fft(fr, B2, ncc, M, A.tw, +1);
+        const float2* r = block_fft(B0, B1, ncc, M, A.tw, +1);
         for (int idx = threadIdx.x; idx < ncc * ng; idx += blockDim.x) {
-          const int y = idx / ncc, col = idx - y * ncc;
-          os[((size_t)o * ng + y) * Mh + c0 + col] = r[col * M + y];
+          const int col = idx / ng, y = idx - col * ng;
+          ot[((size_t)o * Mh + c0 + col) * ng + y] = r[col * M + y];
         }
         __syncthreads();
       }
@@ -277,21 +341,21 @@ __global__ __launch_bounds__(256) void k_fft_cols(FftArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_fft_rows_inv(FftArgs A) {
+// Inverse rows: job (row y, pair p) transforms F_{2p} + i F_{2p+1}.
+__global__ __launch_bounds__(kFftThreads) void k_fft_rows_inv(FftArgs A) {
   extern __shared__ float2 lds[];
   const int g = blockIdx.y;
   const GridDesc d = A.desc[g];
   const int M = d.M, ng = d.ng, Mh = M / 2 + 1;
-  const int capc = kFftLds / 16;
   float2* bufA = lds;
-  float2* bufB = lds + capc;
-  const int J = capc / M;
+  float2* bufB = lds + kFftElems;
+  const int S = kFftElems / M;
   const int jobs = ng * 4;
-  const float2* os = A.ospec + (size_t)g * A.s_ospec;
+  const float2* orr = A.orr + (size_t)g * A.s_o;
   float* pg = A.pot + (size_t)g * A.s_pot;
   const float scale = 1.0f / ((float)M * (float)M);
-  for (int j0 = blockIdx.x * J; j0 < jobs; j0 += gridDim.x * J) {
-    const int nj = jobs - j0 < J ? jobs - j0 : J;
+  for (int j0 = blockIdx.x * S; j0 < jobs; j0 += gridDim.x * S) {
+    const int nj = jobs - j0 < S ? jobs - j0 : S;
     for (int idx = threadIdx.x; idx < nj * M; idx += blockDim.x) {
       const int jl = idx / M, k = idx - jl * M;
       const int job = j0 + jl;
@@ -299,14 +363,14 @@ __global__ __launch_bounds__(256) void k_fft_rows_inv(FftArgs A) {
       const int o0 = 2 * pr, o1 = 2 * pr + 1;
       const bool conj_ = k > M / 2;
       const int kk = conj_ ? M - k : k;
-      float2 f0 = os[((size_t)o0 * ng + ry) * Mh + kk];
+      float2 f0 = orr[((size_t)o0 * ng + ry) * Mh + kk];
       float2 f1 = (o1 == CH_KLN_1 && !A.with_ln) ? make_float2(0.f, 0.f)
-                                                  : os[((size_t)o1 * ng + ry) * Mh + kk];
+                                                  : orr[((size_t)o1 * ng + ry) * Mh + kk];
       if (conj_) {
         f0.y = -f0.y;
         f1.y = -f1.y;
       }
-      bufA[jl * M + k] = make_float2(f0.x - f1.y, f0.y + f1.x);
+      bufA[idx] = make_float2(f0.x - f1.y, f0.y + f1.x);
     }
     __syncthreads();
     const float2* res = block_fft(bufA, bufB, nj, M, A.tw, +1);
@@ -328,20 +392,27 @@ hipError_t launch_fft_conv(Problem& P, float eps, int with_ln, hipStream_t s) {
   A.tw = P.ctx->twiddle;
   A.charges = P.charges;
   A.s_charges = P.stride_charges;
-  A.qspec = P.qspec;
-  A.s_qspec = P.stride_qspec;
-  A.kspec = P.kspec;
-  A.s_kspec = P.stride_kspec;
-  A.ospec = P.ospec;
-  A.s_ospec = P.stride_ospec;
+  A.qr = P.qspec;
+  A.qt = P.qspec_t;
+  A.s_q = P.stride_qspec;
+  A.kr = P.kspec;
+  A.kt = P.kspec_t;
+  A.s_k = P.stride_kspec;
+  A.ot = P.ospec_t;
+  A.orr = P.ospec;
+  A.s_o = P.stride_ospec;
   A.pot = P.pot;
   A.s_pot = P.stride_pot;
   A.eps = eps;
   A.with_ln = with_ln;
-  const int bx = P.G >= 64 ? 4 : (P.G >= 8 ? 32 : 256);
-  hipLaunchKernelGGL(k_fft_rows_fwd, dim3(bx, P.G), dim3(256), kFftLds, s, A);
-  hipLaunchKernelGGL(k_fft_cols, dim3(bx, P.G), dim3(256), kFftLds, s, A);
-  hipLaunchKernelGGL(k_fft_rows_inv, dim3(bx, P.G), dim3(256), kFftLds, s, A);
+  const int bx = P.G >= 64 ? 4 : (P.G >= 8 ? 32 : 512);
+  const int tb = P.G >= 64 ? 16 : (P.G >= 8 ? 64 : 1024);
+  hipLaunchKernelGGL(k_fft_rows_fwd, dim3(bx, P.G), dim3(kFftThreads), kFftLds, s, A);
+  hipLaunchKernelGGL(k_fft_transpose, dim3(tb, P.G), dim3(256), 0, s, A, 0);
+  hipLaunchKernelGGL(k_fft_transpose, dim3(tb, P.G), dim3(256), 0, s, A, 1);
+  hipLaunchKernelGGL(k_fft_cols, dim3(bx, P.G), dim3(kFftThreads), kFftLds, s, A);
+  hipLaunchKernelGGL(k_fft_transpose, dim3(tb, P.G), dim3(256), 0, s, A, 2);
+  hipLaunchKernelGGL(k_fft_rows_inv, dim3(bx, P.G), dim3(kFftThreads), kFftLds, s, A);
   return hipGetLastError();
 }
 

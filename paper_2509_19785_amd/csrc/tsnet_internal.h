@@ -13,7 +13,7 @@ namespace tsnet {
 
 // ---------------------------------------------------------------- constants
 constexpr int kNodes = 3;                 // interpolation nodes per box and axis
-constexpr int kMaxIntervals = 256;        // boxes per axis (power of two)
+constexpr int kMaxIntervals = 512;        // boxes per axis (power of two)
 constexpr int kMaxNg = kNodes * kMaxIntervals;
 constexpr int kMaxM = 2 * kMaxNg;         // FFT length per axis (3 * 2^b)
 constexpr int kPotCh = 8;                 // interleaved potential channels per node
@@ -127,9 +127,12 @@ struct Problem {
   long long* tail_val = nullptr;      // [spread ranges][27]
   int* box_off = nullptr;             // [G cap^2 + 1] first sorted slot of every box
   float* charges = nullptr;           // per graph 3 ng^2
-  float2* qspec = nullptr;            // per graph 3 ng (M/2+1)
-  float* kspec = nullptr;             // per graph 4 (M/2+1)^2
-  float2* ospec = nullptr;            // per graph 8 ng (M/2+1)
+  float2* qspec = nullptr;            // per graph [3][ng][M/2+1] row spectra of the charges
+  float2* qspec_t = nullptr;          // per graph [3][M/2+1][ng] the same, transposed
+  float* kspec = nullptr;             // per graph [4][M/2+1][M/2+1] row spectra of the kernels
+  float* kspec_t = nullptr;           // per graph the same, transposed
+  float2* ospec_t = nullptr;          // per graph [8][M/2+1][ng] products after the column stage
+  float2* ospec = nullptr;            // per graph [8][ng][M/2+1] the same, transposed
   float* pot = nullptr;               // per graph ng^2 * 8
   size_t stride_charges = 0, stride_qspec = 0, stride_kspec = 0, stride_ospec = 0, stride_pot = 0;
   float2* frep = nullptr;             // [n]

@@ -30,7 +30,7 @@ def test_defaults():
     p = _lib.tsnet_params()
     _lib.tsnet_default_params(ctypes.byref(p))
     assert (p.lambda_kl, p.lambda_c, p.lambda_r, p.eps_r) == (1.0, 1.2, 0.01, 0.05)
-    assert (p.interval_width, p.min_intervals, p.max_intervals, p.nodes_per_interval) == (0.25, 50, 256, 3)
+    assert (p.interval_width, p.min_intervals, p.max_intervals, p.nodes_per_interval) == (0.25, 50, 512, 3)
     s = _lib.tsnet_step_params()
     _lib.tsnet_default_step_params(ctypes.byref(s))
     assert (s.momentum_early, s.momentum_late, s.momentum_switch_iter) == (0.5, 0.8, 250)
