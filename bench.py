@@ -88,7 +88,18 @@ def main():
     ap.add_argument("--direct-iters", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-intervals", type=int, default=512)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run 5 device copies of 1 GiB (reference for the HBM traffic counters)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copied 5 x 1 GiB")
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)

@@ -45,6 +45,11 @@ extern "C" {
 #define TSNET_TIE_HASH 0     /* key = SplitMix64 hash of (seed, source, target) */
 #define TSNET_TIE_ID   1     /* key = target id                                 */
 
+/* attract_layout of tsnet_params: how the attractive sum over P is laid out */
+#define TSNET_ATTRACT_AUTO  0  /* tiled from 262144 vertices on, else rows        */
+#define TSNET_ATTRACT_ROWS  1  /* one wave per CSR row, x_j gathered from HBM     */
+#define TSNET_ATTRACT_TILED 2  /* row tiles x column windows, x_j read from LDS   */
+
 /* bits of the device status word (tsnet_status) */
 #define TSNET_STATUS_NONFINITE   0x1u  /* NaN/Inf in X at some grid set-up          */
 #define TSNET_STATUS_GRID_CAPPED 0x2u  /* span / interval_width > max_intervals      */
@@ -67,6 +72,12 @@ typedef struct tsnet_P_s*   tsnet_P;     /* one problem: graph batch, P, workspa
  *  every graph of the problem (about 600 MB per graph at 512, 9.5 MB at 64),
  *  so batches of many graphs should lower it.
  *  nodes_per_interval: interpolation points per box and axis; must be 3.
+ *  attract_layout: TSNET_ATTRACT_*. The tiled layout is a second copy of P
+ *    (8 bytes per nonzero) made on the first evaluation that needs it, or in
+ *    tsnet_build_P / tsnet_P_from_host when the automatic choice picks it; it
+ *    supports up to about 5.8 million vertices (TSNET_EINVAL beyond). Both
+ *    layouts compute the same sums in different orders (FP32 results differ
+ *    by rounding only).
  */
 typedef struct {
   double  lambda_kl;
@@ -77,7 +88,7 @@ typedef struct {
   int32_t min_intervals;
   int32_t max_intervals;
   int32_t nodes_per_interval;
-  int32_t reserved;
+  int32_t attract_layout;
 } tsnet_params;
 
 /*

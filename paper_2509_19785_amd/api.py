@@ -26,6 +26,7 @@ class Params:
     min_intervals: int = 50
     max_intervals: int = 512
     nodes_per_interval: int = 3
+    attract_layout: int = 0   # 0 automatic, 1 CSR rows, 2 tiled (row tiles x column windows)
 
     def to_c(self) -> _lib.tsnet_params:
         p = _lib.tsnet_params()

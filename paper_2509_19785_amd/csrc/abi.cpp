@@ -123,6 +123,10 @@ static void free_problem(Problem& P) {
   dfree(P.rowptr);
   dfree(P.col);
   dfree(P.val);
+  dfree(P.tile_rows);
+  dfree(P.tile_bstart);
+  dfree(P.tile_ent);
+  P.tile_T = P.tile_R = P.tile_NC = 0;
   dfree(P.beta);
   dfree(P.rstatus);
   dfree(P.cond_len);
@@ -263,8 +267,14 @@ static int ensure_grid(Problem& P, int cap) {
 // Layouts derived from P once it exists.
 static int finish_problem(Problem& P, hipStream_t s) {
   if (P.nnz >= ((int64_t)1 << 31)) return fail(TSNET_EINVAL, "P has more than 2^31 nonzeros");
-  (void)s;
-  return build_row_order(P);
+  int rc = build_row_order(P);
+  if (!rc && P.n >= kTileAutoMinN && tiles_supported(P.n)) rc = build_tiles(P, s);
+  return rc;
+}
+
+static bool use_tiles(const Problem& P, const tsnet_params& prm) {
+  if (prm.attract_layout == TSNET_ATTRACT_TILED) return true;
+  return prm.attract_layout == TSNET_ATTRACT_AUTO && P.n >= kTileAutoMinN && tiles_supported(P.n);
 }
 
 static int check_params(const tsnet_params* p) {
@@ -279,6 +289,8 @@ static int check_params(const tsnet_params* p) {
   if (!(p->eps_r > 0) || !std::isfinite(p->eps_r)) return fail(TSNET_EINVAL, "eps_r must be > 0");
   if (!std::isfinite(p->lambda_kl) || !std::isfinite(p->lambda_c) || !std::isfinite(p->lambda_r))
     return fail(TSNET_EINVAL, "lambda values must be finite");
+  if (p->attract_layout < TSNET_ATTRACT_AUTO || p->attract_layout > TSNET_ATTRACT_TILED)
+    return fail(TSNET_EINVAL, "attract_layout must be 0, 1 or 2");
   return TSNET_OK;
 }
 
@@ -344,10 +356,16 @@ static int grad_impl(tsnet_ctx ctx, tsnet_P Pp, const float* X, const tsnet_para
     StageScope t(c, ST_ZRED, s);
     TSNET_LAUNCH(launch_zreduce(P, Z_out, s));
   }
+  const bool tiled = use_tiles(P, *prm);
+  if (tiled && P.tile_T == 0 && (rc = build_tiles(P, s))) return rc;
   {
     StageScope t(c, ST_ATTR, s);
-    TSNET_LAUNCH(launch_attract(P, X2, *prm, reinterpret_cast<float2*>(G),
-                                reinterpret_cast<float2*>(F_attr), s));
+    if (tiled)
+      TSNET_LAUNCH(launch_attract_tiled(P, X2, *prm, reinterpret_cast<float2*>(G),
+                                        reinterpret_cast<float2*>(F_attr), s));
+    else
+      TSNET_LAUNCH(launch_attract(P, X2, *prm, reinterpret_cast<float2*>(G),
+                                  reinterpret_cast<float2*>(F_attr), s));
   }
   if (F_rep || F_ent || Z_i)
     TSNET_LAUNCH(launch_copy_terms(P, reinterpret_cast<float2*>(F_rep),

@@ -433,7 +433,6 @@ __global__ __launch_bounds__(256) void k_perplexity(const int* __restrict__ len,
 
 // ---------------------------------------------------------------------------
 // Stable LSD radix sort of (key, value) pairs, 8-bit digits.
-constexpr int kRadixTile = 2048;  // elements per block tile (8 rounds of 256)
 
 __global__ __launch_bounds__(256) void k_radix_hist(const unsigned* __restrict__ keys, int N,
                                                     int shift, int tiles, int* hist) {
@@ -499,8 +498,8 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const unsigned* __restric
 
 // Sorts (keys, vals) by the low `bits` bits of the key; the result ends in
 // (keys, vals) (ping-pong through kt, vt). Buffers of N entries; hist of 256 * tiles.
-static hipError_t radix_sort(unsigned* keys, unsigned* vals, unsigned* kt, unsigned* vt, int N,
-                             int bits, int* hist, int* tsum, hipStream_t s) {
+hipError_t radix_sort(unsigned* keys, unsigned* vals, unsigned* kt, unsigned* vt, int N, int bits,
+                      int* hist, int* tsum, hipStream_t s) {
   const int tiles = (N + kRadixTile - 1) / kRadixTile;
   if (tiles == 0) return hipSuccess;
   unsigned *ka = keys, *va = vals, *kb = kt, *vb = vt;

@@ -1,0 +1,487 @@
+// Attractive KL term (Eq. 6, first sum) over a two-dimensional tiling of P,
+// fused with the gradient assembly
+//   G_i = 4 l_kl (F_attr,i - F_rep,i / Z) + (l_c / n) X_i - (l_r / n^2) F_ent,i.
+//
+// The row-parallel kernel (attract.hip) gathers x_j straight from HBM; on a
+// graph like Barabasi-Albert the columns of a row are scattered over all of X,
+// so most of those gathers miss L2 and refetch whole lines. Here the gathers
+// come from LDS instead:
+//
+//  * rows are dealt to T row tiles in snake order over decreasing row length
+//    (every tile holds about nnz / T entries); the rows of a tile get slots
+//    0 .. R-1;
+//  * columns are cut into windows of kTileCols vertices;
+//  * block (t, c) holds the entries of tile t's rows whose column lies in
+//    window c, ordered by slot and packed as {slot << 13 | column offset in
+//    the window, value bits}.
+//
+// One workgroup per row tile walks the windows in order, with X[window] in LDS
+// (the next window is fetched into registers while the current one is in use)
+// and the row sums of its tile in LDS. A block is cut into 16 equal pieces,
+// one per wave; a lane walks a run of up to 8 consecutive entries, and partial
+// row sums are joined across lanes by a segmented scan. A row that continues
+// from the previous wave's piece is parked in a slot of its own and added once
+// the window is done. Every sum is taken in an order fixed by the layout, so
+// results are reproducible.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <initializer_list>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "dev_util.h"
+#include "scan.h"
+#include "tsnet_internal.h"
+
+namespace tsnet {
+
+constexpr int kTileColBits = 13;
+constexpr int kTileCols = 1 << kTileColBits;  // vertices per column window (64 KB of X)
+constexpr int kTileThreads = 1024;
+constexpr int kTileWaves = kTileThreads / kWave;
+constexpr int kTileRun = 8;                   // entries per lane and pass
+constexpr int kTileNone = 0x7fffffff;         // key of a lane without entries
+
+static_assert(kTileMaxRows <= (1 << kTileSlotBits), "slot field too narrow");
+static_assert(kTileSlotBits + kTileColBits <= 32, "packed entry too wide");
+
+struct TileArgs {
+  const float2* X;
+  int n, R, NC;
+  const int* tile_rows;   // [T * R] vertex of each slot, -1 for an unused slot
+  const int* bstart;      // [T * NC + 1] first entry of every block
+  const uint2* ent;       // [nnz]
+  const int* goff;
+  int G;
+  const GraphInfo* gi;
+  const double* zg;
+  const float2* frep;
+  const float2* fent;
+  float lkl4, lc, lr;
+  float2* Gout;
+  float2* Fattr;
+};
+
+// Entries [p0, p1) of wave `wv` in block b, and this lane's run in the first pass.
+struct Piece {
+  int p0, p1;
+  int head;   // slot of a row continued from the previous piece, else -1
+};
+
+__device__ __forceinline__ Piece piece_of(const TileArgs& a, int b, int wv) {
+  const int bs = a.bstart[b], be = a.bstart[b + 1];
+  const int64_t L = be - bs;
+  Piece p;
+  p.p0 = bs + (int)((L * wv) / kTileWaves);
+  p.p1 = bs + (int)((L * (wv + 1)) / kTileWaves);
+  p.head = -1;
+  if (p.p0 > bs && p.p0 < p.p1) {
+    const unsigned s0 = a.ent[p.p0].x >> kTileColBits;
+    const unsigned sm = a.ent[p.p0 - 1].x >> kTileColBits;
+    if (s0 == sm) p.head = (int)s0;
+  }
+  return p;
+}
+
+__device__ __forceinline__ void run_of(int base, int p1, int lane, int& s0, int& cnt) {
+  const int Lp = min(kWave * kTileRun, p1 - base);
+  const int U = (Lp + kWave - 1) / kWave;
+  s0 = base + lane * U;
+  cnt = max(0, min(U, base + Lp - s0));
+}
+
+struct Carry {
+  int row;      // slot carried into the next pass, -1 if none
+  float x, y;
+};
+
+// Adds a finished row sum: into the tile accumulator, or into the wave's
+// parking slot when the row began in the previous wave's piece.
+__device__ __forceinline__ void flush(int row, float x, float y, int head, int wv, float2* acc,
+                                      int* hrow, float2* hval) {
+  if (row == head) {
+    hrow[wv] = row;
+    hval[wv] = make_float2(x, y);
+  } else {
+    float2 v = acc[row];
+    v.x += x;
+    v.y += y;
+    acc[row] = v;
+  }
+}
+
+// One pass over up to 64 * kTileRun consecutive entries of a piece.
+__device__ __forceinline__ void tile_pass(const uint2 (&e)[kTileRun], int cnt, bool more, int lane,
+                                          int wv, int head, const float2* win, const float2* xrow,
+                                          float2* acc, int* hrow, float2* hval, Carry& cr) {
+  int cur = -1, frow = -1;
+  float cx = 0.f, cy = 0.f, fx = 0.f, fy = 0.f;
+  float2 xi = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int k = 0; k < kTileRun; ++k) {
+    if (k < cnt) {
+      const int r = (int)(e[k].x >> kTileColBits);
+      const int lc = (int)(e[k].x & (kTileCols - 1));
+      const float p = __uint_as_float(e[k].y);
+      if (r != cur) {
+        if (cur >= 0) {
+          if (frow < 0) {  // the lane's first run may continue from the lane before
+            frow = cur;
+            fx = cx;
+            fy = cy;
+          } else {         // a run wholly inside this lane
+            flush(cur, cx, cy, head, wv, acc, hrow, hval);
+          }
+        }
+        cur = r;
+        cx = 0.f;
+        cy = 0.f;
+        xi = xrow[r];
+      }
+      const float2 xj = win[lc];
+      const float dx = xi.x - xj.x, dy = xi.y - xj.y;
+      const float w = p * __builtin_amdgcn_rcpf(1.0f + dx * dx + dy * dy);
+      cx += w * dx;
+      cy += w * dy;
+    }
+  }
+  // the last run of every lane: segmented inclusive scan over the lanes
+  const int key = cnt > 0 ? cur : kTileNone;
+  const int first = cnt > 0 ? (frow >= 0 ? frow : cur) : kTileNone;
+  float sx = cx, sy = cy;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int kk = __shfl_up(key, o, kWave);
+    const float ax = __shfl_up(sx, o, kWave), ay = __shfl_up(sy, o, kWave);
+    if (lane >= o && kk == key) {
+      sx += ax;
+      sy += ay;
+    }
+  }
+  if (key == cr.row) {  // lanes continuing the row carried from the previous pass
+    sx += cr.x;
+    sy += cr.y;
+  }
+  int pk = __shfl_up(key, 1, kWave);
+  float px = __shfl_up(sx, 1, kWave), py = __shfl_up(sy, 1, kWave);
+  if (lane == 0) {
+    pk = cr.row;
+    px = cr.x;
+    py = cr.y;
+    if (cr.row >= 0 && first != cr.row) flush(cr.row, cr.x, cr.y, head, wv, acc, hrow, hval);
+  }
+  if (frow >= 0) {  // a lane with several runs: its first run ends here
+    float tx = fx, ty = fy;
+    if (first == pk) {
+      tx += px;
+      ty += py;
+    }
+    flush(frow, tx, ty, head, wv, acc, hrow, hval);
+  }
+  int nf = __shfl_down(first, 1, kWave);
+  const float lx = __shfl(sx, kWave - 1, kWave), ly = __shfl(sy, kWave - 1, kWave);
+  const int lk = __shfl(key, kWave - 1, kWave);
+  if (lane == kWave - 1) nf = more ? -2 : kTileNone;  // -2: the next pass decides
+  if (cnt > 0 && nf != key && nf != -2) flush(key, sx, sy, head, wv, acc, hrow, hval);
+  if (more) {
+    cr.row = lk;
+    cr.x = lx;
+    cr.y = ly;
+  } else {
+    cr.row = -1;
+  }
+}
+
+__global__ __launch_bounds__(kTileThreads) void k_attract_tiled(TileArgs a) {
+  constexpr int PRE = kTileCols / kTileThreads;
+  __shared__ float2 win[kTileCols];
+  __shared__ float2 xrow[kTileMaxRows];
+  __shared__ float2 acc[kTileMaxRows];
+  __shared__ int hrow[kTileWaves];
+  __shared__ float2 hval[kTileWaves];
+  const int t = blockIdx.x, tid = threadIdx.x, lane = lane_id(), wv = wave_id();
+  const int R = a.R, NC = a.NC, n = a.n;
+  for (int s = tid; s < R; s += kTileThreads) {
+    const int i = a.tile_rows[(size_t)t * R + s];
+    xrow[s] = i >= 0 ? a.X[i] : make_float2(0.f, 0.f);
+    acc[s] = make_float2(0.f, 0.f);
+  }
+  if (tid < kTileWaves) hrow[tid] = -1;
+  for (int k = tid; k < kTileCols; k += kTileThreads)
+    win[k] = k < n ? a.X[k] : make_float2(0.f, 0.f);
+  __syncthreads();
+
+  Piece pc = piece_of(a, t * NC, wv);
+  int s0, cnt;
+  run_of(pc.p0, pc.p1, lane, s0, cnt);
+  uint2 ec[kTileRun];
+#pragma unroll
+  for (int k = 0; k < kTileRun; ++k)
+    if (k < cnt) ec[k] = a.ent[s0 + k];
+
+  for (int c = 0; c < NC; ++c) {
+    const bool has_next = c + 1 < NC;
+    // the next window and the next piece's first run are in flight during this one
+    float2 pre[PRE];
+    if (has_next) {
+#pragma unroll
+      for (int q = 0; q < PRE; ++q) {
+        const int j = (c + 1) * kTileCols + q * kTileThreads + tid;
+        pre[q] = j < n ? a.X[j] : make_float2(0.f, 0.f);
+      }
+    }
+    Piece pn{0, 0, -1};
+    int ns0 = 0, ncnt = 0;
+    uint2 en[kTileRun];
+    if (has_next) {
+      pn = piece_of(a, t * NC + c + 1, wv);
+      run_of(pn.p0, pn.p1, lane, ns0, ncnt);
+#pragma unroll
+      for (int k = 0; k < kTileRun; ++k)
+        if (k < ncnt) en[k] = a.ent[ns0 + k];
+    }
+    Carry cr{-1, 0.f, 0.f};
+    if (pc.p0 < pc.p1) {
+      tile_pass(ec, cnt, pc.p0 + kWave * kTileRun < pc.p1, lane, wv, pc.head, win, xrow, acc, hrow,
+                hval, cr);
+      for (int base = pc.p0 + kWave * kTileRun; base < pc.p1; base += kWave * kTileRun) {
+        int s1, c1;
+        run_of(base, pc.p1, lane, s1, c1);
+        uint2 e2[kTileRun];
+#pragma unroll
+        for (int k = 0; k < kTileRun; ++k)
+          if (k < c1) e2[k] = a.ent[s1 + k];
+        tile_pass(e2, c1, base + kWave * kTileRun < pc.p1, lane, wv, pc.head, win, xrow, acc, hrow,
+                  hval, cr);
+      }
+    }
+    __syncthreads();
+    if (wv == 0) {
+      // parked partial sums of rows that span pieces, joined per row in wave order
+      const int r = lane < kTileWaves ? hrow[lane] : -1;
+      float2 v = make_float2(0.f, 0.f);
+      if (r >= 0) v = hval[lane];
+#pragma unroll
+      for (int o = 1; o < kTileWaves; o <<= 1) {
+        const int rr = __shfl_up(r, o, kWave);
+        const float ax = __shfl_up(v.x, o, kWave), ay = __shfl_up(v.y, o, kWave);
+        if (lane >= o && rr == r) {
+          v.x += ax;
+          v.y += ay;
+        }
+      }
+      int nr = __shfl_down(r, 1, kWave);
+      if (lane == kTileWaves - 1) nr = -2;
+      if (lane < kTileWaves && r >= 0 && nr != r) {
+        float2 q = acc[r];
+        q.x += v.x;
+        q.y += v.y;
+        acc[r] = q;
+      }
+      if (lane < kTileWaves) hrow[lane] = -1;
+    }
+    if (has_next) {
+#pragma unroll
+      for (int q = 0; q < PRE; ++q) win[q * kTileThreads + tid] = pre[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kTileRun; ++k) ec[k] = en[k];
+    pc = pn;
+    cnt = ncnt;
+  }
+
+  // assembly of the tile's rows
+  for (int s = tid; s < R; s += kTileThreads) {
+    const int i = a.tile_rows[(size_t)t * R + s];
+    if (i < 0) continue;
+    const float2 f = acc[s], xi = xrow[s];
+    const int g = a.G == 1 ? 0 : graph_of(a.goff, a.G, i);
+    const double Z = a.zg[g];
+    const float inv_z = Z > 0.0 ? (float)(1.0 / Z) : 0.0f;
+    const float2 rp = a.frep[i], en = a.fent[i];
+    const float cn = a.lc * a.gi[g].inv_n, rn = a.lr * a.gi[g].inv_n2;
+    float2 o;
+    o.x = a.lkl4 * (f.x - rp.x * inv_z) + cn * xi.x - rn * en.x;
+    o.y = a.lkl4 * (f.y - rp.y * inv_z) + cn * xi.y - rn * en.y;
+    a.Gout[i] = o;
+    if (a.Fattr) a.Fattr[i] = f;
+  }
+}
+
+hipError_t launch_attract_tiled(Problem& P, const float2* X, const tsnet_params& prm, float2* G,
+                                float2* F_attr, hipStream_t s) {
+  TileArgs a;
+  a.X = X;
+  a.n = P.n;
+  a.R = P.tile_R;
+  a.NC = P.tile_NC;
+  a.tile_rows = P.tile_rows;
+  a.bstart = P.tile_bstart;
+  a.ent = P.tile_ent;
+  a.goff = P.goff_d;
+  a.G = P.G;
+  a.gi = P.ginfo;
+  a.zg = P.zg;
+  a.frep = P.frep;
+  a.fent = P.fent;
+  a.lkl4 = (float)(4.0 * prm.lambda_kl);
+  a.lc = (float)prm.lambda_c;
+  a.lr = (float)prm.lambda_r;
+  a.Gout = G;
+  a.Fattr = F_attr;
+  hipLaunchKernelGGL(k_attract_tiled, dim3(P.tile_T), dim3(kTileThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Layout construction (once per problem).
+
+// keys[e] = (block << kTileSlotBits) | slot of e's row; vals[e] = e.
+__global__ __launch_bounds__(256) void k_tile_keys(const int64_t* __restrict__ rowptr,
+                                                   const int* __restrict__ col,
+                                                   const int* __restrict__ tslot, int n, int R,
+                                                   int NC, unsigned* keys, unsigned* vals) {
+  const int lane = lane_id();
+  for (int i = blockIdx.x * 4 + wave_id(); i < n; i += gridDim.x * 4) {
+    const int ts = tslot[i];
+    const unsigned tile = (unsigned)(ts / R), slot = (unsigned)(ts % R);
+    for (int64_t e = rowptr[i] + lane; e < rowptr[i + 1]; e += kWave) {
+      const unsigned b = tile * (unsigned)NC + ((unsigned)col[e] >> kTileColBits);
+      keys[e] = (b << kTileSlotBits) | slot;
+      vals[e] = (unsigned)e;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_tile_fill(const unsigned* __restrict__ keys,
+                                                   const unsigned* __restrict__ vals,
+                                                   const int* __restrict__ col,
+                                                   const float* __restrict__ val, int nnz,
+                                                   uint2* ent) {
+  for (int p = blockIdx.x * 256 + threadIdx.x; p < nnz; p += gridDim.x * 256) {
+    const unsigned e = vals[p];
+    const unsigned slot = keys[p] & ((1u << kTileSlotBits) - 1u);
+    ent[p] = make_uint2((slot << kTileColBits) | ((unsigned)col[e] & (kTileCols - 1)),
+                        __float_as_uint(val[e]));
+  }
+}
+
+// bstart[b] = first sorted position whose block is >= b, for b in [0, nb].
+__global__ __launch_bounds__(256) void k_tile_bounds(const unsigned* __restrict__ keys, int nnz,
+                                                     int nb, int* bstart) {
+  for (int b = blockIdx.x * 256 + threadIdx.x; b <= nb; b += gridDim.x * 256) {
+    int lo = 0, hi = nnz;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if ((keys[mid] >> kTileSlotBits) < (unsigned)b) lo = mid + 1; else hi = mid;
+    }
+    bstart[b] = lo;
+  }
+}
+
+bool tiles_supported(int n) {
+  const int64_t T = std::max<int64_t>(kTileMinTiles, (n + kTileMaxRows - 1) / kTileMaxRows);
+  const int64_t NC = (n + kTileCols - 1) / kTileCols;
+  return T * NC < ((int64_t)1 << (32 - kTileSlotBits));
+}
+
+int build_tiles(Problem& P, hipStream_t s) {
+  const int n = P.n;
+  const int64_t nnz = P.nnz;
+  if (!tiles_supported(n)) return fail(TSNET_EINVAL, "tiled attraction: too many vertices");
+  const int T = std::max(kTileMinTiles, (n + kTileMaxRows - 1) / kTileMaxRows);
+  const int R = (n + T - 1) / T;
+  const int NC = (n + kTileCols - 1) / kTileCols;
+  const int nb = T * NC;
+  // rows dealt to tiles: snake order over decreasing length
+  std::vector<int64_t> rp(n + 1);
+  TSNET_HIP(hipMemcpyAsync(rp.data(), P.rowptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s));
+  TSNET_HIP(hipStreamSynchronize(s));
+  std::vector<int> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return rp[x + 1] - rp[x] > rp[y + 1] - rp[y];
+  });
+  std::vector<int> tslot(n), rows((size_t)T * R, -1);
+  for (int q = 0; q < n; ++q) {
+    const int round = q / T, idx = q % T;
+    const int tile = (round & 1) ? T - 1 - idx : idx;
+    tslot[order[q]] = tile * R + round;
+    rows[(size_t)tile * R + round] = order[q];
+  }
+  int *rows_d = nullptr, *bstart_d = nullptr, *tslot_d = nullptr;
+  uint2* ent_d = nullptr;
+  unsigned *keys = nullptr, *vals = nullptr, *kt = nullptr, *vt = nullptr;
+  int *hist = nullptr, *tsum = nullptr;
+  const int N = (int)nnz;
+  const int rtiles = (N + kRadixTile - 1) / kRadixTile;
+  const int64_t hist_len = (int64_t)256 * rtiles;
+  const int64_t tsum_len = (hist_len + kTileScan - 1) / kTileScan + 8;
+  auto release = [](std::initializer_list<void*> ps) {
+    for (void* p : ps)
+      if (p) (void)hipFree(p);
+  };
+  auto alloc = [&](auto** p, size_t count, const char* what) -> int {
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(p), count * sizeof(**p));
+    if (e != hipSuccess) {
+      *p = nullptr;
+      return fail(e == hipErrorOutOfMemory ? TSNET_ENOMEM : TSNET_EHIP,
+                  std::string("hipMalloc(") + what + "): " + hipGetErrorString(e));
+    }
+    return TSNET_OK;
+  };
+  int rc;
+  if ((rc = alloc(&rows_d, (size_t)T * R, "tile rows")) ||
+      (rc = alloc(&bstart_d, (size_t)nb + 1, "tile blocks")) ||
+      (rc = alloc(&ent_d, (size_t)nnz, "tile entries")) ||
+      (rc = alloc(&tslot_d, (size_t)n, "tile slots")) || (rc = alloc(&keys, (size_t)nnz, "keys")) ||
+      (rc = alloc(&vals, (size_t)nnz, "vals")) || (rc = alloc(&kt, (size_t)nnz, "keys")) ||
+      (rc = alloc(&vt, (size_t)nnz, "vals")) || (rc = alloc(&hist, (size_t)hist_len + 1, "hist")) ||
+      (rc = alloc(&tsum, (size_t)tsum_len, "scan"))) {
+    release({rows_d, bstart_d, ent_d, tslot_d, keys, vals, kt, vt, hist, tsum});
+    return rc;
+  }
+  hipError_t e = hipMemcpyAsync(rows_d, rows.data(), sizeof(int) * rows.size(),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(tslot_d, tslot.data(), sizeof(int) * n, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    int wb = (n + 3) / 4;
+    if (wb > 16384) wb = 16384;
+    hipLaunchKernelGGL(k_tile_keys, dim3(wb), dim3(256), 0, s, P.rowptr, P.col, tslot_d, n, R, NC,
+                       keys, vals);
+    int bits = kTileSlotBits;
+    while (((int64_t)1 << (bits - kTileSlotBits)) <= nb) ++bits;
+    e = hipGetLastError();
+    if (e == hipSuccess) e = radix_sort(keys, vals, kt, vt, N, bits, hist, tsum, s);
+  }
+  if (e == hipSuccess) {
+    int fb = (int)((nnz + 255) / 256);
+    if (fb > 65536) fb = 65536;
+    if (fb < 1) fb = 1;
+    hipLaunchKernelGGL(k_tile_fill, dim3(fb), dim3(256), 0, s, keys, vals, P.col, P.val, N, ent_d);
+    const int bb = (nb + 1 + 255) / 256;
+    hipLaunchKernelGGL(k_tile_bounds, dim3(bb < 65536 ? bb : 65536), dim3(256), 0, s, keys, N, nb,
+                       bstart_d);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  release({tslot_d, keys, vals, kt, vt, hist, tsum});
+  if (e != hipSuccess) {
+    release({rows_d, bstart_d, ent_d});
+    return fail(TSNET_EHIP, std::string("tiled layout: ") + hipGetErrorString(e));
+  }
+  P.tile_rows = rows_d;
+  P.tile_bstart = bstart_d;
+  P.tile_ent = ent_d;
+  P.tile_T = T;
+  P.tile_R = R;
+  P.tile_NC = NC;
+  return TSNET_OK;
+}
+
+}  // namespace tsnet

@@ -23,6 +23,11 @@ constexpr double kSpanFloor = 1e-4;       // smallest grid span (degenerate layo
 constexpr float kFixScale = 268435456.0f; // 2^28: fixed-point scale of spread contributions
 constexpr int kBinTileH = 2048;           // points per tile of the binning radix sort
 constexpr int kSpreadRange = 256;         // sorted points per wave in the spread
+constexpr int kRadixTile = 2048;          // elements per block tile of the LSD radix sort
+constexpr int kTileMaxRows = 4096;        // rows per row tile of the tiled attraction
+constexpr int kTileSlotBits = 12;         // bits of a row slot inside a tile
+constexpr int kTileMinTiles = 256;        // row tiles (one workgroup each) at least
+constexpr int kTileAutoMinN = 262144;     // automatic layout: tiled from this many vertices
 
 // Output channels of the convolution (charge index in comments):
 //  0 K2*1, 1 K2*x, 2 K2*y, 3 K1*1, 4 Ke*1, 5 Ke*x, 6 Ke*y, 7 Kln*1
@@ -100,6 +105,11 @@ struct Problem {
   int* col = nullptr;
   float* val = nullptr;
   int* row_order = nullptr;           // [n] rows by decreasing length (attraction order)
+  // device: tiled copy of P for the attraction (row tiles x column windows)
+  int tile_T = 0, tile_R = 0, tile_NC = 0;  // row tiles, slots per tile, column windows
+  int* tile_rows = nullptr;           // [T * R] vertex of each slot, -1 if unused
+  int* tile_bstart = nullptr;         // [T * NC + 1] first entry of each block
+  uint2* tile_ent = nullptr;          // [nnz] {slot << 13 | column in window, value bits}
   // device: conditional rows and calibration (absent for host-made P)
   double* beta = nullptr;
   int8_t* rstatus = nullptr;
@@ -167,6 +177,8 @@ hipError_t launch_gather(Problem& P, const float2* X, int with_ln, hipStream_t s
 hipError_t launch_zreduce(Problem& P, double* Z_out, hipStream_t s);
 hipError_t launch_attract(Problem& P, const float2* X, const tsnet_params& prm, float2* G,
                           float2* F_attr, hipStream_t s);
+hipError_t launch_attract_tiled(Problem& P, const float2* X, const tsnet_params& prm, float2* G,
+                                float2* F_attr, hipStream_t s);
 hipError_t launch_step(Problem& P, float2* X, float2* upd, float2* gains, const float2* G,
                        const tsnet_step_params& sp, int iter, hipStream_t s);
 hipError_t launch_cost(Problem& P, const float2* X, const tsnet_params& prm, double* cost,
@@ -175,6 +187,17 @@ hipError_t launch_copy_terms(Problem& P, float2* F_rep, float2* F_ent, float* Z_
 
 // visiting order of the attraction rows (attract.hip), built once per problem
 int build_row_order(Problem& P);
+
+// tiled copy of P for the attraction (tile.hip), built once per problem
+bool tiles_supported(int n);
+int build_tiles(Problem& P, hipStream_t s);
+
+// stable LSD radix sort of (key, value) pairs by the low `bits` key bits, 8-bit
+// digits (build.hip); the result ends in (keys, vals); kt, vt are N-entry
+// ping-pong buffers, hist needs 256 * ceil(N / kRadixTile) + 1 ints, tsum the
+// scan scratch of that length.
+hipError_t radix_sort(unsigned* keys, unsigned* vals, unsigned* kt, unsigned* vt, int N, int bits,
+                      int* hist, int* tsum, hipStream_t s);
 
 // FFT convolution (fft.hip)
 hipError_t launch_fft_conv(Problem& P, float eps, int with_ln, hipStream_t s);

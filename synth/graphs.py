@@ -266,6 +266,32 @@ def initial_layout(n: int, seed: int, std: float = 0.01) -> np.ndarray:
     return rng.normal(0.0, std, size=(n, 2)).astype(np.float32)
 
 
+def random_affinity(n: int, mean_len: float, seed: int, hub_rows: int = 0, hub_len: int = 0,
+                    empty_frac: float = 0.0):
+    """A seeded sparse nonnegative n x n matrix in CSR form for layout-independent
+    tests of the sparse sums: row lengths Poisson(mean_len) (the first
+    ``hub_rows`` rows get ``hub_len`` entries, a fraction ``empty_frac`` of the
+    rest none), columns uniform without the diagonal, sorted and distinct,
+    values uniform in (0.1, 1] scaled to sum 1. Returns (rowptr int64,
+    col int32, val float64)."""
+    rng = np.random.default_rng(seed)
+    lens = rng.poisson(mean_len, size=n).astype(np.int64)
+    lens[:hub_rows] = hub_len
+    if empty_frac > 0:
+        lens[hub_rows:][rng.random(n - hub_rows) < empty_frac] = 0
+    lens = np.minimum(lens, n - 1)
+    rows = np.repeat(np.arange(n, dtype=np.int64), lens)
+    col = rng.integers(0, n - 1, size=rows.shape[0], dtype=np.int64)
+    col += col >= rows                                  # skip the diagonal
+    key = np.unique(rows * n + col)                     # sorted, distinct per row
+    rows, col = key // n, key % n
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=rowptr[1:])
+    val = rng.uniform(0.1, 1.0, size=col.shape[0])
+    val /= val.sum() if val.size else 1.0
+    return rowptr, col.astype(np.int32), val
+
+
 # Named workloads (shapes of the paper's graph families, sizes from the
 # benchmark configurations).
 
