@@ -41,7 +41,7 @@ constexpr int kTileColBits = 13;
 constexpr int kTileCols = 1 << kTileColBits;  // vertices per column window (64 KB of X)
 constexpr int kTileThreads = 1024;
 constexpr int kTileWaves = kTileThreads / kWave;
-constexpr int kTileRun = 8;                   // entries per lane and pass
+constexpr int kTileRun = 6;                   // entries per lane and pass
 constexpr int kTileNone = 0x7fffffff;         // key of a lane without entries
 
 static_assert(kTileMaxRows <= (1 << kTileSlotBits), "slot field too narrow");
@@ -50,6 +50,7 @@ static_assert(kTileSlotBits + kTileColBits <= 32, "packed entry too wide");
 struct TileArgs {
   const float2* X;
   int n, R, NC;
+  int last;               // nnz - 1 (at least 0: the entry array has one element or more)
   const int* tile_rows;   // [T * R] vertex of each slot, -1 for an unused slot
   const int* bstart;      // [T * NC + 1] first entry of every block
   const uint2* ent;       // [nnz]
@@ -64,25 +65,31 @@ struct TileArgs {
   float2* Fattr;
 };
 
-// Entries [p0, p1) of wave `wv` in block b, and this lane's run in the first pass.
+// Entries [p0, p1) of wave `wv` in block b. A row continues from the previous
+// piece when the entries at p0 - 1 and p0 share a slot; both are fetched with
+// the piece (indices clamped into the array, so every load is unconditional
+// and the compiler can keep them in flight) and compared when it is used.
 struct Piece {
-  int p0, p1;
-  int head;   // slot of a row continued from the previous piece, else -1
+  int bs, p0, p1;
+  unsigned at, before;  // packed words of entries p0 and p0 - 1
 };
 
 __device__ __forceinline__ Piece piece_of(const TileArgs& a, int b, int wv) {
   const int bs = a.bstart[b], be = a.bstart[b + 1];
   const int64_t L = be - bs;
   Piece p;
+  p.bs = bs;
   p.p0 = bs + (int)((L * wv) / kTileWaves);
   p.p1 = bs + (int)((L * (wv + 1)) / kTileWaves);
-  p.head = -1;
-  if (p.p0 > bs && p.p0 < p.p1) {
-    const unsigned s0 = a.ent[p.p0].x >> kTileColBits;
-    const unsigned sm = a.ent[p.p0 - 1].x >> kTileColBits;
-    if (s0 == sm) p.head = (int)s0;
-  }
+  p.at = a.ent[min(p.p0, a.last)].x;
+  p.before = a.ent[max(0, min(p.p0 - 1, a.last))].x;
   return p;
+}
+
+// Slot of a row that began in the previous wave's piece, else -1.
+__device__ __forceinline__ int piece_head(const Piece& p) {
+  const unsigned s0 = p.at >> kTileColBits, sm = p.before >> kTileColBits;
+  return p.p0 > p.bs && p.p0 < p.p1 && s0 == sm ? (int)s0 : -1;
 }
 
 __device__ __forceinline__ void run_of(int base, int p1, int lane, int& s0, int& cnt) {
@@ -112,41 +119,53 @@ __device__ __forceinline__ void flush(int row, float x, float y, int head, int w
   }
 }
 
-// One pass over up to 64 * kTileRun consecutive entries of a piece.
+// One pass over up to 64 * kTileRun consecutive entries of a piece. Lane l
+// takes a run of cnt consecutive entries (sorted by slot). Its contributions
+// are summed per slot in order; a slot that starts and ends inside the lane
+// is added to the tile accumulator at once, the lane's first and last slots
+// go through the scan across lanes below.
 __device__ __forceinline__ void tile_pass(const uint2 (&e)[kTileRun], int cnt, bool more, int lane,
                                           int wv, int head, const float2* win, const float2* xrow,
                                           float2* acc, int* hrow, float2* hval, Carry& cr) {
-  int cur = -1, frow = -1;
+  int r[kTileRun];
+  float2 xi[kTileRun], xj[kTileRun];
+#pragma unroll
+  for (int k = 0; k < kTileRun; ++k) {  // all LDS reads in flight together
+    r[k] = (int)(e[k].x >> kTileColBits);
+    xi[k] = xrow[r[k]];
+    xj[k] = win[e[k].x & (kTileCols - 1)];
+  }
+  const int r0 = r[0];
+  int rl = r0;
+#pragma unroll
+  for (int k = 1; k < kTileRun; ++k)
+    if (k < cnt) rl = r[k];
   float cx = 0.f, cy = 0.f, fx = 0.f, fy = 0.f;
-  float2 xi = make_float2(0.f, 0.f);
 #pragma unroll
   for (int k = 0; k < kTileRun; ++k) {
-    if (k < cnt) {
-      const int r = (int)(e[k].x >> kTileColBits);
-      const int lc = (int)(e[k].x & (kTileCols - 1));
-      const float p = __uint_as_float(e[k].y);
-      if (r != cur) {
-        if (cur >= 0) {
-          if (frow < 0) {  // the lane's first run may continue from the lane before
-            frow = cur;
-            fx = cx;
-            fy = cy;
-          } else {         // a run wholly inside this lane
-            flush(cur, cx, cy, head, wv, acc, hrow, hval);
-          }
-        }
-        cur = r;
-        cx = 0.f;
-        cy = 0.f;
-        xi = xrow[r];
-      }
-      const float2 xj = win[lc];
-      const float dx = xi.x - xj.x, dy = xi.y - xj.y;
-      const float w = p * __builtin_amdgcn_rcpf(1.0f + dx * dx + dy * dy);
-      cx += w * dx;
-      cy += w * dy;
+    const float dx = xi[k].x - xj[k].x, dy = xi[k].y - xj[k].y;
+    const float w = __uint_as_float(e[k].y) * __builtin_amdgcn_rcpf(1.0f + dx * dx + dy * dy);
+    const bool valid = k < cnt;
+    const bool same = k > 0 && r[k] == r[k - 1];
+    const float wx = w * dx, wy = w * dy;
+    if (valid) {
+      cx = same ? cx + wx : wx;
+      cy = same ? cy + wy : wy;
+    }
+    const bool ends = valid && (k + 1 >= cnt || (k + 1 < kTileRun && r[k + 1] != r[k]));
+    if (ends && r[k] == r0) {
+      fx = cx;
+      fy = cy;
+    }
+    if (ends && r[k] != r0 && r[k] != rl) {  // a slot wholly inside this lane
+      float2 v = acc[r[k]];
+      v.x += cx;
+      v.y += cy;
+      acc[r[k]] = v;
     }
   }
+  const int frow = cnt > 0 && r0 != rl ? r0 : -1;
+  const int cur = rl;
   // the last run of every lane: segmented inclusive scan over the lanes
   const int key = cnt > 0 ? cur : kTileNone;
   const int first = cnt > 0 ? (frow >= 0 ? frow : cur) : kTileNone;
@@ -214,46 +233,40 @@ __global__ __launch_bounds__(kTileThreads) void k_attract_tiled(TileArgs a) {
   __syncthreads();
 
   Piece pc = piece_of(a, t * NC, wv);
+  int head = piece_head(pc);
   int s0, cnt;
   run_of(pc.p0, pc.p1, lane, s0, cnt);
   uint2 ec[kTileRun];
 #pragma unroll
-  for (int k = 0; k < kTileRun; ++k)
-    if (k < cnt) ec[k] = a.ent[s0 + k];
+  for (int k = 0; k < kTileRun; ++k) ec[k] = a.ent[min(s0 + k, a.last)];
 
   for (int c = 0; c < NC; ++c) {
     const bool has_next = c + 1 < NC;
-    // the next window and the next piece's first run are in flight during this one
+    const int cn = has_next ? c + 1 : c;  // the last window fetches itself again, unused
+    // the next window and the next piece's first run are in flight during this
+    // one; the loads are unconditional (clamped indices) so none of them is
+    // waited for before it is needed
     float2 pre[PRE];
-    if (has_next) {
 #pragma unroll
-      for (int q = 0; q < PRE; ++q) {
-        const int j = (c + 1) * kTileCols + q * kTileThreads + tid;
-        pre[q] = j < n ? a.X[j] : make_float2(0.f, 0.f);
-      }
-    }
-    Piece pn{0, 0, -1};
-    int ns0 = 0, ncnt = 0;
+    for (int q = 0; q < PRE; ++q)
+      pre[q] = a.X[min(cn * kTileCols + q * kTileThreads + tid, n - 1)];
+    const Piece pn = piece_of(a, t * NC + cn, wv);
+    int ns0, ncnt;
+    run_of(pn.p0, pn.p1, lane, ns0, ncnt);
     uint2 en[kTileRun];
-    if (has_next) {
-      pn = piece_of(a, t * NC + c + 1, wv);
-      run_of(pn.p0, pn.p1, lane, ns0, ncnt);
 #pragma unroll
-      for (int k = 0; k < kTileRun; ++k)
-        if (k < ncnt) en[k] = a.ent[ns0 + k];
-    }
+    for (int k = 0; k < kTileRun; ++k) en[k] = a.ent[min(ns0 + k, a.last)];
     Carry cr{-1, 0.f, 0.f};
     if (pc.p0 < pc.p1) {
-      tile_pass(ec, cnt, pc.p0 + kWave * kTileRun < pc.p1, lane, wv, pc.head, win, xrow, acc, hrow,
+      tile_pass(ec, cnt, pc.p0 + kWave * kTileRun < pc.p1, lane, wv, head, win, xrow, acc, hrow,
                 hval, cr);
       for (int base = pc.p0 + kWave * kTileRun; base < pc.p1; base += kWave * kTileRun) {
         int s1, c1;
         run_of(base, pc.p1, lane, s1, c1);
         uint2 e2[kTileRun];
 #pragma unroll
-        for (int k = 0; k < kTileRun; ++k)
-          if (k < c1) e2[k] = a.ent[s1 + k];
-        tile_pass(e2, c1, base + kWave * kTileRun < pc.p1, lane, wv, pc.head, win, xrow, acc, hrow,
+        for (int k = 0; k < kTileRun; ++k) e2[k] = a.ent[min(s1 + k, a.last)];
+        tile_pass(e2, c1, base + kWave * kTileRun < pc.p1, lane, wv, head, win, xrow, acc, hrow,
                   hval, cr);
       }
     }
@@ -290,6 +303,7 @@ __global__ __launch_bounds__(kTileThreads) void k_attract_tiled(TileArgs a) {
 #pragma unroll
     for (int k = 0; k < kTileRun; ++k) ec[k] = en[k];
     pc = pn;
+    head = piece_head(pn);  // the probes have landed by now
     cnt = ncnt;
   }
 
@@ -318,6 +332,7 @@ hipError_t launch_attract_tiled(Problem& P, const float2* X, const tsnet_params&
   a.n = P.n;
   a.R = P.tile_R;
   a.NC = P.tile_NC;
+  a.last = P.nnz > 0 ? (int)(P.nnz - 1) : 0;
   a.tile_rows = P.tile_rows;
   a.bstart = P.tile_bstart;
   a.ent = P.tile_ent;
