@@ -116,7 +116,9 @@ void tsnet_default_step_params(tsnet_step_params* p);
 
 /* Create a context on HIP device `device` (made current for the call). */
 int tsnet_ctx_create(tsnet_ctx* out, int device);
-/* Synchronous; frees everything the context owns. NULL is accepted. */
+/* Synchronous; frees everything the context owns. NULL is accepted.
+ * TSNET_EINVAL (and nothing freed) while a problem made in it is alive:
+ * free every tsnet_P of the context first. */
 int tsnet_ctx_destroy(tsnet_ctx ctx);
 
 /*

@@ -7,6 +7,7 @@ given) torch stream.
 from __future__ import annotations
 
 import ctypes
+import weakref
 from dataclasses import dataclass, fields
 
 import numpy as np
@@ -82,9 +83,13 @@ class Context:
         h = ctypes.c_void_p()
         check(lib.tsnet_ctx_create(ctypes.byref(h), device))
         self.handle = h
+        self._problems = weakref.WeakSet()
 
     def close(self):
+        """Free the problems still alive in this context, then the context."""
         if self.handle:
+            for p in list(self._problems):
+                p.free()
             check(lib.tsnet_ctx_destroy(self.handle))
             self.handle = None
 
@@ -132,6 +137,7 @@ class Problem:
     def __init__(self, ctx: Context, handle: ctypes.c_void_p):
         self.ctx = ctx
         self.handle = handle
+        ctx._problems.add(self)
         n, nnz, G, k = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
         check(lib.tsnet_P_info(handle, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(G),
                                ctypes.byref(k)))

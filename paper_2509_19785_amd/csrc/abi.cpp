@@ -114,6 +114,10 @@ static void free_grid(Problem& P) {
 }
 
 static void free_problem(Problem& P) {
+  if (P.ctx) {
+    --P.ctx->live_problems;
+    P.ctx = nullptr;
+  }
   free_grid(P);
   dfree(P.ginfo);
   dfree(P.goff_d);
@@ -179,6 +183,7 @@ static int check_offsets(int n, const int32_t* goff_host, int G, std::vector<int
 // Graph tables, chunk tables and the per-vertex workspace shared by every problem.
 static int init_problem(Ctx& c, Problem& P, int n, const int32_t* goff_host, int G) {
   P.ctx = &c;
+  ++c.live_problems;
   if (n < 1) return fail(TSNET_EINVAL, "n must be >= 1");
   int rc = check_offsets(n, goff_host, G, P.goff);
   if (rc) return rc;
@@ -300,6 +305,7 @@ static int check_call(tsnet_ctx ctx, tsnet_P P) {
   if (P->p.ctx != &ctx->c) return fail(TSNET_EINVAL, "P belongs to another context");
   if (!P->p.rowptr) return fail(TSNET_EINVAL, "P has no affinities");
   TSNET_HIP(hipSetDevice(ctx->c.device));
+  (void)hipGetLastError();  // launch checks below report only this call's errors
   return TSNET_OK;
 }
 
@@ -440,6 +446,8 @@ int tsnet_ctx_create(tsnet_ctx* out, int device) {
 
 int tsnet_ctx_destroy(tsnet_ctx ctx) {
   if (!ctx) return TSNET_OK;
+  if (ctx->c.live_problems > 0)
+    return fail(TSNET_EINVAL, "the context still owns problems: free them first");
   (void)hipSetDevice(ctx->c.device);
   (void)hipDeviceSynchronize();
   for (auto& p : ctx->c.pending) {

@@ -78,6 +78,7 @@ struct Ctx {
   unsigned* status = nullptr;         // device status word
   int lds_per_block = 65536;
   uint32_t timing = 0;                // bit s: time stage s
+  int live_problems = 0;              // problems made in this context and not yet freed
   std::vector<hipEvent_t> ev_free;    // recycled events
   struct Pending { int stage; hipEvent_t a, b; };
   std::vector<Pending> pending;

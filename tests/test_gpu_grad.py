@@ -260,3 +260,17 @@ def test_direct_f64_matches_oracle(api, ctx, grid_problem, std):
     Gr, Zr = prob.grad_direct_f64(torch.tensor(X, device="cuda"), rows=rows)
     assert abs(Zr.item() - ex.Z[0]) <= 1e-12 * ex.Z[0]
     assert rel_l2(Gr.cpu().numpy(), ex.G[rows]) <= 1e-12
+
+
+def test_context_outlives_its_problems(api):
+    from paper_2509_19785_amd import _lib
+    c = api.Context(0)
+    rowptr, col, val = graphs.random_affinity(50, 3.0, 1)
+    prob = api.Problem.from_host(c, rowptr, col, val.astype(np.float32))
+    assert _lib.lib.tsnet_ctx_destroy(c.handle) == _lib.TSNET_EINVAL
+    assert b"free them first" in _lib.lib.tsnet_last_error()
+    X = torch.zeros(50, 2, device="cuda")
+    prob.grad(X)                      # the context is still intact
+    torch.cuda.synchronize()
+    c.close()                         # frees the problem first
+    assert prob.handle is None and c.handle is None

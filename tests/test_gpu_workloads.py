@@ -1,0 +1,219 @@
+"""GPU parity at the sizes of the benchmark workloads.
+
+Where the oracle cannot run the whole workload, outputs are checked on samples
+it computes one by one, or through properties that hold at any size:
+
+* SBM n = 2e4 (20 blocks of 1000): P bit-exact in support against the oracle's
+  build, and the whole gradient against the exact O(n^2) oracle gradient.
+* Barabasi-Albert n = 1e6 (m0 = 4, seed 3), built on the GPU in the launch
+  configuration of the benchmark:
+  - the selection and hop distances of 64 sampled rows are bit-exact against
+    the oracle's partial BFS;
+  - beta of those rows hits ln u;
+  - P[i, j] for every j the oracle selects from i equals
+    (p_{j|i} + p_{i|j}) / 2n from the oracle's conditional rows;
+  - every stored entry of a sampled row is justified by a selection;
+  - P is symmetric on those rows and sums to 1;
+  - the repulsive and entropy sums and Z_i of 256 sampled vertices match the
+    oracle's exact pair sums, and Z equals the sum of Z_i.
+* A random sparse P with n = 1e6 and hub rows (the tiled attraction at full
+  size): F_attr of 256 sampled rows against the oracle, and the tiled and row
+  layouts against each other on all rows.
+* The mixed batch of 256 graphs (n from 500 to 50000) in one problem: P rows
+  and the gradient of sampled graphs against the oracle run on those graphs.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from helpers import P32, rel_l2, say
+from oracle import affinities, gradient, perplexity
+from oracle.gradient import CostParams
+from synth import graphs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2509_19785_amd import api as a
+    return a
+
+
+@pytest.fixture(scope="module")
+def ctx(api):
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+def _ulps(a32, b64):
+    ai = np.asarray(a32, np.float32).view(np.int32).astype(np.int64)
+    bi = np.asarray(b64).astype(np.float32).view(np.int32).astype(np.int64)
+    return np.abs(ai - bi)
+
+
+def _terms(prob, X, prm):
+    out = prob.grad_terms(X, prm)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+# --------------------------------------------------------------------- SBM 20k
+def test_sbm20k_build_and_gradient(api, ctx):
+    g = graphs.workload_sbm20k()
+    say(f"[workload] SBM n={g.n} m={g.m}: oracle P")
+    oP = affinities.build_P(g.indptr, g.indices, 40.0, seed=1)
+    prob = api.Problem.build(ctx, g.indptr, g.indices, 40.0, seed=1)
+    got = prob.export()
+    assert np.array_equal(got["rowptr"], oP.rowptr)
+    assert np.array_equal(got["col"], oP.col)
+    assert _ulps(got["val"], oP.val).max() <= 4
+    X32 = graphs.initial_layout(g.n, 1, std=3.0)
+    t = _terms(prob, torch.tensor(X32, device="cuda"), api.Params())
+    ex = gradient.grad_terms(X32.astype(np.float64), oP, CostParams())
+    e = rel_l2(t["G"], ex.G)
+    say(f"   gradient rel L2 {e:.2e}, Z {t['Z'][0]:.6e} vs {ex.Z[0]:.6e}")
+    assert e <= 1e-3
+    assert abs(t["Z"][0] - ex.Z[0]) <= 1e-4 * ex.Z[0]
+
+
+# --------------------------------------------------------------------- BA 1e6
+@pytest.fixture(scope="module")
+def ba1m(api, ctx):
+    g = graphs.workload_ba1m()
+    say(f"[workload] BA n={g.n} m={g.m}: GPU build")
+    prob = api.Problem.build(ctx, g.indptr, g.indices, 40.0, seed=3)
+    return g, prob
+
+
+def test_ba1m_build_sampled_rows(api, ba1m):
+    g, prob = ba1m
+    got = prob.export(conditional=True)
+    n, k = g.n, prob.k
+    rng = np.random.default_rng(3)
+    rows = np.concatenate([np.arange(4), rng.choice(n, 60, replace=False)])  # 4 hubs + random
+    ptr, nbr, dist, p, beta, status = affinities.conditional_rows(g.indptr, g.indices, 40.0, seed=3,
+                                                                  rows=rows)
+    u = 40.0
+    for r, i in enumerate(rows):
+        a, b = int(ptr[r]), int(ptr[r + 1])
+        L = b - a
+        assert int(got["cond_len"][i]) == L
+        assert np.array_equal(got["cond_nbr"][i, :L], nbr[a:b]), i
+        assert np.array_equal(got["cond_dist"][i, :L].astype(np.int32), dist[a:b]), i
+        assert int(got["status"][i]) == int(status[r])
+        if status[r] == perplexity.STATUS_OK:
+            lv, ct = perplexity.level_histogram(dist[a:b])
+            deltas = lv.astype(float) ** 2 - float(lv[0]) ** 2
+            assert abs(perplexity.entropy_of_beta(got["beta"][i], deltas, ct) - math.log(u)) <= 1e-12
+    rp, col, val = got["rowptr"], got["col"], got["val"]
+    say(f"   nnz={prob.nnz} sum P={float(val.astype(np.float64).sum()):.9f}")
+    assert abs(float(val.astype(np.float64).sum()) - 1.0) <= 1e-5
+    # values of the selected pairs of 16 non-hub rows, from the oracle's conditional rows
+    for r, i in enumerate(rows[4:20], start=4):
+        a, b = int(ptr[r]), int(ptr[r + 1])
+        js = nbr[a:b].astype(np.int64)
+        jp, jn, jd, jpv, _, _ = affinities.conditional_rows(g.indptr, g.indices, 40.0, seed=3, rows=js)
+        row_c = col[rp[i]:rp[i + 1]]
+        row_v = val[rp[i]:rp[i + 1]]
+        for q, j in enumerate(js):
+            sel = jn[jp[q]:jp[q + 1]]
+            hit = np.nonzero(sel == i)[0]
+            p_ij = (p[a + q] + (jpv[jp[q] + hit[0]] if hit.size else 0.0)) / (2.0 * n)
+            pos = np.searchsorted(row_c, j)
+            assert pos < row_c.size and row_c[pos] == j, (i, j)
+            assert _ulps(row_v[pos], p_ij)[()] <= 4, (i, j, row_v[pos], p_ij)
+        # every stored entry is a selection of i or of j, and P is symmetric there
+        extra = np.setdiff1d(row_c, js)
+        if extra.size:
+            ep, en_, _, _, _, _ = affinities.conditional_rows(g.indptr, g.indices, 40.0, seed=3,
+                                                              rows=extra)
+            for q in range(extra.size):
+                assert i in en_[ep[q]:ep[q + 1]], (i, extra[q])
+        for j, v in zip(row_c, row_v):
+            rc = col[rp[j]:rp[j + 1]]
+            pos = np.searchsorted(rc, i)
+            assert pos < rc.size and rc[pos] == i and val[rp[j] + pos] == v
+
+
+@pytest.mark.parametrize("std", [0.01, 8.0])
+def test_ba1m_repulsion_sampled(api, ba1m, std):
+    g, prob = ba1m
+    X32 = graphs.initial_layout(g.n, 0, std=std)
+    t = _terms(prob, torch.tensor(X32, device="cuda"), api.Params())
+    rows = np.random.default_rng(5).choice(g.n, 256, replace=False)
+    zi, frep, fent = gradient.pair_sums(X32.astype(np.float64), 0.05, rows=rows)
+    e_rep = rel_l2(t["F_rep"][rows], frep)
+    e_ent = rel_l2(t["F_ent"][rows], fent)
+    e_zi = rel_l2(t["Z_i"][rows], zi)
+    z_sum = float(t["Z_i"].astype(np.float64).sum())
+    gi = prob.grid_info()
+    say(f"[workload] BA 1e6 std={std} n_int={int(gi['n_intervals'][0])}: rep {e_rep:.2e} ent {e_ent:.2e}"
+        f" Z_i {e_zi:.2e}; Z {t['Z'][0]:.6e} sum Z_i {z_sum:.6e}")
+    assert e_rep <= 1e-3 and e_ent <= 1e-3 and e_zi <= 1e-3
+    assert abs(t["Z"][0] - z_sum) <= 1e-5 * z_sum
+
+
+# --------------------------------------------------------------------- random 1e6
+def test_random1m_tiled_attraction(api, ctx):
+    n = 1_000_000
+    rowptr, col, val = graphs.random_affinity(n, 60.0, 11, hub_rows=8, hub_len=40000, empty_frac=0.01)
+    say(f"[workload] random P n={n} nnz={col.size}")
+    prob = api.Problem.from_host(ctx, rowptr, col, val.astype(np.float32))
+    X = torch.tensor(graphs.initial_layout(n, 11, std=5.0), device="cuda")
+    prm_t = api.Params(attract_layout=2, max_intervals=64)
+    prm_r = api.Params(attract_layout=1, max_intervals=64)
+    t = _terms(prob, X, prm_t)
+    r = _terms(prob, X, prm_r)
+    e_layouts = rel_l2(t["F_attr"], r["F_attr"])
+    rows = np.concatenate([np.arange(8), np.random.default_rng(11).choice(n, 248, replace=False)])
+
+    class _P:
+        pass
+    Pc = _P()
+    Pc.rowptr, Pc.col, Pc.val = rowptr, col, val
+    fa = gradient.attraction(X.cpu().numpy().astype(np.float64), rowptr, col, P32(Pc).val, rows=rows)
+    e = rel_l2(t["F_attr"][rows], fa)
+    say(f"   sampled F_attr rel L2 {e:.2e}; tiled vs rows {e_layouts:.2e}")
+    assert e <= 1e-6 and e_layouts <= 1e-6
+
+
+# --------------------------------------------------------------------- mixed batch
+def test_mixed256_sampled_graphs(api, ctx):
+    b = graphs.workload_mixed256()
+    off = b.graph_offsets.astype(np.int64)
+    sizes = np.diff(off)
+    say(f"[workload] mixed batch: {b.num_graphs} graphs, n={int(off[-1])}")
+    prob = api.Problem.build(ctx, b.indptr, b.indices, 40.0, seed=4, graph_offsets=off)
+    got = prob.export()
+    X32 = graphs.initial_layout(int(off[-1]), 4, std=2.0)
+    prm = api.Params(max_intervals=128)
+    t = _terms(prob, torch.tensor(X32, device="cuda"), prm)
+    order = np.argsort(sizes, kind="stable")
+    pick = list(order[:4]) + list(np.random.default_rng(4).choice(order[4:40], 2, replace=False))
+    for gid in pick:
+        a, e = int(off[gid]), int(off[gid + 1])
+        ng = e - a
+        ptr, nbr, dist, p, beta, status = affinities.conditional_rows(b.indptr, b.indices, 40.0, seed=4,
+                                                                      rows=np.arange(a, e))
+        rp, cl, vl = affinities.symmetrize(ng, ptr, nbr.astype(np.int64) - a, p, status,
+                                           np.array([0, ng], dtype=np.int64))
+        grp = got["rowptr"][a:e + 1] - got["rowptr"][a]
+        gcl = got["col"][got["rowptr"][a]:got["rowptr"][e]] - a
+        gvl = got["val"][got["rowptr"][a]:got["rowptr"][e]]
+        assert np.array_equal(grp, rp) and np.array_equal(gcl, cl), gid
+        assert _ulps(gvl, vl).max() <= 4, gid
+
+        class _P:
+            pass
+        Pg = _P()
+        Pg.rowptr, Pg.col, Pg.val = rp, cl, vl
+        ex = gradient.grad_terms(X32[a:e].astype(np.float64), Pg, CostParams())
+        eg = rel_l2(t["G"][a:e], ex.G)
+        say(f"   graph {gid} ({b.kinds[gid]}, n={ng}): gradient rel L2 {eg:.2e}")
+        assert eg <= 1e-3
+        assert abs(t["Z"][gid] - ex.Z[0]) <= 1e-4 * ex.Z[0]
