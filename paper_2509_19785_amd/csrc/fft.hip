@@ -22,102 +22,149 @@
 //             (u + i v); the first N_g values of each row, times 1 / M^2, are
 //             the node potentials, stored node-major with 8 channels per node.
 //
-// The transforms are one Stockham autosort FFT over LDS with radix-4 passes,
-// one radix-2 pass when b is odd, and a final radix-3 pass. Each block owns
-// two LDS buffers of kFftElems complex values (48 KB); sequences of length
-// M share a block kFftElems / M at a time.
+// The transforms are Stockham autosort FFTs over LDS (fft_core.h): radix-16
+// passes (the last power-of-two pass 8, 4 or 2) and one radix-12 pass, each
+// butterfly an in-register DFT. Each block owns two padded LDS buffers of
+// kFftElems complex values and the M twiddles of its transform length
+// (copied from the context's table once per block); sequences of length M
+// share a block kFftElems / M at a time.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 
 #include "dev_util.h"
+#include "fft_core.h"
 #include "tsnet_internal.h"
 
 namespace tsnet {
 
-constexpr int kFftElems = kMaxM;              // complex values per LDS buffer
-constexpr int kFftLds = 2 * kFftElems * 8;    // bytes of LDS per FFT block
+constexpr int kFftElems = kMaxM;              // complex values per transform buffer
+constexpr int kFftBuf = kFftElems + kFftElems / 16;  // the same, padded (one spare slot per 16)
+constexpr int kFftLds = (kFftBuf + kFftElems / 4) * 8;  // bytes of LDS per FFT block: buffer + quarter twiddles
 constexpr int kFftThreads = 256;
 constexpr int kPerThread = kFftElems / kFftThreads;  // register slots per thread
 
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+// nb sequences of length L (= 3 * 2^b, nb L <= kFftElems) at a[pad(s L + i)];
+// `b` is the ping-pong buffer; tw holds e^{-2 pi i m / L}, m < L (in LDS).
+// sgn = -1 forward, +1 inverse (unnormalised). Returns the buffer holding the
+// result. Must be reached by every thread of the block.
+// e^{-2 pi i m / L} from the quarter table tq[r] = e^{-2 pi i r / L}, r < L / 4
+// (L a multiple of 4; the one length that is not, L = 6, uses no twiddles).
+__device__ __forceinline__ float2 twq(const float2* tq, int m, int L) {
+  const int q4 = L >> 2;
+  const int q = m / q4, r = m - q * q4;
+  const float2 t = tq[r];
+  const float2 u = (q & 1) ? make_float2(t.y, -t.x) : t;  // times -i for odd q
+  return (q & 2) ? make_float2(-u.x, -u.y) : u;           // times -1 for q >= 2
 }
 
-// nb sequences of length L (= 3 * 2^b, L | kMaxM) starting in `a`; `b` is the
-// ping-pong buffer. sign = -1 forward, +1 inverse (unnormalised). Returns the
-// buffer holding the result. Must be reached by every thread of the block.
-__device__ float2* block_fft(float2* a, float2* b, int nb, int L, const float2* __restrict__ tw,
-                             int sign) {
-  int p2 = L / 3;
-  int Ns = 1;
-  const float s3 = 0.86602540378443864676f * (float)(-sign);  // sin(2 pi / 3) with direction
-  while (Ns < L) {
-    int R;
-    if (p2 >= 4) {
-      R = 4;
-      p2 >>= 2;
-    } else if (p2 == 2) {
-      R = 2;
-      p2 = 1;
-    } else {
-      R = 3;
-    }
-    const int nbut = L / R;
-    const int tstep = kMaxM / (Ns * R);
-    const int total = nb * nbut;
-    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-      const int sq = idx / nbut;
-      const int j = idx - sq * nbut;
-      const float2* in = a + sq * L;
-      float2* out = b + sq * L;
-      const int k = j & (Ns - 1);  // Ns is a power of two before every pass
-      float2 v[4];
+// One Stockham pass of radix R over sub-length NS, in place: every thread
+// reads and transforms its butterflies into registers, the block
+// synchronises, then the results are written back to the same buffer.
+// Index arithmetic as in fft_pass (fft_core.h); where the input stride L/R
+// and the output stride NS are multiples of 16 the padded addresses are a
+// base plus constant offsets.
+template <int R, int L, int NS>
+__device__ __forceinline__ void pass_ip(float2* buf, int nb, const float2* tq, float sgn) {
+  constexpr int nbut = L / R;
+  constexpr int tstep = L / (NS * R);
+  constexpr int BPT = (kFftElems / R + kFftThreads - 1) / kFftThreads;
+  constexpr bool in_lin = nbut % 16 == 0;
+  constexpr bool out_lin = NS % 16 == 0 || (NS == 1 && R == 16);
+  const int total = nb * nbut;
+  float2 v[BPT][R];
+  int ob[BPT];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        if (r < R) {
-          float2 x = in[j + r * nbut];
-          if (r > 0 && k > 0) {
-            float2 w = tw[k * r * tstep];
-            if (sign > 0) w.y = -w.y;
-            x = cmul(x, w);
-          }
-          v[r] = x;
+  for (int u = 0; u < BPT; ++u) {
+    const int idx = threadIdx.x + u * kFftThreads;
+    ob[u] = -1;
+    if (idx < total) {
+      const int sq = idx / nbut, j = idx - sq * nbut, k = j & (NS - 1);
+      const int ib = sq * L + j;
+      if constexpr (in_lin) {
+        const float2* p = buf + fft_pad(ib);
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[u][r] = p[r * (nbut + nbut / 16)];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[u][r] = buf[fft_pad(ib + r * nbut)];
+      }
+      if (k > 0) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          float2 w = twq(tq, k * r * tstep, L);
+          if (sgn > 0.f) w.y = -w.y;
+          v[u][r] = fmulc(v[u][r], w);
         }
       }
-      const int base = (j - k) * R + k;
-      if (R == 4) {
-        const float2 t0 = make_float2(v[0].x + v[2].x, v[0].y + v[2].y);
-        const float2 t1 = make_float2(v[0].x - v[2].x, v[0].y - v[2].y);
-        const float2 t2 = make_float2(v[1].x + v[3].x, v[1].y + v[3].y);
-        float2 t3 = make_float2(v[1].x - v[3].x, v[1].y - v[3].y);
-        // multiply by -i (forward) or +i (inverse)
-        t3 = sign < 0 ? make_float2(t3.y, -t3.x) : make_float2(-t3.y, t3.x);
-        out[base] = make_float2(t0.x + t2.x, t0.y + t2.y);
-        out[base + Ns] = make_float2(t1.x + t3.x, t1.y + t3.y);
-        out[base + 2 * Ns] = make_float2(t0.x - t2.x, t0.y - t2.y);
-        out[base + 3 * Ns] = make_float2(t1.x - t3.x, t1.y - t3.y);
-      } else if (R == 2) {
-        out[base] = make_float2(v[0].x + v[1].x, v[0].y + v[1].y);
-        out[base + Ns] = make_float2(v[0].x - v[1].x, v[0].y - v[1].y);
-      } else {
-        const float2 t1 = make_float2(v[1].x + v[2].x, v[1].y + v[2].y);
-        const float2 t2 = make_float2(v[1].x - v[2].x, v[1].y - v[2].y);
-        const float2 m = make_float2(v[0].x - 0.5f * t1.x, v[0].y - 0.5f * t1.y);
-        // n = sign * i * sin(2pi/3) * t2: forward -i s t2, inverse +i s t2
-        const float2 nn = make_float2(s3 * t2.y, -s3 * t2.x);
-        out[base] = make_float2(v[0].x + t1.x, v[0].y + t1.y);
-        out[base + Ns] = make_float2(m.x + nn.x, m.y + nn.y);
-        out[base + 2 * Ns] = make_float2(m.x - nn.x, m.y - nn.y);
-      }
+      small_dft<R>(v[u], sgn);
+      ob[u] = sq * L + (j - k) * R + k;
     }
-    __syncthreads();
-    float2* t = a;
-    a = b;
-    b = t;
-    Ns *= R;
   }
-  return a;
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < BPT; ++u) {
+    if (ob[u] < 0) continue;
+    if constexpr (out_lin) {
+      float2* p = buf + fft_pad(ob[u]);
+#pragma unroll
+      for (int r = 0; r < R; ++r) p[r * (NS + NS / 16)] = v[u][r];
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[fft_pad(ob[u] + r * NS)] = v[u][r];
+    }
+  }
+  __syncthreads();
+}
+
+// The passes of fft_plan for a length known at compile time.
+template <int L, int NS, int P2>
+struct FftPasses {
+  __device__ __forceinline__ static void run(float2* buf, int nb, const float2* tq, float sgn) {
+    if constexpr (P2 > 1) {
+      constexpr int R = P2 >= 16 ? 16 : P2;
+      pass_ip<R, L, NS>(buf, nb, tq, sgn);
+      FftPasses<L, NS * R, P2 / R>::run(buf, nb, tq, sgn);
+    } else {
+      pass_ip<L / NS, L, NS>(buf, nb, tq, sgn);  // the radix-12 (6, 3) pass
+    }
+  }
+};
+
+// One length per function, not inlined into the callers: the kernels pick
+// the length at run time (it comes from the grid plan on the device), and
+// inlining every length into one body inflates the register allocation.
+template <int L>
+__device__ __noinline__ void fft_len(float2* buf, int nb, const float2* tq, float sgn) {
+  constexpr int p2 = L / 3;
+  constexpr int r3 = p2 >= 4 ? 12 : (p2 == 2 ? 6 : 3);
+  FftPasses<L, 1, p2 / (r3 / 3)>::run(buf, nb, tq, sgn);
+}
+
+// nb sequences of length L (= 6 * 2^a <= kFftElems, nb L <= kFftElems) at
+// buf[pad(s L + i)], transformed in place; tq is the quarter twiddle table
+// of length L in LDS. sgn = -1 forward, +1 inverse (unnormalised). Must be
+// reached by every thread of the block.
+__device__ void block_fft(float2* buf, int nb, int L, const float2* tq, float sgn) {
+  switch (L) {
+    case 3072: fft_len<3072>(buf, nb, tq, sgn); break;
+    case 1536: fft_len<1536>(buf, nb, tq, sgn); break;
+    case 768: fft_len<768>(buf, nb, tq, sgn); break;
+    case 384: fft_len<384>(buf, nb, tq, sgn); break;
+    case 192: fft_len<192>(buf, nb, tq, sgn); break;
+    case 96: fft_len<96>(buf, nb, tq, sgn); break;
+    case 48: fft_len<48>(buf, nb, tq, sgn); break;
+    case 24: fft_len<24>(buf, nb, tq, sgn); break;
+    case 12: fft_len<12>(buf, nb, tq, sgn); break;
+    default: fft_len<6>(buf, nb, tq, sgn); break;
+  }
+}
+
+// The first quarter of the twiddles of length M from the context table
+// (length kMaxM) into LDS.
+__device__ __forceinline__ void load_twiddles(float2* tq, const float2* __restrict__ tw, int M) {
+  const int step = kMaxM / M;
+  for (int m = threadIdx.x; m < (M >> 2); m += blockDim.x) tq[m] = tw[m * step];
 }
 
 struct FftArgs {
@@ -150,7 +197,8 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_fwd(FftArgs A) {
   const GridDesc d = A.desc[g];
   const int M = d.M, ng = d.ng, Mh = M / 2 + 1;
   float2* bufA = lds;
-  float2* bufB = lds + kFftElems;
+  float2* twl = lds + kFftBuf;  // quarter twiddle table
+  load_twiddles(twl, A.tw, M);
   const int S = kFftElems / M;  // sequences per block iteration (>= 1)
   const int nseq = 2 * ng + 2 * Mh;
   const float* ch = A.charges + (size_t)g * A.s_charges;
@@ -185,15 +233,15 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_fwd(FftArgs A) {
           v = make_float2(1.0f / (A.eps + r2), A.with_ln ? logf(A.eps + r2) : 0.f);
         }
       }
-      bufA[idx] = v;
+      bufA[fft_pad(idx)] = v;
     }
     __syncthreads();
-    const float2* res = block_fft(bufA, bufB, ns, M, A.tw, -1);
+    block_fft(bufA, ns, M, twl, -1.f);
+    const float2* res = bufA;
     for (int idx = threadIdx.x; idx < ns * Mh; idx += blockDim.x) {
       const int sl = idx / Mh, k = idx - sl * Mh;
       const int km = k == 0 ? 0 : M - k;
-      const float2* z = res + sl * M;
-      const float2 a = z[k], ar = z[km];
+      const float2 a = res[fft_pad(sl * M + k)], ar = res[fft_pad(sl * M + km)];
       const int sq = s0 + sl;
       if (sq < 2 * ng) {
         const int ry = sq >> 1, part = sq & 1;
@@ -268,7 +316,8 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_cols(FftArgs A) {
   const int M = d.M, ng = d.ng, Mh = M / 2 + 1;
   const int S = kFftElems / M;  // columns per block iteration
   float2* B0 = lds;
-  float2* B1 = lds + kFftElems;
+  float2* twl = lds + kFftBuf;  // quarter twiddle table
+  load_twiddles(twl, A.tw, M);
   const float2* qt = A.qt + (size_t)g * A.s_q;
   const float* kt = A.kt + (size_t)g * A.s_k;
   float2* ot = A.ot + (size_t)g * A.s_o;
@@ -283,14 +332,15 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_cols(FftArgs A) {
         const int col = idx / M, y = idx - col * M;
         const int ry = y < M - y ? y : M - y;
         const size_t o = (size_t)(c0 + col) * Mh + ry;
-        B0[idx] = make_float2(kt[(size_t)(2 * pair) * Mh * Mh + o], kt[(size_t)(2 * pair + 1) * Mh * Mh + o]);
+        B0[fft_pad(idx)] = make_float2(kt[(size_t)(2 * pair) * Mh * Mh + o], kt[(size_t)(2 * pair + 1) * Mh * Mh + o]);
       }
       __syncthreads();
-      const float2* r = block_fft(B0, B1, ncc, M, A.tw, -1);
+      block_fft(B0, ncc, M, twl, -1.f);
+      const float2* r = B0;
 #pragma unroll
       for (int q = 0; q < kPerThread; ++q) {
         const int idx = threadIdx.x + q * kFftThreads;
-        const float2 v = idx < tot ? r[idx] : make_float2(0.f, 0.f);
+        const float2 v = idx < tot ? r[fft_pad(idx)] : make_float2(0.f, 0.f);
         kh[2 * pair][q] = v.x;
         kh[2 * pair + 1][q] = v.y;
       }
@@ -299,15 +349,16 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_cols(FftArgs A) {
     for (int c = 0; c < 3; ++c) {
       for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
         const int col = idx / M, y = idx - col * M;
-        B0[idx] = y < ng ? qt[((size_t)c * Mh + c0 + col) * ng + y] : make_float2(0.f, 0.f);
+        B0[fft_pad(idx)] = y < ng ? qt[((size_t)c * Mh + c0 + col) * ng + y] : make_float2(0.f, 0.f);
       }
       __syncthreads();
-      const float2* Q = block_fft(B0, B1, ncc, M, A.tw, -1);
+      block_fft(B0, ncc, M, twl, -1.f);
+      const float2* Q = B0;
       float2 qh[kPerThread];
 #pragma unroll
       for (int q = 0; q < kPerThread; ++q) {
         const int idx = threadIdx.x + q * kFftThreads;
-        qh[q] = idx < tot ? Q[idx] : make_float2(0.f, 0.f);
+        qh[q] = idx < tot ? Q[fft_pad(idx)] : make_float2(0.f, 0.f);
       }
       __syncthreads();
       const int nout = c == 0 ? nout0 : 2;
@@ -325,14 +376,15 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_cols(FftArgs A) {
           const int idx = threadIdx.x + q * kFftThreads;
           if (idx < tot) {
             const float kv = kk == 0 ? kh[0][q] : (kk == 1 ? kh[1][q] : (kk == 2 ? kh[2][q] : kh[3][q]));
-            B0[idx] = make_float2(kv * qh[q].x, kv * qh[q].y);
+            B0[fft_pad(idx)] = make_float2(kv * qh[q].x, kv * qh[q].y);
           }
         }
         __syncthreads();
-        const float2* r = block_fft(B0, B1, ncc, M, A.tw, +1);
+        block_fft(B0, ncc, M, twl, +1.f);
+        const float2* r = B0;
         for (int idx = threadIdx.x; idx < ncc * ng; idx += blockDim.x) {
           const int col = idx / ng, y = idx - col * ng;
-          ot[((size_t)o * Mh + c0 + col) * ng + y] = r[col * M + y];
+          ot[((size_t)o * Mh + c0 + col) * ng + y] = r[fft_pad(col * M + y)];
         }
         __syncthreads();
       }
@@ -348,7 +400,8 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_inv(FftArgs A) {
   const GridDesc d = A.desc[g];
   const int M = d.M, ng = d.ng, Mh = M / 2 + 1;
   float2* bufA = lds;
-  float2* bufB = lds + kFftElems;
+  float2* twl = lds + kFftBuf;  // quarter twiddle table
+  load_twiddles(twl, A.tw, M);
   const int S = kFftElems / M;
   const int jobs = ng * 4;
   const float2* orr = A.orr + (size_t)g * A.s_o;
@@ -370,15 +423,16 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_inv(FftArgs A) {
         f0.y = -f0.y;
         f1.y = -f1.y;
       }
-      bufA[idx] = make_float2(f0.x - f1.y, f0.y + f1.x);
+      bufA[fft_pad(idx)] = make_float2(f0.x - f1.y, f0.y + f1.x);
     }
     __syncthreads();
-    const float2* res = block_fft(bufA, bufB, nj, M, A.tw, +1);
+    block_fft(bufA, nj, M, twl, +1.f);
+    const float2* res = bufA;
     for (int idx = threadIdx.x; idx < nj * ng; idx += blockDim.x) {
       const int jl = idx / ng, x = idx - jl * ng;
       const int job = j0 + jl;
       const int ry = job >> 2, pr = job & 3;
-      const float2 v = res[jl * M + x];
+      const float2 v = res[fft_pad(jl * M + x)];
       *reinterpret_cast<float2*>(pg + ((size_t)ry * ng + x) * kPotCh + 2 * pr) =
           make_float2(v.x * scale, v.y * scale);
     }
@@ -405,7 +459,7 @@ hipError_t launch_fft_conv(Problem& P, float eps, int with_ln, hipStream_t s) {
   A.s_pot = P.stride_pot;
   A.eps = eps;
   A.with_ln = with_ln;
-  const int bx = P.G >= 64 ? 4 : (P.G >= 8 ? 32 : 512);
+  const int bx = P.G >= 64 ? 4 : (P.G >= 8 ? 32 : 1024);
   const int tb = P.G >= 64 ? 16 : (P.G >= 8 ? 64 : 1024);
   hipLaunchKernelGGL(k_fft_rows_fwd, dim3(bx, P.G), dim3(kFftThreads), kFftLds, s, A);
   hipLaunchKernelGGL(k_fft_transpose, dim3(tb, P.G), dim3(256), 0, s, A, 0);
