@@ -219,8 +219,8 @@ static int init_problem(Ctx& c, Problem& P, int n, const int32_t* goff_host, int
       (rc = dmalloc(&P.keys_tmp, n, "keys")) || (rc = dmalloc(&P.perm_tmp, n, "perm")) ||
       (rc = dmalloc(&P.perm_tmp2, n, "perm")) || (rc = dmalloc(&P.skeys, n, "keys")) ||
       (rc = dmalloc(&P.xs, n, "xs")) ||
-      (rc = dmalloc(&P.bin_hist, (size_t)256 * tiles + 1, "hist")) ||
-      (rc = dmalloc(&P.bin_tsum, (size_t)256 * tiles / 2048 + 8, "hist")) ||
+      (rc = dmalloc(&P.bin_hist, ((size_t)1 << kBinDigitBits) * tiles + 1, "hist")) ||
+      (rc = dmalloc(&P.bin_tsum, ((size_t)1 << kBinDigitBits) * tiles / 2048 + 8, "hist")) ||
       (rc = dmalloc(&P.head_box, ranges, "ranges")) || (rc = dmalloc(&P.tail_box, ranges, "ranges")) ||
       (rc = dmalloc(&P.head_val, ranges * 27, "ranges")) ||
       (rc = dmalloc(&P.tail_val, ranges * 27, "ranges")) ||

@@ -1,7 +1,7 @@
 // Binning of points by interpolation box and the spread to the nodes.
 //
-// Binning: stable LSD radix sort (8-bit digits) of the global box id of every
-// point. Tiles of 2048 points rank their digits in LDS with wave ballots, so
+// Binning: stable LSD radix sort (9-bit digits: two passes cover the 2^18
+// boxes of a 512 x 512 grid) of the global box id of every point. Tiles of 2048 points rank their digits in LDS with wave ballots, so
 // no global atomics are needed and the order is deterministic (by box, then
 // by vertex id). Pass 0 computes the keys from X; the last pass also gathers
 // X into sorted order. box_off[b] is the first sorted slot of box b.
@@ -24,6 +24,8 @@ namespace tsnet {
 
 typedef unsigned long long u64;
 constexpr int kBinTile = 2048;
+constexpr int kDigitBits = kBinDigitBits;
+constexpr int kDigits = 1 << kDigitBits;   // buckets per pass
 
 __device__ __forceinline__ int box_key(const GridDesc& d, float x, float y) {
   int bx, by;
@@ -37,8 +39,8 @@ __global__ __launch_bounds__(256) void k_bin_keys(const float2* __restrict__ X, 
                                                   const int* __restrict__ goff, int G,
                                                   const GridDesc* __restrict__ desc, int* keys,
                                                   int tiles, int* hist) {
-  __shared__ int cnt[256];
-  cnt[threadIdx.x] = 0;
+  __shared__ int cnt[kDigits];
+  for (int q = threadIdx.x; q < kDigits; q += 256) cnt[q] = 0;
   __syncthreads();
   const int base = blockIdx.x * kBinTile;
   for (int q = threadIdx.x; q < kBinTile; q += 256) {
@@ -48,25 +50,25 @@ __global__ __launch_bounds__(256) void k_bin_keys(const float2* __restrict__ X, 
       const float2 p = X[i];
       const int key = box_key(desc[g], p.x, p.y);
       keys[i] = key;
-      atomicAdd(&cnt[key & 255], 1);
+      atomicAdd(&cnt[key & (kDigits - 1)], 1);
     }
   }
   __syncthreads();
-  hist[threadIdx.x * tiles + blockIdx.x] = cnt[threadIdx.x];
+  for (int q = threadIdx.x; q < kDigits; q += 256) hist[q * tiles + blockIdx.x] = cnt[q];
 }
 
 __global__ __launch_bounds__(256) void k_bin_hist(const int* __restrict__ keys, int n, int shift,
                                                   int tiles, int* hist) {
-  __shared__ int cnt[256];
-  cnt[threadIdx.x] = 0;
+  __shared__ int cnt[kDigits];
+  for (int q = threadIdx.x; q < kDigits; q += 256) cnt[q] = 0;
   __syncthreads();
   const int base = blockIdx.x * kBinTile;
   for (int q = threadIdx.x; q < kBinTile; q += 256) {
     const int i = base + q;
-    if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255], 1);
+    if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & (kDigits - 1)], 1);
   }
   __syncthreads();
-  hist[threadIdx.x * tiles + blockIdx.x] = cnt[threadIdx.x];
+  for (int q = threadIdx.x; q < kDigits; q += 256) hist[q * tiles + blockIdx.x] = cnt[q];
 }
 
 // Stable scatter of one pass. vin == nullptr means the payload is the index.
@@ -76,11 +78,13 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const int* __restrict__ kin
                                                      int tiles, const int* __restrict__ offs,
                                                      int* kout, int* vout,
                                                      const float2* __restrict__ X, float2* Xs) {
-  __shared__ int run[256];
-  __shared__ int wc[4][256];
+  __shared__ int run[kDigits];
+  __shared__ int wc[4][kDigits];
   const int tid = threadIdx.x, w = wave_id(), lane = lane_id();
-  run[tid] = offs[tid * tiles + blockIdx.x];
-  for (int q = 0; q < 4; ++q) wc[q][tid] = 0;
+  for (int d = tid; d < kDigits; d += 256) {
+    run[d] = offs[d * tiles + blockIdx.x];
+    for (int q = 0; q < 4; ++q) wc[q][d] = 0;
+  }
   __syncthreads();
   const u64 lt = (1ull << lane) - 1ull;
   const int base = blockIdx.x * kBinTile;
@@ -91,12 +95,12 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const int* __restrict__ kin
     if (valid) {
       key = kin[i];
       val = vin ? vin[i] : i;
-      dg = (key >> shift) & 255;
+      dg = (key >> shift) & (kDigits - 1);
     }
     const u64 vb = __ballot(valid);
     u64 peers = valid ? vb : ~vb;
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
+    for (int b = 0; b < kDigitBits; ++b) {
       const bool bit = (dg >> b) & 1;
       const u64 bb = __ballot(bit);
       peers &= bit ? bb : ~bb;
@@ -112,8 +116,10 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const int* __restrict__ kin
       if (Xs) Xs[pos] = X[val];
     }
     __syncthreads();
-    run[tid] += wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
-    for (int q = 0; q < 4; ++q) wc[q][tid] = 0;
+    for (int d = tid; d < kDigits; d += 256) {
+      run[d] += wc[0][d] + wc[1][d] + wc[2][d] + wc[3][d];
+      for (int q = 0; q < 4; ++q) wc[q][d] = 0;
+    }
     __syncthreads();
   }
 }
@@ -138,7 +144,7 @@ hipError_t launch_bin(Problem& P, const float2* X, hipStream_t s) {
   const int tiles = (n + kBinTile - 1) / kBinTile;
   int bits = 1;
   while (((int64_t)1 << bits) < (int64_t)P.G * P.cap * P.cap) ++bits;
-  const int passes = (bits + 7) / 8;
+  const int passes = (bits + kDigitBits - 1) / kDigitBits;
   // pass p reads (kin, vin) and writes the final pair on the last pass, else
   // alternates between (keys_tmp, perm_tmp) and (keys, perm_tmp2); keys is
   // free once pass 0 has read it.
@@ -147,10 +153,10 @@ hipError_t launch_bin(Problem& P, const float2* X, hipStream_t s) {
   hipLaunchKernelGGL(k_bin_keys, dim3(tiles), dim3(256), 0, s, X, n, P.goff_d, P.G, P.desc, P.keys,
                      tiles, P.bin_hist);
   for (int p = 0; p < passes; ++p) {
-    const int shift = 8 * p;
+    const int shift = kDigitBits * p;
     if (p > 0)
       hipLaunchKernelGGL(k_bin_hist, dim3(tiles), dim3(256), 0, s, kin, n, shift, tiles, P.bin_hist);
-    hipError_t e = exclusive_scan<int>(P.bin_hist, (int64_t)256 * tiles, P.bin_hist, P.bin_tsum, s);
+    hipError_t e = exclusive_scan<int>(P.bin_hist, (int64_t)kDigits * tiles, P.bin_hist, P.bin_tsum, s);
     if (e != hipSuccess) return e;
     const bool last = p == passes - 1;
     int *kout, *vout;
@@ -305,15 +311,17 @@ __global__ __launch_bounds__(256) void k_spread_ranges(
   }
 }
 
+// Phase 2, one thread per box: empty boxes get zero nodes, boxes whose points
+// span several ranges add up the head and tail partials of those ranges (in
+// range order; integer sums, so the order does not matter anyway). Boxes
+// that phase 1 wrote whole are skipped.
 __global__ __launch_bounds__(256) void k_spread_boxes(
     const int* __restrict__ box_off, const int* __restrict__ btotal,
     const GridDesc* __restrict__ desc, int G, float* charges, size_t stride,
     const int* __restrict__ head_box, const int* __restrict__ tail_box,
     const long long* __restrict__ head_val, const long long* __restrict__ tail_val) {
   const int B = *btotal;
-  const int lane = lane_id();
-  const int nw = blockDim.x / kWave;
-  for (int b = blockIdx.x * nw + wave_id(); b < B; b += gridDim.x * nw) {
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x) {
     const int bs = box_off[b], be = box_off[b + 1];
     const int r0 = bs / kRange, r1 = (be - 1) / kRange;
     if (be > bs && r0 == r1) continue;  // written whole by phase 1
@@ -325,16 +333,14 @@ __global__ __launch_bounds__(256) void k_spread_boxes(
 #pragma unroll
     for (int q = 0; q < kVals; ++q) acc[q] = 0;
     if (be > bs) {
-      for (int r = r0 + lane; r <= r1; r += kWave) {
+      for (int r = r0; r <= r1; ++r) {
         const long long* src = head_box[r] == b ? head_val + (size_t)r * kVals
                                                  : tail_val + (size_t)r * kVals;
 #pragma unroll
         for (int q = 0; q < kVals; ++q) acc[q] += src[q];
       }
-#pragma unroll
-      for (int q = 0; q < kVals; ++q) acc[q] = wave_sum(acc[q]);
     }
-    if (lane == 0) node_store(charges + (size_t)g * stride, d.ng, bx, by, acc);
+    node_store(charges + (size_t)g * stride, d.ng, bx, by, acc);
   }
 }
 
@@ -346,8 +352,8 @@ hipError_t launch_spread(Problem& P, const float2* X, hipStream_t s) {
   hipLaunchKernelGGL(k_spread_ranges, dim3(blocks), dim3(256), 0, s, P.xs, P.skeys, P.n, P.box_off,
                      P.desc, P.G, P.charges, P.stride_charges, P.head_box, P.tail_box, P.head_val,
                      P.tail_val);
-  int bblocks = (P.G * P.cap * P.cap + 3) / 4;
-  if (bblocks > 4096) bblocks = 4096;
+  int bblocks = (P.G * P.cap * P.cap + 255) / 256;
+  if (bblocks > 8192) bblocks = 8192;
   hipLaunchKernelGGL(k_spread_boxes, dim3(bblocks), dim3(256), 0, s, P.box_off, P.btotal, P.desc,
                      P.G, P.charges, P.stride_charges, P.head_box, P.tail_box, P.head_val,
                      P.tail_val);

@@ -22,6 +22,7 @@ constexpr int kMaxK = 1024;               // neighbours per vertex in tsnet_buil
 constexpr double kSpanFloor = 1e-4;       // smallest grid span (degenerate layouts)
 constexpr float kFixScale = 268435456.0f; // 2^28: fixed-point scale of spread contributions
 constexpr int kBinTileH = 2048;           // points per tile of the binning radix sort
+constexpr int kBinDigitBits = 9;          // digit width of the binning radix sort
 constexpr int kSpreadRange = 256;         // sorted points per wave in the spread
 constexpr int kRadixTile = 2048;          // elements per block tile of the LSD radix sort
 constexpr int kTileMaxRows = 4096;        // rows per row tile of the tiled attraction
