@@ -88,6 +88,10 @@ def main():
     ap.add_argument("--direct-iters", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-intervals", type=int, default=512)
+    ap.add_argument("--graph-steps", type=int, default=0,
+                    help="iterations per captured HIP graph in the timed region (0: plain launches; "
+                         "graph replays measured slower than plain launches on ROCm 7, and event "
+                         "times read from graph nodes are not usable)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 5 device copies of 1 GiB (reference for the HBM traffic counters)")
     args = ap.parse_args()
@@ -151,15 +155,47 @@ def main():
     log(f"warmup done, status {ctx.status():#x}")
 
     # timed region: events only around the dominant kernel
-    ctx.set_timing(["attract_assemble"])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for it in range(args.warmup, args.warmup + args.steps):
-        one(it)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    st = ctx.stage_times()
-    ctx.set_timing(None)
+    K = args.graph_steps
+    graphs_used = K > 0
+    if graphs_used:
+        # events for the graphs come from the context's pool: fill it with
+        # gradient evaluations on a scratch copy (the trajectory is untouched)
+        Xs, Gs, Zs = X.clone(), torch.empty_like(X), torch.empty_like(Z)
+        ctx.set_timing(["attract_assemble"])
+        for _ in range(2 * K + 2):
+            prob.grad(Xs, prm, G=Gs, Z=Zs)
+        torch.cuda.synchronize()
+        ctx.stage_times()
+        del Xs, Gs, Zs
+        sw = sp.momentum_switch_iter
+        g_early = api.StepGraph(prob, X, upd, gains, G, Z, prm, sp, 0, K)
+        g_late = api.StepGraph(prob, X, upd, gains, G, Z, prm, sp, sw, K)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it = args.warmup
+        end = args.warmup + args.steps
+        while it < end:
+            if it + K <= end and (it + K <= sw or it >= sw):
+                (g_early if it < sw else g_late).replay()
+                it += K
+            else:  # a block that straddles the momentum switch or the end
+                one(it)
+                it += 1
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = ctx.stage_times()  # the events in the graphs hold their last replay
+        ctx.set_timing(None)
+        del g_early, g_late
+    else:
+        ctx.set_timing(["attract_assemble"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for it in range(args.warmup, args.warmup + args.steps):
+            one(it)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = ctx.stage_times()
+        ctx.set_timing(None)
     ms_per_step = wall / args.steps * 1e3
     iters_per_s = args.steps / wall
     attr_ms, attr_calls = st["attract_assemble"]
@@ -167,7 +203,8 @@ def main():
     n, nnz = prob.n, prob.nnz
     attr_bytes = 8 * nnz + 8 * (n + 1) + 8 * n + 16 * n + 8 * n
     achieved = attr_bytes / attr_avg_s / 1e9
-    log(f"timed: {ms_per_step:.4f} ms/step, {iters_per_s:.1f} iters/s; attract {attr_avg_s * 1e6:.1f} us "
+    log(f"timed ({'graphs of ' + str(K) if graphs_used else 'plain launches'}): {ms_per_step:.4f} ms/step, "
+        f"{iters_per_s:.1f} iters/s; attract {attr_avg_s * 1e6:.1f} us over {attr_calls} launches "
         f"-> {achieved:.0f} GB/s")
 
     # stage breakdown (separate short run, every stage bracketed)
@@ -231,6 +268,7 @@ def main():
             "init": "N(0,1e-4) seed 0", "interval_width": prm.interval_width,
             "min_intervals": prm.min_intervals, "max_intervals": prm.max_intervals,
             "n_intervals_end": int(gi["n_intervals"][0]), "span_end": span,
+            "launch": f"HIP graphs of {K} iterations" if graphs_used else "plain launches",
         },
         "roofline": {
             "bound": "hbm",
@@ -242,6 +280,7 @@ def main():
             "traffic": None,
             "algorithmic_bytes": attr_bytes,
             "avg_launch_us": attr_avg_s * 1e6,
+            "launches_timed": attr_calls,
         },
         "cpu_baseline": cpu,
         "build_P_ms": build_ms,

@@ -287,3 +287,34 @@ class Problem:
                                         None if rows is None else rows.data_ptr(), nr,
                                         None if T is None else T.data_ptr(), _stream(stream)))
         return (G, Z, T) if with_terms else (G, Z)
+
+
+class StepGraph:
+    """k iterations of (gradient, step) recorded once as a HIP graph and replayed.
+
+    The library's calls only enqueue kernels on the given stream, so a stream
+    capture records them as they are (torch.cuda.CUDAGraph is HIP's graph on
+    ROCm). Everything is fixed at capture: the buffers, the parameters and the
+    iteration numbers first_iter .. first_iter + k - 1 (they select the
+    momentum of the step). Run every call once before capturing (the first
+    gradient sizes the evaluation workspace). Stage timing that is on during
+    the capture is recorded into the graph: each replay re-records the same
+    events, so the stage times read afterwards are those of the last replay.
+    """
+
+    def __init__(self, problem: Problem, X, update, gains, G, Z, params: Params,
+                 step_params: StepParams, first_iter: int, k: int):
+        self.k = k
+        self.first_iter = first_iter
+        s = torch.cuda.Stream(device=X.device)
+        s.wait_stream(torch.cuda.current_stream(X.device))
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(self.graph, stream=s):
+                for t in range(k):
+                    problem.grad(X, params, G=G, Z=Z, stream=s)
+                    problem.step(X, update, gains, G, first_iter + t, step_params, stream=s)
+        torch.cuda.current_stream(X.device).wait_stream(s)
+
+    def replay(self):
+        self.graph.replay()
