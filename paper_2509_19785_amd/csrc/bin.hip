@@ -311,36 +311,81 @@ __global__ __launch_bounds__(256) void k_spread_ranges(
   }
 }
 
-// Phase 2, one thread per box: empty boxes get zero nodes, boxes whose points
-// span several ranges add up the head and tail partials of those ranges (in
-// range order; integer sums, so the order does not matter anyway). Boxes
-// that phase 1 wrote whole are skipped.
+// Phase 2: empty boxes get zero nodes, boxes whose points span several
+// ranges add up the head and tail partials of those ranges (integer sums, so
+// the order does not matter). Boxes that phase 1 wrote whole are skipped.
+// One thread per box; a box spanning more than kDenseRanges ranges (a dense
+// cluster of points) is summed by its whole wave instead, lanes over ranges.
+constexpr int kDenseRanges = 4;
+
+__device__ __forceinline__ const long long* partial_of(int r, int b, const int* head_box,
+                                                       const long long* head_val,
+                                                       const long long* tail_val) {
+  return head_box[r] == b ? head_val + (size_t)r * kVals : tail_val + (size_t)r * kVals;
+}
+
 __global__ __launch_bounds__(256) void k_spread_boxes(
     const int* __restrict__ box_off, const int* __restrict__ btotal,
     const GridDesc* __restrict__ desc, int G, float* charges, size_t stride,
     const int* __restrict__ head_box, const int* __restrict__ tail_box,
     const long long* __restrict__ head_val, const long long* __restrict__ tail_val) {
   const int B = *btotal;
-  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x) {
-    const int bs = box_off[b], be = box_off[b + 1];
-    const int r0 = bs / kRange, r1 = (be - 1) / kRange;
-    if (be > bs && r0 == r1) continue;  // written whole by phase 1
-    const int g = G == 1 ? 0 : graph_of_box(desc, G, b);
-    const GridDesc d = desc[g];
-    const int local = b - d.box_base;
-    const int by = local / d.n_int, bx = local - by * d.n_int;
-    long long acc[kVals];
+  const int lane = lane_id();
+  const int nwaves = gridDim.x * (blockDim.x / kWave);
+  // every lane of a wave runs the same number of rounds (ballots below)
+  for (int base = (blockIdx.x * (blockDim.x / kWave) + wave_id()) * kWave; base < B;
+       base += nwaves * kWave) {
+    const int b = base + lane;
+    int r0 = 0, r1 = -1, bs = 0, be = 0;
+    if (b < B) {
+      bs = box_off[b];
+      be = box_off[b + 1];
+      if (be > bs) {
+        r0 = bs / kRange;
+        r1 = (be - 1) / kRange;
+      }
+    }
+    const bool mine = b < B && !(be > bs && r0 == r1);  // not written whole by phase 1
+    const bool dense = mine && r1 - r0 >= kDenseRanges;
+    if (mine && !dense) {
+      long long acc[kVals];
 #pragma unroll
-    for (int q = 0; q < kVals; ++q) acc[q] = 0;
-    if (be > bs) {
+      for (int q = 0; q < kVals; ++q) acc[q] = 0;
       for (int r = r0; r <= r1; ++r) {
-        const long long* src = head_box[r] == b ? head_val + (size_t)r * kVals
-                                                 : tail_val + (size_t)r * kVals;
+        const long long* src = partial_of(r, b, head_box, head_val, tail_val);
 #pragma unroll
         for (int q = 0; q < kVals; ++q) acc[q] += src[q];
       }
+      const int g = G == 1 ? 0 : graph_of_box(desc, G, b);
+      const GridDesc d = desc[g];
+      const int local = b - d.box_base;
+      const int by = local / d.n_int, bx = local - by * d.n_int;
+      node_store(charges + (size_t)g * stride, d.ng, bx, by, acc);
     }
-    node_store(charges + (size_t)g * stride, d.ng, bx, by, acc);
+    u64 todo = __ballot(dense);
+    while (todo) {
+      const int src_lane = __ffsll((long long)todo) - 1;
+      todo &= todo - 1;
+      const int bd = __shfl(b, src_lane, kWave);
+      const int d0 = __shfl(r0, src_lane, kWave), d1 = __shfl(r1, src_lane, kWave);
+      long long acc[kVals];
+#pragma unroll
+      for (int q = 0; q < kVals; ++q) acc[q] = 0;
+      for (int r = d0 + lane; r <= d1; r += kWave) {
+        const long long* src = partial_of(r, bd, head_box, head_val, tail_val);
+#pragma unroll
+        for (int q = 0; q < kVals; ++q) acc[q] += src[q];
+      }
+#pragma unroll
+      for (int q = 0; q < kVals; ++q) acc[q] = wave_sum(acc[q]);
+      if (lane == 0) {
+        const int g = G == 1 ? 0 : graph_of_box(desc, G, bd);
+        const GridDesc d = desc[g];
+        const int local = bd - d.box_base;
+        const int by = local / d.n_int, bx = local - by * d.n_int;
+        node_store(charges + (size_t)g * stride, d.ng, bx, by, acc);
+      }
+    }
   }
 }
 
