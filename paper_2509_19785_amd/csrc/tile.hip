@@ -119,6 +119,40 @@ __device__ __forceinline__ void flush(int row, float x, float y, int head, int w
   }
 }
 
+// Cross-lane moves of the scan below as DPP operand modifiers (VALU, no LDS
+// traffic). Controls: row_shr:n shifts within rows of 16 lanes, row_bcast:15
+// and :31 carry the last lane of a row (of rows 0-1) into the next row (rows
+// 2-3), wave_shr:1 / wave_shl:1 shift by one lane across the whole wave.
+// Lanes without a source keep `old`.
+constexpr int kDppRowShr = 0x110;
+constexpr int kDppRowBcast15 = 0x142;
+constexpr int kDppRowBcast31 = 0x143;
+constexpr int kDppWaveShl1 = 0x130;
+constexpr int kDppWaveShr1 = 0x138;
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_i(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_f(float old, float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL,
+                                                    ROWS, 0xF, false));
+}
+
+// One step of the segmented inclusive scan: add the partial sums that the
+// move brings in when they belong to the same slot (keys are sorted along
+// the wave, so equal end points mean one segment).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void seg_step(int key, float& sx, float& sy) {
+  const int kk = dpp_i<CTRL, ROWS>(kTileNone - 1, key);
+  const float ax = dpp_f<CTRL, ROWS>(0.f, sx), ay = dpp_f<CTRL, ROWS>(0.f, sy);
+  if (kk == key) {
+    sx += ax;
+    sy += ay;
+  }
+}
+
 // One pass over up to 64 * kTileRun consecutive entries of a piece. Lane l
 // takes a run of cnt consecutive entries (sorted by slot). Its contributions
 // are summed per slot in order; a slot that starts and ends inside the lane
@@ -170,21 +204,18 @@ __device__ __forceinline__ void tile_pass(const uint2 (&e)[kTileRun], int cnt, b
   const int key = cnt > 0 ? cur : kTileNone;
   const int first = cnt > 0 ? (frow >= 0 ? frow : cur) : kTileNone;
   float sx = cx, sy = cy;
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const int kk = __shfl_up(key, o, kWave);
-    const float ax = __shfl_up(sx, o, kWave), ay = __shfl_up(sy, o, kWave);
-    if (lane >= o && kk == key) {
-      sx += ax;
-      sy += ay;
-    }
-  }
+  seg_step<kDppRowShr | 1, 0xF>(key, sx, sy);
+  seg_step<kDppRowShr | 2, 0xF>(key, sx, sy);
+  seg_step<kDppRowShr | 4, 0xF>(key, sx, sy);
+  seg_step<kDppRowShr | 8, 0xF>(key, sx, sy);
+  seg_step<kDppRowBcast15, 0xA>(key, sx, sy);
+  seg_step<kDppRowBcast31, 0xC>(key, sx, sy);
   if (key == cr.row) {  // lanes continuing the row carried from the previous pass
     sx += cr.x;
     sy += cr.y;
   }
-  int pk = __shfl_up(key, 1, kWave);
-  float px = __shfl_up(sx, 1, kWave), py = __shfl_up(sy, 1, kWave);
+  int pk = dpp_i<kDppWaveShr1, 0xF>(kTileNone - 1, key);
+  float px = dpp_f<kDppWaveShr1, 0xF>(0.f, sx), py = dpp_f<kDppWaveShr1, 0xF>(0.f, sy);
   if (lane == 0) {
     pk = cr.row;
     px = cr.x;
@@ -199,9 +230,10 @@ __device__ __forceinline__ void tile_pass(const uint2 (&e)[kTileRun], int cnt, b
     }
     flush(frow, tx, ty, head, wv, acc, hrow, hval);
   }
-  int nf = __shfl_down(first, 1, kWave);
-  const float lx = __shfl(sx, kWave - 1, kWave), ly = __shfl(sy, kWave - 1, kWave);
-  const int lk = __shfl(key, kWave - 1, kWave);
+  int nf = dpp_i<kDppWaveShl1, 0xF>(kTileNone, first);
+  const float lx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sx), kWave - 1));
+  const float ly = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sy), kWave - 1));
+  const int lk = __builtin_amdgcn_readlane(key, kWave - 1);
   if (lane == kWave - 1) nf = more ? -2 : kTileNone;  // -2: the next pass decides
   if (cnt > 0 && nf != key && nf != -2) flush(key, sx, sy, head, wv, acc, hrow, hval);
   if (more) {
