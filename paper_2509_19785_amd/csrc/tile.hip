@@ -119,12 +119,13 @@ __device__ __forceinline__ void flush(int row, float x, float y, int head, int w
   }
 }
 
-// Cross-lane moves of the scan below as DPP operand modifiers (VALU, no LDS
-// traffic). Controls: row_shr:n shifts within rows of 16 lanes, row_bcast:15
+// Cross-lane moves of the scans below as DPP operand modifiers (VALU, no LDS
+// traffic). Controls: row_shr:n / row_shl:n shift within rows of 16 lanes, row_bcast:15
 // and :31 carry the last lane of a row (of rows 0-1) into the next row (rows
 // 2-3), wave_shr:1 / wave_shl:1 shift by one lane across the whole wave.
 // Lanes without a source keep `old`.
 constexpr int kDppRowShr = 0x110;
+constexpr int kDppRowShl1 = 0x101;
 constexpr int kDppRowBcast15 = 0x142;
 constexpr int kDppRowBcast31 = 0x143;
 constexpr int kDppWaveShl1 = 0x130;
@@ -305,19 +306,17 @@ __global__ __launch_bounds__(kTileThreads) void k_attract_tiled(TileArgs a) {
     __syncthreads();
     if (wv == 0) {
       // parked partial sums of rows that span pieces, joined per row in wave order
+      // (the 16 slots sit in the first row of 16 lanes: row shifts suffice)
+      static_assert(kTileWaves == 16, "one DPP row of parking slots");
       const int r = lane < kTileWaves ? hrow[lane] : -1;
       float2 v = make_float2(0.f, 0.f);
       if (r >= 0) v = hval[lane];
-#pragma unroll
-      for (int o = 1; o < kTileWaves; o <<= 1) {
-        const int rr = __shfl_up(r, o, kWave);
-        const float ax = __shfl_up(v.x, o, kWave), ay = __shfl_up(v.y, o, kWave);
-        if (lane >= o && rr == r) {
-          v.x += ax;
-          v.y += ay;
-        }
-      }
-      int nr = __shfl_down(r, 1, kWave);
+      // slots of no row hold -1 and add zeros among themselves
+      seg_step<kDppRowShr | 1, 0xF>(r, v.x, v.y);
+      seg_step<kDppRowShr | 2, 0xF>(r, v.x, v.y);
+      seg_step<kDppRowShr | 4, 0xF>(r, v.x, v.y);
+      seg_step<kDppRowShr | 8, 0xF>(r, v.x, v.y);
+      int nr = dpp_i<kDppRowShl1, 0xF>(-2, r);
       if (lane == kTileWaves - 1) nr = -2;
       if (lane < kTileWaves && r >= 0 && nr != r) {
         float2 q = acc[r];
