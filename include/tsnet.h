@@ -239,7 +239,8 @@ int tsnet_status(tsnet_ctx ctx, uint32_t* flags_host);
  * call's stream; 0 turns timing off. tsnet_stage_times (synchronous) returns
  * accumulated milliseconds and call counts per stage ([tsnet_stage_count()]
  * host arrays, either may be NULL) and resets them; names via
- * tsnet_stage_name.
+ * tsnet_stage_name. The Z reduction runs inside the gather kernel, so the
+ * "z_reduce" stage (kept so stage ids stay stable) records no calls.
  */
 int tsnet_set_timing(tsnet_ctx ctx, uint32_t stage_mask);
 int tsnet_stage_count(void);

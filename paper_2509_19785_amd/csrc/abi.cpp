@@ -154,8 +154,7 @@ static void free_problem(Problem& P) {
   dfree(P.head_val);
   dfree(P.tail_val);
   dfree(P.row_order);
-  dfree(P.frep);
-  dfree(P.fent);
+  dfree(P.rep_ent);
   dfree(P.zi);
   dfree(P.lnv);
   dfree(P.zpart);
@@ -224,10 +223,10 @@ static int init_problem(Ctx& c, Problem& P, int n, const int32_t* goff_host, int
       (rc = dmalloc(&P.head_box, ranges, "ranges")) || (rc = dmalloc(&P.tail_box, ranges, "ranges")) ||
       (rc = dmalloc(&P.head_val, ranges * 27, "ranges")) ||
       (rc = dmalloc(&P.tail_val, ranges * 27, "ranges")) ||
-      (rc = dmalloc(&P.perm, n, "perm")) || (rc = dmalloc(&P.frep, n, "frep")) ||
-      (rc = dmalloc(&P.fent, n, "fent")) || (rc = dmalloc(&P.zi, n, "zi")) ||
+      (rc = dmalloc(&P.perm, n, "perm")) || (rc = dmalloc(&P.rep_ent, n, "rep_ent")) ||
+      (rc = dmalloc(&P.zi, n, "zi")) ||
       (rc = dmalloc(&P.lnv, n, "lnv")) || (rc = dmalloc(&P.zpart, nc, "zpart")) ||
-      (rc = dmalloc(&P.zg, G, "zg")) || (rc = dmalloc(&P.cost_part, (size_t)nc * 5, "cost")))
+      (rc = dmalloc(&P.zg, G, "zg")) || (rc = dmalloc(&P.cost_part, (size_t)nc * kCostTerms, "cost")))
     return rc;
   TSNET_HIP(hipMemcpy(P.ginfo, P.ginfo_h.data(), sizeof(GraphInfo) * G, hipMemcpyHostToDevice));
   TSNET_HIP(hipMemcpy(P.goff_d, P.goff.data(), sizeof(int) * (G + 1), hipMemcpyHostToDevice));
@@ -317,7 +316,7 @@ static int check_call(tsnet_ctx ctx, tsnet_P P) {
 
 // The interpolation pipeline shared by grad and cost: grid, sort, spread, FFT, gather.
 static int run_interp(Problem& P, const float2* X, const tsnet_params& prm, int with_ln,
-                      hipStream_t s) {
+                      int with_zi, double* Z_out, hipStream_t s) {
   Ctx& c = *P.ctx;
   int rc = ensure_grid(P, prm.max_intervals);
   if (rc) return rc;
@@ -340,7 +339,7 @@ static int run_interp(Problem& P, const float2* X, const tsnet_params& prm, int 
   }
   {
     StageScope t(c, ST_GATHER, s);
-    TSNET_LAUNCH(launch_gather(P, X, with_ln, s));
+    TSNET_LAUNCH(launch_gather(P, X, with_ln, with_zi, Z_out, s));
   }
   return TSNET_OK;
 }
@@ -357,11 +356,8 @@ static int grad_impl(tsnet_ctx ctx, tsnet_P Pp, const float* X, const tsnet_para
   Ctx& c = ctx->c;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const float2* X2 = reinterpret_cast<const float2*>(X);
-  if ((rc = run_interp(P, X2, *prm, 0, s))) return rc;
-  {
-    StageScope t(c, ST_ZRED, s);
-    TSNET_LAUNCH(launch_zreduce(P, Z_out, s));
-  }
+  // the gather also reduces Z; Z_i is stored only when asked for
+  if ((rc = run_interp(P, X2, *prm, 0, Z_i != nullptr, Z_out, s))) return rc;
   const bool tiled = use_tiles(P, *prm);
   if (tiled && P.tile_T == 0 && (rc = build_tiles(P, s))) return rc;
   {
@@ -625,7 +621,7 @@ int tsnet_cost(tsnet_ctx ctx, tsnet_P Pp, const float* X, const tsnet_params* pr
   if (!X || !cost) return fail(TSNET_EINVAL, "X and cost must not be NULL");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const float2* X2 = reinterpret_cast<const float2*>(X);
-  if ((rc = run_interp(Pp->p, X2, *prm, 1, s))) return rc;
+  if ((rc = run_interp(Pp->p, X2, *prm, 1, 0, nullptr, s))) return rc;
   StageScope t(ctx->c, ST_COST, s);
   TSNET_LAUNCH(launch_cost(Pp->p, X2, *prm, cost, s));
   return TSNET_OK;

@@ -42,8 +42,8 @@ __global__ __launch_bounds__(256) void k_attract(
     const float2* __restrict__ X, const int64_t* __restrict__ rowptr, const int* __restrict__ col,
     const float* __restrict__ val, const int* __restrict__ order, int n,
     const int* __restrict__ goff, int G, const GraphInfo* __restrict__ gi,
-    const double* __restrict__ zg, const float2* __restrict__ frep,
-    const float2* __restrict__ fent, AttrParams ap, float2* Gout, float2* Fattr) {
+    const double* __restrict__ zg, const float4* __restrict__ rep_ent, AttrParams ap, float2* Gout,
+    float2* Fattr) {
   const int lane = lane_id();
   const int nwaves = blockDim.x / kWave;
   for (int t = blockIdx.x * nwaves + wave_id(); t < n; t += gridDim.x * nwaves) {
@@ -78,7 +78,8 @@ __global__ __launch_bounds__(256) void k_attract(
       const int g = G == 1 ? 0 : graph_of(goff, G, i);
       const double Z = zg[g];
       const float inv_z = Z > 0.0 ? (float)(1.0 / Z) : 0.0f;
-      const float2 r = frep[i], en = fent[i];
+      const float4 re = rep_ent[i];
+      const float2 r = make_float2(re.x, re.y), en = make_float2(re.z, re.w);
       const float cn = ap.lc * gi[g].inv_n, rn = ap.lr * gi[g].inv_n2;
       float2 o;
       o.x = ap.lkl4 * (fx - r.x * inv_z) + cn * xi.x - rn * en.x;
@@ -98,7 +99,7 @@ hipError_t launch_attract(Problem& P, const float2* X, const tsnet_params& prm, 
   int blocks = (P.n + 3) / 4;
   if (blocks > 8192) blocks = 8192;
   hipLaunchKernelGGL(k_attract, dim3(blocks), dim3(256), 0, s, X, P.rowptr, P.col, P.val,
-                     P.row_order, P.n, P.goff_d, P.G, P.ginfo, P.zg, P.frep, P.fent, ap, G, F_attr);
+                     P.row_order, P.n, P.goff_d, P.G, P.ginfo, P.zg, P.rep_ent, ap, G, F_attr);
   return hipGetLastError();
 }
 

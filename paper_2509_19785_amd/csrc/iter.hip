@@ -18,12 +18,17 @@ namespace tsnet {
 // bounding box, n_int = ceil(span / h_target) clamped to [min, max] and
 // rounded up to a power of two, box side h = span / n_int, grid centred on the
 // bounding box. The decisions are taken in FP64.
-__global__ __launch_bounds__(256) void k_bbox_plan(
+// One block of kChunkThreads per chunk (a few vertices per thread); the bounds
+// of every chunk go to part[chunk] and the last block to finish plans the
+// grids. One counter update per chunk: many more blocks would queue on it.
+constexpr int kChunkThreads = 1024;
+
+__global__ __launch_bounds__(kChunkThreads) void k_bbox_plan(
     const float2* __restrict__ X, const int* __restrict__ chunk_start,
-    const int* __restrict__ chunk_end, int num_chunks, float4* part, unsigned* counter,
+    const int* __restrict__ chunk_end, int nblocks, float4* part, unsigned* counter,
     const GraphInfo* __restrict__ gi, int G, PlanParams pp, GridDesc* desc, int* btotal,
     unsigned* status) {
-  __shared__ float red[4][4];
+  __shared__ float red[kChunkThreads / kWave][4];
   __shared__ int bad_s;
   __shared__ int last_s;
   const int c = blockIdx.x;
@@ -31,7 +36,7 @@ __global__ __launch_bounds__(256) void k_bbox_plan(
   __syncthreads();
   float xmn = FLT_MAX, xmx = -FLT_MAX, ymn = FLT_MAX, ymx = -FLT_MAX;
   int bad = 0;
-  for (int i = chunk_start[c] + threadIdx.x; i < chunk_end[c]; i += blockDim.x) {
+  for (int i = chunk_start[c] + threadIdx.x; i < chunk_end[c]; i += kChunkThreads) {
     const float2 p = X[i];
     if (!(isfinite(p.x) && isfinite(p.y))) {
       bad = 1;
@@ -64,7 +69,7 @@ __global__ __launch_bounds__(256) void k_bbox_plan(
     part[c] = make_float4(bad_s ? NAN : xmn, xmx, ymn, ymx);
     __threadfence();
     const unsigned prev = atomicAdd(counter, 1u);
-    last_s = (prev == (unsigned)(num_chunks - 1));
+    last_s = (prev == (unsigned)(nblocks - 1));
   }
   __syncthreads();
   if (!last_s) return;
@@ -141,7 +146,7 @@ __global__ __launch_bounds__(256) void k_bbox_plan(
 }
 
 hipError_t launch_bbox_plan(Problem& P, const float2* X, const PlanParams& pp, hipStream_t s) {
-  hipLaunchKernelGGL(k_bbox_plan, dim3(P.num_chunks), dim3(256), 0, s, X, P.chunk_start,
+  hipLaunchKernelGGL(k_bbox_plan, dim3(P.num_chunks), dim3(kChunkThreads), 0, s, X, P.chunk_start,
                      P.chunk_end, P.num_chunks, P.bbox_part, P.counters + 0, P.ginfo, P.G, pp,
                      P.desc, P.btotal, P.ctx->status);
   return hipGetLastError();
@@ -153,19 +158,29 @@ hipError_t launch_bbox_plan(Problem& P, const float2* X, const PlanParams& pp, h
 // wave reads few nodes), then form
 //   F_rep = (x - c) phi[K2,1] - phi[K2,x],  F_ent = (x - c) phi[Ke,1] - phi[Ke,x],
 //   Z_i = phi[K1,1] - 1 (the self term K1(0) = 1),
-// and write them at the vertex of the slot.
-__global__ __launch_bounds__(256) void k_gather(
+// and write them at the vertex of the slot (F_rep and F_ent as one 16-byte
+// record, Z_i only when it is asked for).
+// One block of kChunkThreads per chunk. Each block also sums the Z_i of its
+// chunk (compensated FP32, in sorted order) into zpart[chunk]; the last block
+// to finish adds the chunk sums of every graph in FP64 (fixed order, so Z is
+// reproducible) into zg and Z_out.
+__global__ __launch_bounds__(kChunkThreads) void k_gather(
     const float2* __restrict__ xs, const int* __restrict__ skeys, const int* __restrict__ perm,
     const int* __restrict__ chunk_graph, const int* __restrict__ chunk_start,
     const int* __restrict__ chunk_end, const GridDesc* __restrict__ desc,
-    const GraphInfo* __restrict__ gi, const float* __restrict__ pot, size_t stride_pot,
-    float2* frep, float2* fent, float* zi, float* lnv) {
+    const GraphInfo* __restrict__ gi, int G, const float* __restrict__ pot, size_t stride_pot,
+    float4* rep_ent, float* zi, float* lnv, double* zpart, unsigned* counter,
+    int nblocks, double* zg, double* Z_out) {
+  constexpr int NW = kChunkThreads / kWave;
+  __shared__ float sh_hi[NW], sh_lo[NW];
+  __shared__ int last_s;
   const int c = blockIdx.x;
   const int g = chunk_graph[c];
   const GridDesc d = desc[g];
   const float* pg = pot + (size_t)g * stride_pot;
   const bool single = gi[g].n == 1;
-  for (int p = chunk_start[c] + threadIdx.x; p < chunk_end[c]; p += blockDim.x) {
+  CompSum zs;
+  for (int p = chunk_start[c] + threadIdx.x; p < chunk_end[c]; p += kChunkThreads) {
     const float2 x = xs[p];
     const int local = skeys[p] - d.box_base;
     const int by = local / d.n_int, bx = local - by * d.n_int;
@@ -207,65 +222,48 @@ __global__ __launch_bounds__(256) void k_gather(
       z = 0.f;
     }
     const int i = perm[p];
-    frep[i] = r;
-    fent[i] = e;
-    zi[i] = z;
+    rep_ent[i] = make_float4(r.x, r.y, e.x, e.y);  // one scattered 16-byte store
+    if (zi) zi[i] = z;
     if (lnv) lnv[i] = single ? 0.f : phi[CH_KLN_1];
+    zs.add(z);
   }
-}
-
-hipError_t launch_gather(Problem& P, const float2* X, int with_ln, hipStream_t s) {
-  (void)X;
-  hipLaunchKernelGGL(k_gather, dim3(P.num_chunks), dim3(256), 0, s, P.xs, P.skeys, P.perm,
-                     P.chunk_graph, P.chunk_start, P.chunk_end, P.desc, P.ginfo, P.pot,
-                     P.stride_pot, P.frep, P.fent, P.zi, with_ln ? P.lnv : nullptr);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Z per graph: compensated FP32 sums per chunk (vertex order), FP64 across chunks.
-__global__ __launch_bounds__(256) void k_zreduce(const float* __restrict__ zi,
-                                                 const int* __restrict__ chunk_start,
-                                                 const int* __restrict__ chunk_end, int num_chunks,
-                                                 double* zpart, unsigned* counter,
-                                                 const GraphInfo* __restrict__ gi, int G,
-                                                 double* zg, double* Z_out) {
-  __shared__ float sh_hi[4], sh_lo[4];
-  __shared__ int last_s;
-  const int c = blockIdx.x;
-  CompSum acc;
-  for (int i = chunk_start[c] + threadIdx.x; i < chunk_end[c]; i += blockDim.x) acc.add(zi[i]);
-  acc = wave_comp_sum(acc);
+  zs = wave_comp_sum(zs);
   if (lane_id() == 0) {
-    sh_hi[wave_id()] = acc.hi;
-    sh_lo[wave_id()] = acc.lo;
+    sh_hi[wave_id()] = zs.hi;
+    sh_lo[wave_id()] = zs.lo;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     double v = 0.0;
-    for (int w = 0; w < 4; ++w) v += (double)sh_hi[w] + (double)sh_lo[w];
+    for (int w = 0; w < NW; ++w) v += (double)sh_hi[w] + (double)sh_lo[w];
     zpart[c] = v;
     __threadfence();
-    last_s = (atomicAdd(counter, 1u) == (unsigned)(num_chunks - 1));
+    last_s = (atomicAdd(counter, 1u) == (unsigned)(nblocks - 1));
   }
   __syncthreads();
   if (!last_s) return;
   __threadfence();
-  for (int g = wave_id(); g < G; g += blockDim.x / kWave) {
+  for (int gg = wave_id(); gg < G; gg += blockDim.x / kWave) {
     double z = 0.0;
-    for (int k = gi[g].chunk_begin + lane_id(); k < gi[g].chunk_end; k += kWave) z += ld_coherent(&zpart[k]);
+    for (int k = gi[gg].chunk_begin + lane_id(); k < gi[gg].chunk_end; k += kWave)
+      z += ld_coherent(&zpart[k]);
     z = wave_sum(z);
     if (lane_id() == 0) {
-      zg[g] = z;
-      if (Z_out) Z_out[g] = z;
+      zg[gg] = z;
+      if (Z_out) Z_out[gg] = z;
     }
   }
   if (threadIdx.x == 0) *counter = 0u;
 }
 
-hipError_t launch_zreduce(Problem& P, double* Z_out, hipStream_t s) {
-  hipLaunchKernelGGL(k_zreduce, dim3(P.num_chunks), dim3(256), 0, s, P.zi, P.chunk_start,
-                     P.chunk_end, P.num_chunks, P.zpart, P.counters + 1, P.ginfo, P.G, P.zg, Z_out);
+hipError_t launch_gather(Problem& P, const float2* X, int with_ln, int with_zi, double* Z_out,
+                         hipStream_t s) {
+  (void)X;
+  const int nb = P.num_chunks;
+  hipLaunchKernelGGL(k_gather, dim3(nb), dim3(kChunkThreads), 0, s, P.xs, P.skeys, P.perm, P.chunk_graph,
+                     P.chunk_start, P.chunk_end, P.desc, P.ginfo, P.G, P.pot, P.stride_pot,
+                     P.rep_ent, with_zi ? P.zi : nullptr, with_ln ? P.lnv : nullptr, P.zpart,
+                     P.counters + 1, nb, P.zg, Z_out);
   return hipGetLastError();
 }
 
@@ -316,9 +314,10 @@ hipError_t launch_step(Problem& P, float2* X, float2* upd, float2* gains, const 
 // ---------------------------------------------------------------------------
 // Cost of Eq. (1), entropy in the kernel form -l_r / (4 n^2) sum ln(eps + r^2):
 //  per row: sum_j p_ij (ln p_ij + ln(1 + r_ij^2)) over p > 0 and sum_j p_ij;
-//  per chunk: compensated sums of those, of ||X_i||^2, of the interpolated
-//  sum_j ln(eps + r_ij^2) (self term ln eps included) and of Z_i;
-//  per graph (last block): C_KL = l_kl (S_pl + S_p ln Z), C_CMP, C_ENT, total.
+//  per chunk: compensated sums of those, of ||X_i||^2 and of the interpolated
+//  sum_j ln(eps + r_ij^2) (self term ln eps included);
+//  per graph (last block): C_KL = l_kl (S_pl + S_p ln Z) with the Z the gather
+//  reduced, C_CMP, C_ENT, total.
 __global__ __launch_bounds__(256) void k_cost_rows(const float2* __restrict__ X,
                                                    const int64_t* __restrict__ rowptr,
                                                    const int* __restrict__ col,
@@ -350,13 +349,14 @@ struct CostK {
 
 __global__ __launch_bounds__(256) void k_cost_reduce(
     const float2* __restrict__ X, const float2* __restrict__ rowv, const float* __restrict__ lnv,
-    const float* __restrict__ zi, const int* __restrict__ chunk_start,
+    const double* __restrict__ zg, const int* __restrict__ chunk_start,
     const int* __restrict__ chunk_end, int num_chunks, double* part, unsigned* counter,
     const GraphInfo* __restrict__ gi, int G, CostK ck, double* cost) {
-  __shared__ float sh[5][2][4];
+  constexpr int NQ = kCostTerms;
+  __shared__ float sh[NQ][2][4];
   __shared__ int last_s;
   const int c = blockIdx.x;
-  CompSum acc[5];
+  CompSum acc[NQ];
   for (int i = chunk_start[c] + threadIdx.x; i < chunk_end[c]; i += blockDim.x) {
     const float2 rv = rowv[i];
     const float2 x = X[i];
@@ -364,10 +364,9 @@ __global__ __launch_bounds__(256) void k_cost_reduce(
     acc[1].add(rv.y);
     acc[2].add(x.x * x.x + x.y * x.y);
     acc[3].add(lnv[i]);
-    acc[4].add(zi[i]);
   }
 #pragma unroll
-  for (int q = 0; q < 5; ++q) {
+  for (int q = 0; q < NQ; ++q) {
     acc[q] = wave_comp_sum(acc[q]);
     if (lane_id() == 0) {
       sh[q][0][wave_id()] = acc[q].hi;
@@ -376,10 +375,10 @@ __global__ __launch_bounds__(256) void k_cost_reduce(
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int q = 0; q < 5; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       double v = 0.0;
       for (int w = 0; w < 4; ++w) v += (double)sh[q][0][w] + (double)sh[q][1][w];
-      part[(size_t)c * 5 + q] = v;
+      part[(size_t)c * NQ + q] = v;
     }
     __threadfence();
     last_s = (atomicAdd(counter, 1u) == (unsigned)(num_chunks - 1));
@@ -388,13 +387,13 @@ __global__ __launch_bounds__(256) void k_cost_reduce(
   if (!last_s) return;
   __threadfence();
   for (int g = wave_id(); g < G; g += blockDim.x / kWave) {
-    double s[5] = {0, 0, 0, 0, 0};
+    double s[NQ] = {0, 0, 0, 0};
     for (int k = gi[g].chunk_begin + lane_id(); k < gi[g].chunk_end; k += kWave)
-      for (int q = 0; q < 5; ++q) s[q] += ld_coherent(&part[(size_t)k * 5 + q]);
-    for (int q = 0; q < 5; ++q) s[q] = wave_sum(s[q]);
+      for (int q = 0; q < NQ; ++q) s[q] += ld_coherent(&part[(size_t)k * NQ + q]);
+    for (int q = 0; q < NQ; ++q) s[q] = wave_sum(s[q]);
     if (lane_id() != 0) continue;
     const double n = (double)gi[g].n;
-    const double Z = s[4];
+    const double Z = zg[g];
     const double kl = (n > 1 && Z > 0) ? ck.lkl * (s[0] + s[1] * log(Z)) : 0.0;
     const double cm = ck.lc / (2.0 * n) * s[2];
     const double en = n > 1 ? -ck.lr / (4.0 * n * n) * (s[3] - n * ck.log_eps) : 0.0;
@@ -410,23 +409,33 @@ hipError_t launch_cost(Problem& P, const float2* X, const tsnet_params& prm, dou
                        hipStream_t s) {
   int blocks = (P.n + 3) / 4;
   if (blocks > 8192) blocks = 8192;
-  // rows' KL sums go to frep's storage (unused by the cost path)
+  // rows' KL sums go to the storage of rep_ent (unused by the cost path)
+  float2* rowv = reinterpret_cast<float2*>(P.rep_ent);
   hipLaunchKernelGGL(k_cost_rows, dim3(blocks), dim3(256), 0, s, X, P.rowptr, P.col, P.val, P.n,
-                     P.frep);
+                     rowv);
   CostK ck{prm.lambda_kl, prm.lambda_c, prm.lambda_r, log(prm.eps_r)};
-  hipLaunchKernelGGL(k_cost_reduce, dim3(P.num_chunks), dim3(256), 0, s, X, P.frep, P.lnv, P.zi,
+  hipLaunchKernelGGL(k_cost_reduce, dim3(P.num_chunks), dim3(256), 0, s, X, rowv, P.lnv, P.zg,
                      P.chunk_start, P.chunk_end, P.num_chunks, P.cost_part, P.counters + 2, P.ginfo,
                      P.G, ck, cost);
   return hipGetLastError();
 }
 
-hipError_t launch_copy_terms(Problem& P, float2* F_rep, float2* F_ent, float* Z_i, hipStream_t s) {
-  if (F_rep) {
-    hipError_t e = hipMemcpyAsync(F_rep, P.frep, sizeof(float2) * P.n, hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) return e;
+// The two halves of the packed (F_rep, F_ent) records into the caller's arrays.
+__global__ __launch_bounds__(256) void k_split_terms(const float4* __restrict__ re, int n,
+                                                     float2* F_rep, float2* F_ent) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const float4 v = re[i];
+    if (F_rep) F_rep[i] = make_float2(v.x, v.y);
+    if (F_ent) F_ent[i] = make_float2(v.z, v.w);
   }
-  if (F_ent) {
-    hipError_t e = hipMemcpyAsync(F_ent, P.fent, sizeof(float2) * P.n, hipMemcpyDeviceToDevice, s);
+}
+
+hipError_t launch_copy_terms(Problem& P, float2* F_rep, float2* F_ent, float* Z_i, hipStream_t s) {
+  if ((F_rep || F_ent) && P.n > 0) {
+    int blocks = (P.n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_split_terms, dim3(blocks), dim3(256), 0, s, P.rep_ent, P.n, F_rep, F_ent);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   if (Z_i) {

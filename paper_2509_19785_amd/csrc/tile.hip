@@ -58,8 +58,7 @@ struct TileArgs {
   int G;
   const GraphInfo* gi;
   const double* zg;
-  const float2* frep;
-  const float2* fent;
+  const float4* rep_ent;  // (F_rep, F_ent) of each vertex
   float lkl4, lc, lr;
   float2* Gout;
   float2* Fattr;
@@ -346,7 +345,8 @@ __global__ __launch_bounds__(kTileThreads) void k_attract_tiled(TileArgs a) {
     const int g = a.G == 1 ? 0 : graph_of(a.goff, a.G, i);
     const double Z = a.zg[g];
     const float inv_z = Z > 0.0 ? (float)(1.0 / Z) : 0.0f;
-    const float2 rp = a.frep[i], en = a.fent[i];
+    const float4 re = a.rep_ent[i];
+    const float2 rp = make_float2(re.x, re.y), en = make_float2(re.z, re.w);
     const float cn = a.lc * a.gi[g].inv_n, rn = a.lr * a.gi[g].inv_n2;
     float2 o;
     o.x = a.lkl4 * (f.x - rp.x * inv_z) + cn * xi.x - rn * en.x;
@@ -371,8 +371,7 @@ hipError_t launch_attract_tiled(Problem& P, const float2* X, const tsnet_params&
   a.G = P.G;
   a.gi = P.ginfo;
   a.zg = P.zg;
-  a.frep = P.frep;
-  a.fent = P.fent;
+  a.rep_ent = P.rep_ent;
   a.lkl4 = (float)(4.0 * prm.lambda_kl);
   a.lc = (float)prm.lambda_c;
   a.lr = (float)prm.lambda_r;

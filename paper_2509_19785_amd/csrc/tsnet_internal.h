@@ -17,6 +17,7 @@ constexpr int kMaxIntervals = 512;        // boxes per axis (power of two)
 constexpr int kMaxNg = kNodes * kMaxIntervals;
 constexpr int kMaxM = 2 * kMaxNg;         // FFT length per axis (3 * 2^b)
 constexpr int kPotCh = 8;                 // interleaved potential channels per node
+constexpr int kCostTerms = 4;             // chunk sums of the cost reduction
 constexpr int kChunk = 2048;              // vertices per chunk of per-vertex kernels
 constexpr int kMaxK = 1024;               // neighbours per vertex in tsnet_build_P
 constexpr double kSpanFloor = 1e-4;       // smallest grid span (degenerate layouts)
@@ -147,11 +148,10 @@ struct Problem {
   float2* ospec = nullptr;            // per graph [8][ng][M/2+1] the same, transposed
   float* pot = nullptr;               // per graph ng^2 * 8
   size_t stride_charges = 0, stride_qspec = 0, stride_kspec = 0, stride_ospec = 0, stride_pot = 0;
-  float2* frep = nullptr;             // [n]
-  float2* fent = nullptr;             // [n]
+  float4* rep_ent = nullptr;          // [n] (F_rep.x, F_rep.y, F_ent.x, F_ent.y) of each vertex
   float* zi = nullptr;                // [n]
   float* lnv = nullptr;               // [n] interpolated sum_j ln(eps + r^2) (cost path)
-  double* zpart = nullptr;            // [num_chunks]
+  double* zpart = nullptr;            // [num_chunks] Z chunk sums of the gather
   double* zg = nullptr;               // [G]
   double* cost_part = nullptr;        // [num_chunks * 5]
   double* direct_part = nullptr;      // scratch of the FP64 direct kernel
@@ -175,8 +175,9 @@ int fail(int code, const std::string& msg);
 hipError_t launch_bbox_plan(Problem& P, const float2* X, const PlanParams& pp, hipStream_t s);
 hipError_t launch_bin(Problem& P, const float2* X, hipStream_t s);
 hipError_t launch_spread(Problem& P, const float2* X, hipStream_t s);
-hipError_t launch_gather(Problem& P, const float2* X, int with_ln, hipStream_t s);
-hipError_t launch_zreduce(Problem& P, double* Z_out, hipStream_t s);
+// gather also reduces Z per graph into zg (and Z_out when not NULL)
+hipError_t launch_gather(Problem& P, const float2* X, int with_ln, int with_zi, double* Z_out,
+                         hipStream_t s);
 hipError_t launch_attract(Problem& P, const float2* X, const tsnet_params& prm, float2* G,
                           float2* F_attr, hipStream_t s);
 hipError_t launch_attract_tiled(Problem& P, const float2* X, const tsnet_params& prm, float2* G,
