@@ -18,7 +18,7 @@
 // One workgroup per row tile walks the windows in order, with X[window] in LDS
 // (the next window is fetched into registers while the current one is in use)
 // and the row sums of its tile in LDS. A block is cut into 16 equal pieces,
-// one per wave; a lane walks a run of up to 8 consecutive entries, and partial
+// one per wave; a lane walks a run of up to 6 consecutive entries, and partial
 // row sums are joined across lanes by a segmented scan. A row that continues
 // from the previous wave's piece is parked in a slot of its own and added once
 // the window is done. Every sum is taken in an order fixed by the layout, so
@@ -43,6 +43,7 @@ constexpr int kTileThreads = 1024;
 constexpr int kTileWaves = kTileThreads / kWave;
 constexpr int kTileRun = 6;                   // entries per lane and pass
 constexpr int kTileNone = 0x7fffffff;         // key of a lane without entries
+constexpr int kTileMaxNC = 768;               // column windows at most (block starts in LDS)
 
 static_assert(kTileMaxRows <= (1 << kTileSlotBits), "slot field too narrow");
 static_assert(kTileSlotBits + kTileColBits <= 32, "packed entry too wide");
@@ -64,17 +65,18 @@ struct TileArgs {
   float2* Fattr;
 };
 
-// Entries [p0, p1) of wave `wv` in block b. A row continues from the previous
-// piece when the entries at p0 - 1 and p0 share a slot; both are fetched with
-// the piece (indices clamped into the array, so every load is unconditional
-// and the compiler can keep them in flight) and compared when it is used.
+// Entries [p0, p1) of wave `wv` in window c of the tile (bst: the tile's
+// block starts, in LDS). A row continues from the previous piece when the
+// entries at p0 - 1 and p0 share a slot; both are fetched with the piece
+// (indices clamped into the array, so every load is unconditional and the
+// compiler can keep them in flight) and compared when it is used.
 struct Piece {
   int bs, p0, p1;
   unsigned at, before;  // packed words of entries p0 and p0 - 1
 };
 
-__device__ __forceinline__ Piece piece_of(const TileArgs& a, int b, int wv) {
-  const int bs = a.bstart[b], be = a.bstart[b + 1];
+__device__ __forceinline__ Piece piece_of(const TileArgs& a, const int* bst, int c, int wv) {
+  const int bs = bst[c], be = bst[c + 1];
   const int64_t L = be - bs;
   Piece p;
   p.bs = bs;
@@ -96,6 +98,19 @@ __device__ __forceinline__ void run_of(int base, int p1, int lane, int& s0, int&
   const int U = (Lp + kWave - 1) / kWave;
   s0 = base + lane * U;
   cnt = max(0, min(U, base + Lp - s0));
+}
+
+// Vertex of slot q * kTileThreads + tid of tile t for every q, -1 where the
+// slot is unused or beyond R (loads clamped into the tile, none conditional).
+constexpr int kTileRowsPerThread = kTileMaxRows / kTileThreads;
+__device__ __forceinline__ void tile_row_ids(const TileArgs& a, int t, int tid,
+                                             int (&iv)[kTileRowsPerThread]) {
+#pragma unroll
+  for (int q = 0; q < kTileRowsPerThread; ++q) {
+    const int s = q * kTileThreads + tid;
+    iv[q] = a.tile_rows[(size_t)t * a.R + min(s, a.R - 1)];
+    if (s >= a.R) iv[q] = -1;
+  }
 }
 
 struct Carry {
@@ -252,19 +267,36 @@ __global__ __launch_bounds__(kTileThreads) void k_attract_tiled(TileArgs a) {
   __shared__ float2 acc[kTileMaxRows];
   __shared__ int hrow[kTileWaves];
   __shared__ float2 hval[kTileWaves];
+  __shared__ int bst[kTileMaxNC + 1];
   const int t = blockIdx.x, tid = threadIdx.x, lane = lane_id(), wv = wave_id();
   const int R = a.R, NC = a.NC, n = a.n;
-  for (int s = tid; s < R; s += kTileThreads) {
-    const int i = a.tile_rows[(size_t)t * R + s];
-    xrow[s] = i >= 0 ? a.X[i] : make_float2(0.f, 0.f);
-    acc[s] = make_float2(0.f, 0.f);
+  // the tile's block starts: read once, so no window waits on a load of them
+  static_assert(kTileMaxNC < kTileThreads, "one block start per thread");
+  if (tid <= NC) bst[tid] = a.bstart[(size_t)t * NC + tid];
+  // the tile's rows and the first window: every load issued before any is used
+  {
+    int iv[kTileRowsPerThread];
+    float2 xv[kTileRowsPerThread], wv0[PRE];
+    tile_row_ids(a, t, tid, iv);
+#pragma unroll
+    for (int q = 0; q < kTileRowsPerThread; ++q) xv[q] = a.X[max(iv[q], 0)];
+#pragma unroll
+    for (int q = 0; q < PRE; ++q) wv0[q] = a.X[min(q * kTileThreads + tid, n - 1)];
+#pragma unroll
+    for (int q = 0; q < kTileRowsPerThread; ++q) {
+      const int s = q * kTileThreads + tid;
+      if (s < R) {
+        xrow[s] = iv[q] >= 0 ? xv[q] : make_float2(0.f, 0.f);
+        acc[s] = make_float2(0.f, 0.f);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PRE; ++q) win[q * kTileThreads + tid] = wv0[q];
   }
   if (tid < kTileWaves) hrow[tid] = -1;
-  for (int k = tid; k < kTileCols; k += kTileThreads)
-    win[k] = k < n ? a.X[k] : make_float2(0.f, 0.f);
   __syncthreads();
 
-  Piece pc = piece_of(a, t * NC, wv);
+  Piece pc = piece_of(a, bst, 0, wv);
   int head = piece_head(pc);
   int s0, cnt;
   run_of(pc.p0, pc.p1, lane, s0, cnt);
@@ -282,7 +314,7 @@ __global__ __launch_bounds__(kTileThreads) void k_attract_tiled(TileArgs a) {
 #pragma unroll
     for (int q = 0; q < PRE; ++q)
       pre[q] = a.X[min(cn * kTileCols + q * kTileThreads + tid, n - 1)];
-    const Piece pn = piece_of(a, t * NC + cn, wv);
+    const Piece pn = piece_of(a, bst, cn, wv);
     int ns0, ncnt;
     run_of(pn.p0, pn.p1, lane, ns0, ncnt);
     uint2 en[kTileRun];
@@ -290,16 +322,32 @@ __global__ __launch_bounds__(kTileThreads) void k_attract_tiled(TileArgs a) {
     for (int k = 0; k < kTileRun; ++k) en[k] = a.ent[min(ns0 + k, a.last)];
     Carry cr{-1, 0.f, 0.f};
     if (pc.p0 < pc.p1) {
-      tile_pass(ec, cnt, pc.p0 + kWave * kTileRun < pc.p1, lane, wv, head, win, xrow, acc, hrow,
-                hval, cr);
-      for (int base = pc.p0 + kWave * kTileRun; base < pc.p1; base += kWave * kTileRun) {
-        int s1, c1;
-        run_of(base, pc.p1, lane, s1, c1);
-        uint2 e2[kTileRun];
+      // a piece longer than one pass: the entries of each further pass are
+      // loaded before the pass ahead of it runs
+      constexpr int kPass = kWave * kTileRun;
+      uint2 e2[kTileRun];
+      int c1 = 0;
+      const bool two = pc.p0 + kPass < pc.p1;
+      if (two) {
+        int s1;
+        run_of(pc.p0 + kPass, pc.p1, lane, s1, c1);
 #pragma unroll
         for (int k = 0; k < kTileRun; ++k) e2[k] = a.ent[min(s1 + k, a.last)];
-        tile_pass(e2, c1, base + kWave * kTileRun < pc.p1, lane, wv, head, win, xrow, acc, hrow,
-                  hval, cr);
+      }
+      tile_pass(ec, cnt, two, lane, wv, head, win, xrow, acc, hrow, hval, cr);
+      for (int base = pc.p0 + kPass; base < pc.p1; base += kPass) {
+        uint2 cur[kTileRun];
+#pragma unroll
+        for (int k = 0; k < kTileRun; ++k) cur[k] = e2[k];
+        const int cc = c1;
+        const bool more = base + kPass < pc.p1;
+        if (more) {
+          int s1;
+          run_of(base + kPass, pc.p1, lane, s1, c1);
+#pragma unroll
+          for (int k = 0; k < kTileRun; ++k) e2[k] = a.ent[min(s1 + k, a.last)];
+        }
+        tile_pass(cur, cc, more, lane, wv, head, win, xrow, acc, hrow, hval, cr);
       }
     }
     __syncthreads();
@@ -337,15 +385,21 @@ __global__ __launch_bounds__(kTileThreads) void k_attract_tiled(TileArgs a) {
     cnt = ncnt;
   }
 
-  // assembly of the tile's rows
-  for (int s = tid; s < R; s += kTileThreads) {
-    const int i = a.tile_rows[(size_t)t * R + s];
+  // assembly of the tile's rows (loads batched as at the start)
+  int iv[kTileRowsPerThread];
+  float4 rv[kTileRowsPerThread];
+  tile_row_ids(a, t, tid, iv);
+#pragma unroll
+  for (int q = 0; q < kTileRowsPerThread; ++q) rv[q] = a.rep_ent[max(iv[q], 0)];
+#pragma unroll
+  for (int q = 0; q < kTileRowsPerThread; ++q) {
+    const int s = q * kTileThreads + tid, i = iv[q];
     if (i < 0) continue;
     const float2 f = acc[s], xi = xrow[s];
     const int g = a.G == 1 ? 0 : graph_of(a.goff, a.G, i);
     const double Z = a.zg[g];
     const float inv_z = Z > 0.0 ? (float)(1.0 / Z) : 0.0f;
-    const float4 re = a.rep_ent[i];
+    const float4 re = rv[q];
     const float2 rp = make_float2(re.x, re.y), en = make_float2(re.z, re.w);
     const float cn = a.lc * a.gi[g].inv_n, rn = a.lr * a.gi[g].inv_n2;
     float2 o;
@@ -430,7 +484,7 @@ __global__ __launch_bounds__(256) void k_tile_bounds(const unsigned* __restrict_
 bool tiles_supported(int n) {
   const int64_t T = std::max<int64_t>(kTileMinTiles, (n + kTileMaxRows - 1) / kTileMaxRows);
   const int64_t NC = (n + kTileCols - 1) / kTileCols;
-  return T * NC < ((int64_t)1 << (32 - kTileSlotBits));
+  return NC <= kTileMaxNC && T * NC < ((int64_t)1 << (32 - kTileSlotBits));
 }
 
 int build_tiles(Problem& P, hipStream_t s) {
