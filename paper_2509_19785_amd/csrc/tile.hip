@@ -190,6 +190,8 @@ __device__ __forceinline__ void tile_pass(const uint2 (&e)[kTileRun], int cnt, b
   for (int k = 1; k < kTileRun; ++k)
     if (k < cnt) rl = r[k];
   float cx = 0.f, cy = 0.f, fx = 0.f, fy = 0.f;
+  float2 own[kTileRun];  // sums of the slots wholly inside this lane
+  bool put[kTileRun];
 #pragma unroll
   for (int k = 0; k < kTileRun; ++k) {
     const float dx = xi[k].x - xj[k].x, dy = xi[k].y - xj[k].y;
@@ -206,13 +208,18 @@ __device__ __forceinline__ void tile_pass(const uint2 (&e)[kTileRun], int cnt, b
       fx = cx;
       fy = cy;
     }
-    if (ends && r[k] != r0 && r[k] != rl) {  // a slot wholly inside this lane
-      float2 v = acc[r[k]];
-      v.x += cx;
-      v.y += cy;
-      acc[r[k]] = v;
-    }
+    put[k] = ends && r[k] != r0 && r[k] != rl;
+    own[k] = make_float2(cx, cy);
   }
+  // no other lane or wave touches those slots in this window: all their reads
+  // go out together (slots of the clamped tail entries are valid indices and
+  // are read but not written), then the writes
+  float2 old[kTileRun];
+#pragma unroll
+  for (int k = 0; k < kTileRun; ++k) old[k] = acc[r[k]];
+#pragma unroll
+  for (int k = 0; k < kTileRun; ++k)
+    if (put[k]) acc[r[k]] = make_float2(old[k].x + own[k].x, old[k].y + own[k].y);
   const int frow = cnt > 0 && r0 != rl ? r0 : -1;
   const int cur = rl;
   // the last run of every lane: segmented inclusive scan over the lanes
