@@ -149,11 +149,11 @@ static void free_problem(Problem& P) {
   dfree(P.xs);
   dfree(P.bin_hist);
   dfree(P.bin_tsum);
+  dfree(P.row_order);
   dfree(P.head_box);
   dfree(P.tail_box);
   dfree(P.head_val);
   dfree(P.tail_val);
-  dfree(P.row_order);
   dfree(P.rep_ent);
   dfree(P.zi);
   dfree(P.lnv);

@@ -8,12 +8,12 @@
 //
 // Spread (Sec. 2.3): node charge w[c][a] = sum over the points of the node's
 // box of L_tx(s) L_ty(t) q_c, q = (1, (x - cx) / half, (y - cy) / half).
-// Every contribution is rounded to a 2^-28 grid and summed in 64-bit
-// integers, so the totals do not depend on the summation order. Phase 1:
-// one wave per range of 256 sorted points, a segmented wave reduction by box;
-// boxes entirely inside the range are written directly, the box pieces at the
-// two ends of the range are kept as partials. Phase 2: one wave per box adds
-// the partials of boxes that span ranges and clears empty boxes.
+// The points of a box are contiguous after the sort. Phase 1 cuts the sorted
+// points into ranges of 1024, one wave each, and sums every box's piece of a
+// range in FP32 in a fixed order (a lane per short piece, the whole wave for a
+// long one); whole boxes go straight to their nodes, the pieces at the two
+// ends of a range are kept as partials. Phase 2 adds the partials of boxes
+// that span ranges, in range order, and clears empty boxes.
 #include <hip/hip_runtime.h>
 
 #include "dev_util.h"
@@ -182,11 +182,15 @@ hipError_t launch_bin(Problem& P, const float2* X, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-constexpr int kRange = 256;  // sorted points per wave in spread phase 1
-constexpr int kVals = 27;    // 9 nodes x 3 charges
+constexpr int kVals = 27;        // 9 nodes x 3 charges
+constexpr int kRange = kSpreadRange;
+constexpr int kRangeWaves = 4;   // waves per block of phase 1
+constexpr int kLongSeg = 64;     // segments this long are summed by the whole wave
+constexpr int kSpreadBatch = 4;  // points loaded together by one lane
 
-__device__ __forceinline__ void node_store(float* out, int ng, int bx, int by, const long long* v) {
-  const double inv = 1.0 / (double)kFixScale;
+// Charges of the 9 nodes of box (bx, by): out[c][node], c = 1, x, y.
+template <typename T>
+__device__ __forceinline__ void node_store(float* out, int ng, int bx, int by, const T* v) {
 #pragma unroll
   for (int ty = 0; ty < 3; ++ty)
 #pragma unroll
@@ -194,7 +198,7 @@ __device__ __forceinline__ void node_store(float* out, int ng, int bx, int by, c
       const size_t node = (size_t)(3 * by + ty) * ng + (3 * bx + tx);
       const int k = (ty * 3 + tx) * 3;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) out[(size_t)c * ng * ng + node] = (float)((double)v[k + c] * inv);
+      for (int c = 0; c < 3; ++c) out[(size_t)c * ng * ng + node] = (float)v[k + c];
     }
 }
 
@@ -207,128 +211,164 @@ __device__ __forceinline__ int graph_of_box(const GridDesc* __restrict__ desc, i
   return lo;
 }
 
-__global__ __launch_bounds__(256) void k_spread_ranges(
+struct BoxAt {
+  int g, bx, by;
+  GridDesc d;
+};
+
+__device__ __forceinline__ BoxAt box_at(const GridDesc* __restrict__ desc, int G, int key) {
+  BoxAt b;
+  b.g = G == 1 ? 0 : graph_of_box(desc, G, key);
+  b.d = desc[b.g];
+  const int local = key - b.d.box_base;
+  b.by = local / b.d.n_int;
+  b.bx = local - b.by * b.d.n_int;
+  return b;
+}
+
+// Adds the 27 node contributions of point x of box (bx, by), times w0, to acc
+// (w0 = 0 for the padding of a batch).
+__device__ __forceinline__ void add_point(const BoxAt& b, float2 x, float w0, float (&acc)[kVals]) {
+  const GridDesc& d = b.d;
+  const float s = (x.x - d.x0) / d.h - (float)b.bx;
+  const float t = (x.y - d.y0) / d.h - (float)b.by;
+  float lx[3], ly[3];
+  lagrange3(s, lx);
+  lagrange3(t, ly);
+  const float inv_half = 1.0f / d.half;
+  const float q1 = (x.x - d.cx) * inv_half, q2 = (x.y - d.cy) * inv_half;
+#pragma unroll
+  for (int ty = 0; ty < 3; ++ty)
+#pragma unroll
+    for (int tx = 0; tx < 3; ++tx) {
+      const float w = w0 * ly[ty] * lx[tx];
+      const int k = (ty * 3 + tx) * 3;
+      acc[k + 0] += w;
+      acc[k + 1] += w * q1;
+      acc[k + 2] += w * q2;
+    }
+}
+
+// Sorted points [a, a + stride * m) of one box, m batches of kSpreadBatch
+// points `stride` apart, every point below `end` counted once.
+__device__ __forceinline__ void add_points(const float2* __restrict__ Xs, const BoxAt& b, int a,
+                                           int end, int stride, float (&acc)[kVals]) {
+  for (int p = a; p < end; p += kSpreadBatch * stride) {
+    float2 x[kSpreadBatch];
+#pragma unroll
+    for (int k = 0; k < kSpreadBatch; ++k) x[k] = Xs[min(p + k * stride, end - 1)];
+#pragma unroll
+    for (int k = 0; k < kSpreadBatch; ++k)
+      add_point(b, x[k], p + k * stride < end ? 1.f : 0.f, acc);
+  }
+}
+
+// Where the sum of segment s = [a, b) of range r goes: a whole box to its
+// nodes, the first segment of the range to the head partial, the last one to
+// the tail partial (a segment that is not a whole box touches an end of the
+// range).
+__device__ __forceinline__ void emit(const int* __restrict__ box_off, const BoxAt& bx, int key,
+                                     int a, int b, int s, int r, float* charges, size_t stride,
+                                     float* head_val, float* tail_val, const float (&v)[kVals]) {
+  if (box_off[key] == a && box_off[key + 1] == b) {
+    node_store(charges + (size_t)bx.g * stride, bx.d.ng, bx.bx, bx.by, v);
+  } else {
+    float* dst = (s == 0 ? head_val : tail_val) + (size_t)r * kVals;
+#pragma unroll
+    for (int q = 0; q < kVals; ++q) dst[q] = v[q];
+  }
+}
+
+// Phase 1: one wave per range of kRange sorted points. The range splits into
+// segments of equal box id (start positions collected in LDS). A lane sums a
+// short segment by itself; a long one is summed by the whole wave (lanes
+// stride over its points, then a DPP reduction). Every sum runs in a fixed
+// order, so the charges are reproducible bit for bit.
+__global__ __launch_bounds__(kRangeWaves * kWave) void k_spread_ranges(
     const float2* __restrict__ Xs, const int* __restrict__ skeys, int n,
     const int* __restrict__ box_off, const GridDesc* __restrict__ desc, int G, float* charges,
-    size_t stride, int* head_box, int* tail_box, long long* head_val, long long* tail_val) {
+    size_t stride, int* head_box, int* tail_box, float* head_val, float* tail_val) {
+  __shared__ int seg_all[kRangeWaves][kRange + 1];
+  int* seg = seg_all[wave_id()];
   const int lane = lane_id();
-  const u64 le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+  const u64 below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
   const int nranges = (n + kRange - 1) / kRange;
-  const int nw = blockDim.x / kWave;
-  for (int r = blockIdx.x * nw + wave_id(); r < nranges; r += gridDim.x * nw) {
+  const int nw = gridDim.x * kRangeWaves;
+  for (int r = blockIdx.x * kRangeWaves + wave_id(); r < nranges; r += nw) {
     const int p0 = r * kRange;
     const int p1 = p0 + kRange < n ? p0 + kRange : n;
-    if (lane == 0) {
-      head_box[r] = -1;
-      tail_box[r] = -1;
-    }
-    long long carry[kVals];
-#pragma unroll
-    for (int q = 0; q < kVals; ++q) carry[q] = 0;
-    int carry_key = -1, carry_start = p0;
-    for (int sp = p0; sp < p1; sp += kWave) {
-      const int p = sp + lane;
+    int nseg = 0;
+    for (int c = p0; c < p1; c += kWave) {
+      const int p = c + lane;
       const bool valid = p < p1;
-      const int key = valid ? skeys[p] : -2 - lane;
-      long long v[kVals];
+      const int key = skeys[min(p, p1 - 1)];
+      const int prev = skeys[max(min(p, p1 - 1) - 1, 0)];
+      const bool start = valid && (p == p0 || key != prev);
+      const u64 m = __ballot(start);
+      if (start) seg[nseg + __popcll(m & below)] = p;
+      nseg += __popcll(m);
+    }
+    if (lane == 0) seg[nseg] = p1;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane == 0) {  // which end pieces of the range are partials
+      const int k0 = skeys[p0], kl = skeys[p1 - 1];
+      const bool whole0 = box_off[k0] == p0 && box_off[k0 + 1] == seg[1];
+      const bool wholel = box_off[kl] == seg[nseg - 1] && box_off[kl + 1] == p1;
+      head_box[r] = whole0 ? -1 : k0;
+      tail_box[r] = (nseg > 1 && !wholel) ? kl : -1;
+    }
+    for (int s0 = 0; s0 < nseg; s0 += kWave) {
+      const int s = s0 + lane;
+      const bool mine = s < nseg;
+      const int a = mine ? seg[s] : 0, b = mine ? seg[s + 1] : 0;
+      if (mine && b - a < kLongSeg) {
+        const int key = skeys[a];
+        const BoxAt bx = box_at(desc, G, key);
+        float acc[kVals];
 #pragma unroll
-      for (int q = 0; q < kVals; ++q) v[q] = 0;
-      int g = 0, bx = 0, by = 0;
-      if (valid) {
-        g = G == 1 ? 0 : graph_of_box(desc, G, key);
-        const GridDesc d = desc[g];
-        const int local = key - d.box_base;
-        by = local / d.n_int;
-        bx = local - by * d.n_int;
-        const float2 x = Xs[p];
-        const float s = (x.x - d.x0) / d.h - (float)bx;
-        const float t = (x.y - d.y0) / d.h - (float)by;
-        float lx[3], ly[3];
-        lagrange3(s, lx);
-        lagrange3(t, ly);
-        const float inv_half = 1.0f / d.half;
-        const float q1 = (x.x - d.cx) * inv_half, q2 = (x.y - d.cy) * inv_half;
-#pragma unroll
-        for (int ty = 0; ty < 3; ++ty)
-#pragma unroll
-          for (int tx = 0; tx < 3; ++tx) {
-            const float w = ly[ty] * lx[tx];
-            const int k = (ty * 3 + tx) * 3;
-            v[k + 0] = __float2int_rn(fminf(fmaxf(w, -4.0f), 4.0f) * kFixScale);
-            v[k + 1] = __float2int_rn(fminf(fmaxf(w * q1, -4.0f), 4.0f) * kFixScale);
-            v[k + 2] = __float2int_rn(fminf(fmaxf(w * q2, -4.0f), 4.0f) * kFixScale);
-          }
+        for (int q = 0; q < kVals; ++q) acc[q] = 0.f;
+        add_points(Xs, bx, a, b, 1, acc);
+        emit(box_off, bx, key, a, b, s, r, charges, stride, head_val, tail_val, acc);
       }
-      const int prev_key = __shfl_up(key, 1, kWave);
-      const bool head = lane == 0 ? key != carry_key : key != prev_key;
-      if (lane == 0 && !head) {
+      u64 todo = __ballot(mine && b - a >= kLongSeg);
+      while (todo) {
+        const int src = __ffsll((long long)todo) - 1;
+        todo &= todo - 1;
+        const int la = __shfl(a, src, kWave), lb = __shfl(b, src, kWave);
+        const int key = skeys[la];
+        const BoxAt bx = box_at(desc, G, key);
+        float acc[kVals];
 #pragma unroll
-        for (int q = 0; q < kVals; ++q) v[q] += carry[q];
+        for (int q = 0; q < kVals; ++q) acc[q] = 0.f;
+        if (la + lane < lb) add_points(Xs, bx, la + lane, lb, kWave, acc);
+#pragma unroll
+        for (int q = 0; q < kVals; ++q) acc[q] = wave_sum_to_last(acc[q]);
+        if (lane == kWave - 1)
+          emit(box_off, bx, key, la, lb, s0 + src, r, charges, stride, head_val, tail_val, acc);
       }
-      // segmented inclusive scan: (v, h) combine as h2 ? v2 : v1 + v2
-      bool h = head;
-#pragma unroll
-      for (int o = 1; o < kWave; o <<= 1) {
-        const bool hh = __shfl_up(h, o, kWave);
-        const bool take = lane >= o && !h;
-#pragma unroll
-        for (int q = 0; q < kVals; ++q) {
-          const long long vv = __shfl_up(v[q], o, kWave);
-          if (take) v[q] += vv;
-        }
-        if (lane >= o) h = h || hh;
-      }
-      const u64 heads = __ballot(head);
-      const u64 hb = heads & le;
-      const int seg_start = hb ? sp + 63 - __clzll(hb) : carry_start;
-      // key of the next sorted point (lane 63 looks into the next step)
-      int next_key = __shfl_down(key, 1, kWave);
-      if (lane == kWave - 1) next_key = p + 1 < p1 ? skeys[p + 1] : -1;
-      const bool last_pt = p == p1 - 1;
-      const bool ends = valid && (last_pt || next_key != key);
-      if (ends) {
-        const GridDesc d = desc[g];
-        const int bs = box_off[key], be = box_off[key + 1];
-        float* out = charges + (size_t)g * stride;
-        if (seg_start == bs && p == be - 1) {
-          node_store(out, d.ng, bx, by, v);
-        } else if (seg_start == p0) {
-          head_box[r] = key;
-#pragma unroll
-          for (int q = 0; q < kVals; ++q) head_val[(size_t)r * kVals + q] = v[q];
-        } else {
-          tail_box[r] = key;
-#pragma unroll
-          for (int q = 0; q < kVals; ++q) tail_val[(size_t)r * kVals + q] = v[q];
-        }
-      }
-      // the segment of lane 63 continues into the next step
-#pragma unroll
-      for (int q = 0; q < kVals; ++q) carry[q] = __shfl(v[q], kWave - 1, kWave);
-      carry_key = __shfl(key, kWave - 1, kWave);
-      carry_start = __shfl(seg_start, kWave - 1, kWave);
     }
   }
 }
 
 // Phase 2: empty boxes get zero nodes, boxes whose points span several
-// ranges add up the head and tail partials of those ranges (integer sums, so
-// the order does not matter). Boxes that phase 1 wrote whole are skipped.
-// One thread per box; a box spanning more than kDenseRanges ranges (a dense
-// cluster of points) is summed by its whole wave instead, lanes over ranges.
+// ranges add up the partials of those ranges in FP64, in range order. Boxes
+// that phase 1 wrote whole are skipped. One lane per box; a box spanning more
+// than kDenseRanges ranges is summed by its whole wave instead, lanes over
+// ranges, lane sums joined in a fixed order.
 constexpr int kDenseRanges = 4;
 
-__device__ __forceinline__ const long long* partial_of(int r, int b, const int* head_box,
-                                                       const long long* head_val,
-                                                       const long long* tail_val) {
+__device__ __forceinline__ const float* partial_of(int r, int b, const int* head_box,
+                                                   const float* head_val, const float* tail_val) {
   return head_box[r] == b ? head_val + (size_t)r * kVals : tail_val + (size_t)r * kVals;
 }
 
 __global__ __launch_bounds__(256) void k_spread_boxes(
     const int* __restrict__ box_off, const int* __restrict__ btotal,
     const GridDesc* __restrict__ desc, int G, float* charges, size_t stride,
-    const int* __restrict__ head_box, const int* __restrict__ tail_box,
-    const long long* __restrict__ head_val, const long long* __restrict__ tail_val) {
+    const int* __restrict__ head_box, const float* __restrict__ head_val,
+    const float* __restrict__ tail_val) {
   const int B = *btotal;
   const int lane = lane_id();
   const int nwaves = gridDim.x * (blockDim.x / kWave);
@@ -348,19 +388,16 @@ __global__ __launch_bounds__(256) void k_spread_boxes(
     const bool mine = b < B && !(be > bs && r0 == r1);  // not written whole by phase 1
     const bool dense = mine && r1 - r0 >= kDenseRanges;
     if (mine && !dense) {
-      long long acc[kVals];
+      double acc[kVals];
 #pragma unroll
-      for (int q = 0; q < kVals; ++q) acc[q] = 0;
+      for (int q = 0; q < kVals; ++q) acc[q] = 0.0;
       for (int r = r0; r <= r1; ++r) {
-        const long long* src = partial_of(r, b, head_box, head_val, tail_val);
+        const float* src = partial_of(r, b, head_box, head_val, tail_val);
 #pragma unroll
-        for (int q = 0; q < kVals; ++q) acc[q] += src[q];
+        for (int q = 0; q < kVals; ++q) acc[q] += (double)src[q];
       }
-      const int g = G == 1 ? 0 : graph_of_box(desc, G, b);
-      const GridDesc d = desc[g];
-      const int local = b - d.box_base;
-      const int by = local / d.n_int, bx = local - by * d.n_int;
-      node_store(charges + (size_t)g * stride, d.ng, bx, by, acc);
+      const BoxAt bx = box_at(desc, G, b);
+      node_store(charges + (size_t)bx.g * stride, bx.d.ng, bx.bx, bx.by, acc);
     }
     u64 todo = __ballot(dense);
     while (todo) {
@@ -368,22 +405,19 @@ __global__ __launch_bounds__(256) void k_spread_boxes(
       todo &= todo - 1;
       const int bd = __shfl(b, src_lane, kWave);
       const int d0 = __shfl(r0, src_lane, kWave), d1 = __shfl(r1, src_lane, kWave);
-      long long acc[kVals];
+      double acc[kVals];
 #pragma unroll
-      for (int q = 0; q < kVals; ++q) acc[q] = 0;
+      for (int q = 0; q < kVals; ++q) acc[q] = 0.0;
       for (int r = d0 + lane; r <= d1; r += kWave) {
-        const long long* src = partial_of(r, bd, head_box, head_val, tail_val);
+        const float* src = partial_of(r, bd, head_box, head_val, tail_val);
 #pragma unroll
-        for (int q = 0; q < kVals; ++q) acc[q] += src[q];
+        for (int q = 0; q < kVals; ++q) acc[q] += (double)src[q];
       }
 #pragma unroll
       for (int q = 0; q < kVals; ++q) acc[q] = wave_sum(acc[q]);
       if (lane == 0) {
-        const int g = G == 1 ? 0 : graph_of_box(desc, G, bd);
-        const GridDesc d = desc[g];
-        const int local = bd - d.box_base;
-        const int by = local / d.n_int, bx = local - by * d.n_int;
-        node_store(charges + (size_t)g * stride, d.ng, bx, by, acc);
+        const BoxAt bx = box_at(desc, G, bd);
+        node_store(charges + (size_t)bx.g * stride, bx.d.ng, bx.bx, bx.by, acc);
       }
     }
   }
@@ -392,16 +426,15 @@ __global__ __launch_bounds__(256) void k_spread_boxes(
 hipError_t launch_spread(Problem& P, const float2* X, hipStream_t s) {
   (void)X;
   const int nranges = (P.n + kRange - 1) / kRange;
-  int blocks = (nranges + 3) / 4;
+  int blocks = (nranges + kRangeWaves - 1) / kRangeWaves;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_spread_ranges, dim3(blocks), dim3(256), 0, s, P.xs, P.skeys, P.n, P.box_off,
-                     P.desc, P.G, P.charges, P.stride_charges, P.head_box, P.tail_box, P.head_val,
-                     P.tail_val);
+  hipLaunchKernelGGL(k_spread_ranges, dim3(blocks), dim3(kRangeWaves * kWave), 0, s, P.xs, P.skeys,
+                     P.n, P.box_off, P.desc, P.G, P.charges, P.stride_charges, P.head_box,
+                     P.tail_box, P.head_val, P.tail_val);
   int bblocks = (P.G * P.cap * P.cap + 255) / 256;
   if (bblocks > 8192) bblocks = 8192;
   hipLaunchKernelGGL(k_spread_boxes, dim3(bblocks), dim3(256), 0, s, P.box_off, P.btotal, P.desc,
-                     P.G, P.charges, P.stride_charges, P.head_box, P.tail_box, P.head_val,
-                     P.tail_val);
+                     P.G, P.charges, P.stride_charges, P.head_box, P.head_val, P.tail_val);
   return hipGetLastError();
 }
 

@@ -12,6 +12,39 @@ constexpr int kWave = 64;
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 __device__ __forceinline__ int wave_id() { return threadIdx.x / kWave; }
 
+// Cross-lane moves as DPP operand modifiers (VALU, no LDS traffic). Controls: row_shr:n / row_shl:n shift within rows of 16 lanes, row_bcast:15
+// and :31 carry the last lane of a row (of rows 0-1) into the next row (rows
+// 2-3), wave_shr:1 / wave_shl:1 shift by one lane across the whole wave.
+// Lanes without a source keep `old`.
+constexpr int kDppRowShr = 0x110;
+constexpr int kDppRowShl1 = 0x101;
+constexpr int kDppRowBcast15 = 0x142;
+constexpr int kDppRowBcast31 = 0x143;
+constexpr int kDppWaveShl1 = 0x130;
+constexpr int kDppWaveShr1 = 0x138;
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_i(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_f(float old, float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL,
+                                                    ROWS, 0xF, false));
+}
+
+// Sum over the wave, in a fixed order, left in lane 63 (an inclusive prefix
+// sum by DPP row shifts and row broadcasts; other lanes hold partial sums).
+__device__ __forceinline__ float wave_sum_to_last(float v) {
+  v += dpp_f<kDppRowShr | 1, 0xF>(0.f, v);
+  v += dpp_f<kDppRowShr | 2, 0xF>(0.f, v);
+  v += dpp_f<kDppRowShr | 4, 0xF>(0.f, v);
+  v += dpp_f<kDppRowShr | 8, 0xF>(0.f, v);
+  v += dpp_f<kDppRowBcast15, 0xA>(0.f, v);
+  v += dpp_f<kDppRowBcast31, 0xC>(0.f, v);
+  return v;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll

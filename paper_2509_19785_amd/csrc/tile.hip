@@ -133,28 +133,6 @@ __device__ __forceinline__ void flush(int row, float x, float y, int head, int w
   }
 }
 
-// Cross-lane moves of the scans below as DPP operand modifiers (VALU, no LDS
-// traffic). Controls: row_shr:n / row_shl:n shift within rows of 16 lanes, row_bcast:15
-// and :31 carry the last lane of a row (of rows 0-1) into the next row (rows
-// 2-3), wave_shr:1 / wave_shl:1 shift by one lane across the whole wave.
-// Lanes without a source keep `old`.
-constexpr int kDppRowShr = 0x110;
-constexpr int kDppRowShl1 = 0x101;
-constexpr int kDppRowBcast15 = 0x142;
-constexpr int kDppRowBcast31 = 0x143;
-constexpr int kDppWaveShl1 = 0x130;
-constexpr int kDppWaveShr1 = 0x138;
-
-template <int CTRL, int ROWS>
-__device__ __forceinline__ int dpp_i(int old, int v) {
-  return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xF, false);
-}
-template <int CTRL, int ROWS>
-__device__ __forceinline__ float dpp_f(float old, float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL,
-                                                    ROWS, 0xF, false));
-}
-
 // One step of the segmented inclusive scan: add the partial sums that the
 // move brings in when they belong to the same slot (keys are sorted along
 // the wave, so equal end points mean one segment).

@@ -18,13 +18,12 @@ constexpr int kMaxNg = kNodes * kMaxIntervals;
 constexpr int kMaxM = 2 * kMaxNg;         // FFT length per axis (3 * 2^b)
 constexpr int kPotCh = 8;                 // interleaved potential channels per node
 constexpr int kCostTerms = 4;             // chunk sums of the cost reduction
+constexpr int kSpreadRange = 1024;        // sorted points per wave in the spread
 constexpr int kChunk = 2048;              // vertices per chunk of per-vertex kernels
 constexpr int kMaxK = 1024;               // neighbours per vertex in tsnet_build_P
 constexpr double kSpanFloor = 1e-4;       // smallest grid span (degenerate layouts)
-constexpr float kFixScale = 268435456.0f; // 2^28: fixed-point scale of spread contributions
 constexpr int kBinTileH = 2048;           // points per tile of the binning radix sort
 constexpr int kBinDigitBits = 9;          // digit width of the binning radix sort
-constexpr int kSpreadRange = 256;         // sorted points per wave in the spread
 constexpr int kRadixTile = 2048;          // elements per block tile of the LSD radix sort
 constexpr int kTileMaxRows = 4096;        // rows per row tile of the tiled attraction
 constexpr int kTileSlotBits = 12;         // bits of a row slot inside a tile
@@ -134,10 +133,6 @@ struct Problem {
   float2* xs = nullptr;               // [n] X in sorted order
   int* bin_hist = nullptr;            // [256 tiles + 1] digit counts, then offsets
   int* bin_tsum = nullptr;            // scan scratch
-  int* head_box = nullptr;            // [spread ranges] box of the leading partial
-  int* tail_box = nullptr;            // [spread ranges] box of the trailing partial
-  long long* head_val = nullptr;      // [spread ranges][27]
-  long long* tail_val = nullptr;      // [spread ranges][27]
   int* box_off = nullptr;             // [G cap^2 + 1] first sorted slot of every box
   float* charges = nullptr;           // per graph 3 ng^2
   float2* qspec = nullptr;            // per graph [3][ng][M/2+1] row spectra of the charges
@@ -148,6 +143,10 @@ struct Problem {
   float2* ospec = nullptr;            // per graph [8][ng][M/2+1] the same, transposed
   float* pot = nullptr;               // per graph ng^2 * 8
   size_t stride_charges = 0, stride_qspec = 0, stride_kspec = 0, stride_ospec = 0, stride_pot = 0;
+  int* head_box = nullptr;            // [spread ranges] box of the leading partial, -1 if none
+  int* tail_box = nullptr;            // [spread ranges] box of the trailing partial, -1 if none
+  float* head_val = nullptr;          // [spread ranges][27]
+  float* tail_val = nullptr;          // [spread ranges][27]
   float4* rep_ent = nullptr;          // [n] (F_rep.x, F_rep.y, F_ent.x, F_ent.y) of each vertex
   float* zi = nullptr;                // [n]
   float* lnv = nullptr;               // [n] interpolated sum_j ln(eps + r^2) (cost path)
