@@ -78,6 +78,92 @@ def cpu_baseline(X: np.ndarray, budget_s: float = 12.0):
     }
 
 
+# --------------------------------------------------------------------------- per-kernel table
+FIXED_GRID_STDS = (6.0, 12.0)   # layouts N(0, std^2): 256 and 512 intervals at n = 1e6
+FIXED_GRID_EVALS = 20
+
+
+def fixed_grids(info_path: str):
+    """Gradient evaluations (each followed by a step on a copy, so the layout and
+    its grid stay fixed) at two fixed layouts of the benchmark problem, for a
+    kernel trace; writes the sizes the per-kernel table needs to info_path."""
+    import torch
+    from synth import graphs
+    from paper_2509_19785_amd import api
+    g = graphs.workload_ba1m()
+    ctx = api.Context(0)
+    dev = torch.device("cuda", 0)
+    prob = api.Problem.build(ctx, torch.as_tensor(g.indptr).to(dev), torch.as_tensor(g.indices).to(dev),
+                             40.0, seed=3)
+    prm, sp = api.Params(), api.StepParams()
+    info = {"n": prob.n, "nnz": prob.nnz, "phases": []}
+    for std in FIXED_GRID_STDS:
+        X = torch.tensor(graphs.initial_layout(g.n, 1, std=std), device=dev)
+        upd, gains = torch.zeros_like(X), torch.ones_like(X)
+        G, Z = torch.empty_like(X), torch.empty(1, dtype=torch.float64, device=dev)
+        for _ in range(FIXED_GRID_EVALS):
+            prob.grad(X, prm, G=G, Z=Z)
+            prob.step(X.clone(), upd, gains, G, 300, sp)
+        torch.cuda.synchronize()
+        ni = int(prob.grid_info()["n_intervals"][0])
+        info["phases"].append({"std": std, "n_int": ni, "evals": FIXED_GRID_EVALS})
+        log(f"fixed layout std={std}: {ni} intervals")
+    with open(info_path, "w") as f:
+        json.dump(info, f)
+
+
+def kernel_algorithmic_bytes(kernel: str, n: int, nnz: int, ni: int):
+    """Compulsory HBM bytes of one launch of each per-iteration kernel at n
+    vertices, nnz nonzeros and ni intervals per axis (N_g = 3 ni nodes, M = 6 ni)."""
+    ng, Mh = 3 * ni, 3 * ni + 1
+    return {
+        "k_attract_tiled": 8 * nnz + 40 * n + 8,
+        "k_bbox_plan": 8 * n,
+        "k_bin_keys": 12 * n,
+        "k_box_bounds": 12 * ng * ng,                         # clears the 3 charge grids
+        "k_spread_ranges": 12 * n + 12 * ng * ng,
+        "k_gather": 40 * n + 32 * ng * ng,
+        "k_fft_rows_fwd": 12 * ng * ng + 3 * ng * Mh * 8 + 4 * Mh * Mh * 4,
+        "k_fft_cols": 3 * ng * Mh * 8 + 4 * Mh * Mh * 4 + 7 * Mh * ng * 8,
+        "k_fft_rows_inv": 7 * Mh * ng * 8 + 32 * ng * ng,
+        "k_step": 56 * n,
+    }.get(kernel)
+
+
+def kernel_table(trace_csv: str, info_path: str):
+    """Markdown table of the per-iteration kernels from a rocprofv3 kernel trace
+    of --fixed-grids: mean duration per layout, algorithmic bytes, GB/s and the
+    fraction of the 8 TB/s HBM peak."""
+    import collections
+    import csv
+    info = json.load(open(info_path))
+    n, nnz, phases = info["n"], info["nnz"], info["phases"]
+    seq = collections.defaultdict(list)
+    for r in csv.DictReader(open(trace_csv)):
+        name = r["Kernel_Name"]
+        name = name[:name.index("(")] if "(" in name else name
+        name = name.replace("void ", "").replace("tsnet::", "")
+        seq[name].append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    per_eval = len(phases) * FIXED_GRID_EVALS
+    print("| kernel | intervals | launches | mean us | algorithmic bytes | GB/s | of 8 TB/s |")
+    print("|---|---:|---:|---:|---:|---:|---:|")
+    for k in sorted(seq, key=lambda x: -sum(d for _, d in seq[x])):
+        v = sorted(seq[k])
+        if len(v) < per_eval or len(v) % per_eval:
+            continue  # not a once-per-iteration kernel of this workload
+        per = len(v) // len(phases)
+        for p, ph in enumerate(phases):
+            d = [x[1] for x in v[p * per:(p + 1) * per]]
+            avg_us = sum(d) / len(d) / 1e3
+            b = kernel_algorithmic_bytes(k, n, nnz, ph["n_int"])
+            if b:
+                gbs = b / (avg_us * 1e-6) / 1e9
+                print(f"| {k} | {ph['n_int']} | {len(d)} | {avg_us:.1f} | {b:,} | {gbs:.0f} | "
+                      f"{gbs / HBM_PEAK_GBS:.2f} |")
+            else:
+                print(f"| {k} | {ph['n_int']} | {len(d)} | {avg_us:.1f} | | | |")
+
+
 # --------------------------------------------------------------------------- GPU
 def main():
     ap = argparse.ArgumentParser()
@@ -88,13 +174,27 @@ def main():
     ap.add_argument("--direct-iters", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-intervals", type=int, default=512)
+    ap.add_argument("--runs", type=int, default=5,
+                    help="timed runs from the initial layout (plain launches); value is their mean")
+    ap.add_argument("--last", type=int, default=100,
+                    help="the rate of the last LAST steps of every run is reported beside the whole-run rate")
     ap.add_argument("--graph-steps", type=int, default=0,
                     help="iterations per captured HIP graph in the timed region (0: plain launches; "
                          "graph replays measured slower than plain launches on ROCm 7, and event "
                          "times read from graph nodes are not usable)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 5 device copies of 1 GiB (reference for the HBM traffic counters)")
+    ap.add_argument("--fixed-grids", metavar="INFO_JSON",
+                    help="only run gradient evaluations at two fixed layouts (for a kernel trace)")
+    ap.add_argument("--kernel-table", nargs=2, metavar=("TRACE_CSV", "INFO_JSON"),
+                    help="only print the per-kernel roofline table of a --fixed-grids trace")
     args = ap.parse_args()
+    if args.kernel_table:
+        kernel_table(*args.kernel_table)
+        return
+    if args.fixed_grids:
+        fixed_grids(args.fixed_grids)
+        return
     if args.calibrate_copy:
         import torch
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -138,7 +238,8 @@ def main():
     log(f"build_P: nnz={prob.nnz} in {build_ms:.1f} ms")
     del ip, ix
 
-    X = torch.tensor(X0, device=dev)
+    X0d = torch.tensor(X0, device=dev)
+    X = X0d.clone()
     upd = torch.zeros_like(X)
     gains = torch.ones_like(X)
     G = torch.empty_like(X)
@@ -149,10 +250,16 @@ def main():
         prob.grad(X, prm, G=G, Z=Z, stream=stream)
         prob.step(X, upd, gains, G, it, sp, stream=stream)
 
+    def restart():
+        X.copy_(X0d)
+        upd.zero_()
+        gains.fill_(1.0)
+
     for it in range(args.warmup):
         one(it)
     torch.cuda.synchronize()
     log(f"warmup done, status {ctx.status():#x}")
+    last = max(1, min(args.last, args.steps))
 
     # timed region: events only around the dominant kernel
     K = args.graph_steps
@@ -186,16 +293,38 @@ def main():
         st = ctx.stage_times()  # the events in the graphs hold their last replay
         ctx.set_timing(None)
         del g_early, g_late
+        run_rates, last_rates = [args.steps / wall], []
     else:
-        ctx.set_timing(["attract_assemble"])
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for it in range(args.warmup, args.warmup + args.steps):
-            one(it)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        st = ctx.stage_times()
-        ctx.set_timing(None)
+        # every run starts from the initial layout: warmup steps untimed, then
+        # exactly --steps steps between two device synchronisations
+        run_rates, last_rates, attr_ms, attr_calls = [], [], 0.0, 0
+        for r in range(max(1, args.runs)):
+            if r > 0:
+                restart()
+                for it in range(args.warmup):
+                    one(it)
+            ev_last = torch.cuda.Event(enable_timing=True)
+            ev_end = torch.cuda.Event(enable_timing=True)
+            ctx.set_timing(["attract_assemble"])
+            ctx.stage_times()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for it in range(args.warmup, args.warmup + args.steps):
+                if it == args.warmup + args.steps - last:
+                    ev_last.record(stream)
+                one(it)
+            ev_end.record(stream)
+            torch.cuda.synchronize()
+            w = time.perf_counter() - t0
+            a_ms, a_calls = ctx.stage_times()["attract_assemble"]
+            ctx.set_timing(None)
+            attr_ms += a_ms
+            attr_calls += a_calls
+            run_rates.append(args.steps / w)
+            last_rates.append(last / (ev_last.elapsed_time(ev_end) * 1e-3))
+            log(f"run {r}: {run_rates[-1]:.1f} iters/s, last {last} steps {last_rates[-1]:.1f} iters/s")
+        st = {"attract_assemble": (attr_ms, attr_calls)}
+        wall = args.steps / (sum(run_rates) / len(run_rates))
     ms_per_step = wall / args.steps * 1e3
     iters_per_s = args.steps / wall
     attr_ms, attr_calls = st["attract_assemble"]
@@ -219,6 +348,24 @@ def main():
     Xh = X.cpu().numpy()
     span = float((Xh.max(0) - Xh.min(0)).max())
     log("stages (ms/call): " + ", ".join(f"{k} {v:.4f}" for k, v in stages.items()))
+
+    # grid of every iteration of one run (replayed untimed: reading it synchronises)
+    restart()
+    grid_ni, grid_span = [], []
+    for it in range(args.warmup + args.steps):
+        one(it)
+        g_i = prob.grid_info()
+        grid_ni.append(int(g_i["n_intervals"][0]))
+        grid_span.append(float(g_i["n_intervals"][0]) * float(g_i["box_side"][0]))
+    log("grid per iteration (it span n_int M): " + "; ".join(
+        f"{i} {grid_span[i]:.2f} {grid_ni[i]} {6 * grid_ni[i]}" for i in range(len(grid_ni))))
+    timed_ni = grid_ni[args.warmup:]
+    ni_runs = []
+    for v in timed_ni:
+        if ni_runs and ni_runs[-1][0] == v:
+            ni_runs[-1][1] += 1
+        else:
+            ni_runs.append([v, 1])
 
     # FP64 direct all-pairs baseline on the same problem and layout
     direct = None
@@ -283,6 +430,21 @@ def main():
             "launches_timed": attr_calls,
         },
         "cpu_baseline": cpu,
+        "runs": {
+            "count": len(run_rates),
+            "iters_per_s": run_rates,
+            "mean": float(np.mean(run_rates)),
+            "sd": float(np.std(run_rates, ddof=1)) if len(run_rates) > 1 else 0.0,
+            "last_steps": last,
+            "last_iters_per_s": last_rates,
+            "last_mean": float(np.mean(last_rates)) if last_rates else None,
+        },
+        "grid_timed_steps": {
+            "n_intervals_runs": ni_runs,
+            "fft_length_M": "6 * n_intervals",
+            "span_min": float(min(grid_span[args.warmup:])),
+            "span_max": float(max(grid_span[args.warmup:])),
+        },
         "build_P_ms": build_ms,
         "stages_ms": stages,
         "direct_f64": direct,

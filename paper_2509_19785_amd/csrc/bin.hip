@@ -13,7 +13,8 @@
 // range in FP32 in a fixed order (a lane per short piece, the whole wave for a
 // long one); whole boxes go straight to their nodes, the pieces at the two
 // ends of a range are kept as partials. Phase 2 adds the partials of boxes
-// that span ranges, in range order, and clears empty boxes.
+// that span ranges, in range order. Empty boxes keep the zeros written while
+// the box offsets are found.
 #include <hip/hip_runtime.h>
 
 #include "dev_util.h"
@@ -126,16 +127,30 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const int* __restrict__ kin
 
 // box_off[b] = first sorted slot with key >= b, for b in [0, btotal]
 // (a binary search per box, so long runs of empty boxes cost nothing extra).
+// The same launch clears the charge grids of every graph with 16-byte stores,
+// so the spread writes only the boxes that hold points.
 __global__ __launch_bounds__(256) void k_box_bounds(const int* __restrict__ skeys, int n,
-                                                    const int* __restrict__ btotal, int* box_off) {
+                                                    const int* __restrict__ btotal, int* box_off,
+                                                    const GridDesc* __restrict__ desc, int G,
+                                                    float* charges, size_t stride) {
   const int B = *btotal;
-  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b <= B; b += gridDim.x * blockDim.x) {
+  const int t0 = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
+  for (int b = t0; b <= B; b += nt) {
     int lo = 0, hi = n;
     while (lo < hi) {
       const int m = (lo + hi) >> 1;
       if (skeys[m] < b) lo = m + 1; else hi = m;
     }
     box_off[b] = lo;
+  }
+  for (int g = 0; g < G; ++g) {
+    const size_t len = (size_t)3 * desc[g].ng * desc[g].ng;  // floats of the graph's 3 grids
+    float* base = charges + (size_t)g * stride;
+    // stride is a multiple of 4 floats whenever the grid cap is 2 or more
+    const size_t len4 = (stride % 4 == 0) ? len / 4 : 0;
+    float4* b4 = reinterpret_cast<float4*>(base);
+    for (size_t k = t0; k < len4; k += nt) b4[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (size_t k = 4 * len4 + t0; k < len; k += nt) base[k] = 0.f;
   }
 }
 
@@ -177,7 +192,9 @@ hipError_t launch_bin(Problem& P, const float2* X, hipStream_t s) {
   }
   int bb = (P.G * P.cap * P.cap + 1 + 255) / 256;
   if (bb > 4096) bb = 4096;
-  hipLaunchKernelGGL(k_box_bounds, dim3(bb), dim3(256), 0, s, P.skeys, n, P.btotal, P.box_off);
+  if (bb < 1024) bb = 1024;  // enough threads for the grid clearing
+  hipLaunchKernelGGL(k_box_bounds, dim3(bb), dim3(256), 0, s, P.skeys, n, P.btotal, P.box_off,
+                     P.desc, P.G, P.charges, P.stride_charges);
   return hipGetLastError();
 }
 
@@ -352,9 +369,9 @@ __global__ __launch_bounds__(kRangeWaves * kWave) void k_spread_ranges(
   }
 }
 
-// Phase 2: empty boxes get zero nodes, boxes whose points span several
-// ranges add up the partials of those ranges in FP64, in range order. Boxes
-// that phase 1 wrote whole are skipped. One lane per box; a box spanning more
+// Phase 2: boxes whose points span several ranges add up the partials of
+// those ranges in FP64, in range order. Empty boxes keep the zeros the
+// binning wrote; boxes that phase 1 wrote whole are skipped. One lane per box; a box spanning more
 // than kDenseRanges ranges is summed by its whole wave instead, lanes over
 // ranges, lane sums joined in a fixed order.
 constexpr int kDenseRanges = 4;
@@ -385,7 +402,7 @@ __global__ __launch_bounds__(256) void k_spread_boxes(
         r1 = (be - 1) / kRange;
       }
     }
-    const bool mine = b < B && !(be > bs && r0 == r1);  // not written whole by phase 1
+    const bool mine = b < B && be > bs && r0 != r1;  // holds points, not written whole by phase 1
     const bool dense = mine && r1 - r0 >= kDenseRanges;
     if (mine && !dense) {
       double acc[kVals];
