@@ -25,6 +25,7 @@ namespace tsnet {
 
 typedef unsigned long long u64;
 constexpr int kBinTile = 2048;
+constexpr int kBinRounds = kBinTile / 256;  // points per thread of a tile
 constexpr int kDigitBits = kBinDigitBits;
 constexpr int kDigits = 1 << kDigitBits;   // buckets per pass
 
@@ -44,12 +45,15 @@ __global__ __launch_bounds__(256) void k_bin_keys(const float2* __restrict__ X, 
   for (int q = threadIdx.x; q < kDigits; q += 256) cnt[q] = 0;
   __syncthreads();
   const int base = blockIdx.x * kBinTile;
-  for (int q = threadIdx.x; q < kBinTile; q += 256) {
-    const int i = base + q;
+  float2 p[kBinRounds];  // every load of the tile issued before any is used
+#pragma unroll
+  for (int r = 0; r < kBinRounds; ++r) p[r] = X[min(base + r * 256 + (int)threadIdx.x, n - 1)];
+#pragma unroll
+  for (int r = 0; r < kBinRounds; ++r) {
+    const int i = base + r * 256 + threadIdx.x;
     if (i < n) {
       const int g = G == 1 ? 0 : graph_of(goff, G, i);
-      const float2 p = X[i];
-      const int key = box_key(desc[g], p.x, p.y);
+      const int key = box_key(desc[g], p[r].x, p[r].y);
       keys[i] = key;
       atomicAdd(&cnt[key & (kDigits - 1)], 1);
     }
@@ -64,10 +68,12 @@ __global__ __launch_bounds__(256) void k_bin_hist(const int* __restrict__ keys, 
   for (int q = threadIdx.x; q < kDigits; q += 256) cnt[q] = 0;
   __syncthreads();
   const int base = blockIdx.x * kBinTile;
-  for (int q = threadIdx.x; q < kBinTile; q += 256) {
-    const int i = base + q;
-    if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & (kDigits - 1)], 1);
-  }
+  int k[kBinRounds];  // every load of the tile issued before any is used
+#pragma unroll
+  for (int r = 0; r < kBinRounds; ++r) k[r] = keys[min(base + r * 256 + (int)threadIdx.x, n - 1)];
+#pragma unroll
+  for (int r = 0; r < kBinRounds; ++r)
+    if (base + r * 256 + (int)threadIdx.x < n) atomicAdd(&cnt[(k[r] >> shift) & (kDigits - 1)], 1);
   __syncthreads();
   for (int q = threadIdx.x; q < kDigits; q += 256) hist[q * tiles + blockIdx.x] = cnt[q];
 }
@@ -89,15 +95,27 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const int* __restrict__ kin
   __syncthreads();
   const u64 lt = (1ull << lane) - 1ull;
   const int base = blockIdx.x * kBinTile;
-  for (int round = 0; round < kBinTile / 256; ++round) {
+  // the tile's keys and payloads (and on the last pass the X rows they name)
+  // are loaded before the first round: one memory latency per tile, not one
+  // per round
+  int kr[kBinRounds], vr[kBinRounds];
+#pragma unroll
+  for (int r = 0; r < kBinRounds; ++r) {
+    const int ic = min(base + r * 256 + tid, n - 1);
+    kr[r] = kin[ic];
+    vr[r] = vin ? vin[ic] : ic;
+  }
+  float2 xr[kBinRounds];
+  if (Xs) {
+#pragma unroll
+    for (int r = 0; r < kBinRounds; ++r) xr[r] = X[vr[r]];
+  }
+#pragma unroll
+  for (int round = 0; round < kBinRounds; ++round) {
     const int i = base + round * 256 + tid;
     const bool valid = i < n;
-    int key = 0, val = 0, dg = 0;
-    if (valid) {
-      key = kin[i];
-      val = vin ? vin[i] : i;
-      dg = (key >> shift) & (kDigits - 1);
-    }
+    const int key = kr[round], val = vr[round];
+    const int dg = valid ? (key >> shift) & (kDigits - 1) : 0;
     const u64 vb = __ballot(valid);
     u64 peers = valid ? vb : ~vb;
 #pragma unroll
@@ -114,7 +132,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const int* __restrict__ kin
       for (int q = 0; q < w; ++q) pos += wc[q][dg];
       kout[pos] = key;
       vout[pos] = val;
-      if (Xs) Xs[pos] = X[val];
+      if (Xs) Xs[pos] = xr[round];
     }
     __syncthreads();
     for (int d = tid; d < kDigits; d += 256) {

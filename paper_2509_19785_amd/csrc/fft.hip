@@ -24,10 +24,11 @@
 //
 // The transforms are Stockham autosort FFTs over LDS (fft_core.h): radix-16
 // passes (the last power-of-two pass 8, 4 or 2) and one radix-12 pass, each
-// butterfly an in-register DFT. Each block owns two padded LDS buffers of
-// kFftElems complex values and the M twiddles of its transform length
-// (copied from the context's table once per block); sequences of length M
-// share a block kFftElems / M at a time.
+// butterfly an in-register DFT; every pass reads the buffer into registers,
+// synchronises and writes back in place. Each block owns one padded LDS
+// buffer of kFftElems complex values and the first M / 2 twiddles of its
+// transform length (copied from the context's table once per block);
+// sequences of length M share a block kFftElems / M at a time.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -40,22 +41,18 @@ namespace tsnet {
 
 constexpr int kFftElems = kMaxM;              // complex values per transform buffer
 constexpr int kFftBuf = kFftElems + kFftElems / 16;  // the same, padded (one spare slot per 16)
-constexpr int kFftLds = (kFftBuf + kFftElems / 4) * 8;  // bytes of LDS per FFT block: buffer + quarter twiddles
+constexpr int kFftLds = (kFftBuf + kFftElems / 2) * 8;  // bytes of LDS per FFT block: buffer + half twiddles
 constexpr int kFftThreads = 256;
 constexpr int kPerThread = kFftElems / kFftThreads;  // register slots per thread
 
-// nb sequences of length L (= 3 * 2^b, nb L <= kFftElems) at a[pad(s L + i)];
-// `b` is the ping-pong buffer; tw holds e^{-2 pi i m / L}, m < L (in LDS).
-// sgn = -1 forward, +1 inverse (unnormalised). Returns the buffer holding the
-// result. Must be reached by every thread of the block.
-// e^{-2 pi i m / L} from the quarter table tq[r] = e^{-2 pi i r / L}, r < L / 4
-// (L a multiple of 4; the one length that is not, L = 6, uses no twiddles).
-__device__ __forceinline__ float2 twq(const float2* tq, int m, int L) {
-  const int q4 = L >> 2;
-  const int q = m / q4, r = m - q * q4;
-  const float2 t = tq[r];
-  const float2 u = (q & 1) ? make_float2(t.y, -t.x) : t;  // times -i for odd q
-  return (q & 2) ? make_float2(-u.x, -u.y) : u;           // times -1 for q >= 2
+// e^{-2 pi i m / L}, 0 <= m < L, from the half table th[r] = e^{-2 pi i r / L},
+// r < L / 2 (the second half is the negated first half).
+template <int L>
+__device__ __forceinline__ float2 twh(const float2* th, int m) {
+  constexpr int h = L / 2;
+  const bool hi = m >= h;
+  const float2 t = th[hi ? m - h : m];
+  return hi ? make_float2(-t.x, -t.y) : t;
 }
 
 // One Stockham pass of radix R over sub-length NS, in place: every thread
@@ -63,9 +60,11 @@ __device__ __forceinline__ float2 twq(const float2* tq, int m, int L) {
 // synchronises, then the results are written back to the same buffer.
 // Index arithmetic as in fft_pass (fft_core.h); where the input stride L/R
 // and the output stride NS are multiples of 16 the padded addresses are a
-// base plus constant offsets.
-template <int R, int L, int NS>
-__device__ __forceinline__ void pass_ip(float2* buf, int nb, const float2* tq, float sgn) {
+// base plus constant offsets. INV: inverse transform (conjugate twiddles),
+// fixed at compile time so the sign folds into the arithmetic.
+template <int R, int L, int NS, bool INV>
+__device__ __forceinline__ void pass_ip(float2* buf, int nb, const float2* th) {
+  constexpr float sgn = INV ? 1.f : -1.f;
   constexpr int nbut = L / R;
   constexpr int tstep = L / (NS * R);
   constexpr int BPT = (kFftElems / R + kFftThreads - 1) / kFftThreads;
@@ -89,11 +88,11 @@ __device__ __forceinline__ void pass_ip(float2* buf, int nb, const float2* tq, f
 #pragma unroll
         for (int r = 0; r < R; ++r) v[u][r] = buf[fft_pad(ib + r * nbut)];
       }
-      if (k > 0) {
+      if (k > 0) {  // k r tstep < NS R tstep = L
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          float2 w = twq(tq, k * r * tstep, L);
-          if (sgn > 0.f) w.y = -w.y;
+          float2 w = twh<L>(th, k * r * tstep);
+          if constexpr (INV) w.y = -w.y;
           v[u][r] = fmulc(v[u][r], w);
         }
       }
@@ -118,53 +117,62 @@ __device__ __forceinline__ void pass_ip(float2* buf, int nb, const float2* tq, f
 }
 
 // The passes of fft_plan for a length known at compile time.
-template <int L, int NS, int P2>
+template <int L, int NS, int P2, bool INV>
 struct FftPasses {
-  __device__ __forceinline__ static void run(float2* buf, int nb, const float2* tq, float sgn) {
+  __device__ __forceinline__ static void run(float2* buf, int nb, const float2* th) {
     if constexpr (P2 > 1) {
       constexpr int R = P2 >= 16 ? 16 : P2;
-      pass_ip<R, L, NS>(buf, nb, tq, sgn);
-      FftPasses<L, NS * R, P2 / R>::run(buf, nb, tq, sgn);
+      pass_ip<R, L, NS, INV>(buf, nb, th);
+      FftPasses<L, NS * R, P2 / R, INV>::run(buf, nb, th);
     } else {
-      pass_ip<L / NS, L, NS>(buf, nb, tq, sgn);  // the radix-12 (6, 3) pass
+      pass_ip<L / NS, L, NS, INV>(buf, nb, th);  // the radix-12 (6, 3) pass
     }
   }
 };
 
-// One length per function, not inlined into the callers: the kernels pick
-// the length at run time (it comes from the grid plan on the device), and
-// inlining every length into one body inflates the register allocation.
-template <int L>
-__device__ __noinline__ void fft_len(float2* buf, int nb, const float2* tq, float sgn) {
+// One length and direction per function, not inlined into the callers: the
+// kernels pick the length at run time (it comes from the grid plan on the
+// device), and inlining every length into one body inflates the register
+// allocation.
+template <int L, bool INV>
+__device__ __noinline__ void fft_len(float2* buf, int nb, const float2* th) {
   constexpr int p2 = L / 3;
   constexpr int r3 = p2 >= 4 ? 12 : (p2 == 2 ? 6 : 3);
-  FftPasses<L, 1, p2 / (r3 / 3)>::run(buf, nb, tq, sgn);
+  FftPasses<L, 1, p2 / (r3 / 3), INV>::run(buf, nb, th);
 }
 
-// nb sequences of length L (= 6 * 2^a <= kFftElems, nb L <= kFftElems) at
-// buf[pad(s L + i)], transformed in place; tq is the quarter twiddle table
-// of length L in LDS. sgn = -1 forward, +1 inverse (unnormalised). Must be
-// reached by every thread of the block.
-__device__ void block_fft(float2* buf, int nb, int L, const float2* tq, float sgn) {
+template <bool INV>
+__device__ void block_fft_dir(float2* buf, int nb, int L, const float2* th) {
   switch (L) {
-    case 3072: fft_len<3072>(buf, nb, tq, sgn); break;
-    case 1536: fft_len<1536>(buf, nb, tq, sgn); break;
-    case 768: fft_len<768>(buf, nb, tq, sgn); break;
-    case 384: fft_len<384>(buf, nb, tq, sgn); break;
-    case 192: fft_len<192>(buf, nb, tq, sgn); break;
-    case 96: fft_len<96>(buf, nb, tq, sgn); break;
-    case 48: fft_len<48>(buf, nb, tq, sgn); break;
-    case 24: fft_len<24>(buf, nb, tq, sgn); break;
-    case 12: fft_len<12>(buf, nb, tq, sgn); break;
-    default: fft_len<6>(buf, nb, tq, sgn); break;
+    case 3072: fft_len<3072, INV>(buf, nb, th); break;
+    case 1536: fft_len<1536, INV>(buf, nb, th); break;
+    case 768: fft_len<768, INV>(buf, nb, th); break;
+    case 384: fft_len<384, INV>(buf, nb, th); break;
+    case 192: fft_len<192, INV>(buf, nb, th); break;
+    case 96: fft_len<96, INV>(buf, nb, th); break;
+    case 48: fft_len<48, INV>(buf, nb, th); break;
+    case 24: fft_len<24, INV>(buf, nb, th); break;
+    case 12: fft_len<12, INV>(buf, nb, th); break;
+    default: fft_len<6, INV>(buf, nb, th); break;
   }
 }
 
-// The first quarter of the twiddles of length M from the context table
-// (length kMaxM) into LDS.
-__device__ __forceinline__ void load_twiddles(float2* tq, const float2* __restrict__ tw, int M) {
+// nb sequences of length L (= 6 * 2^a <= kFftElems, nb L <= kFftElems) at
+// buf[pad(s L + i)], transformed in place; th is the half twiddle table of
+// length L in LDS. sgn = -1 forward, +1 inverse (unnormalised). Must be
+// reached by every thread of the block.
+__device__ __forceinline__ void block_fft(float2* buf, int nb, int L, const float2* th, float sgn) {
+  if (sgn > 0.f)
+    block_fft_dir<true>(buf, nb, L, th);
+  else
+    block_fft_dir<false>(buf, nb, L, th);
+}
+
+// The first half of the twiddles of length M from the context table (length
+// kMaxM) into LDS.
+__device__ __forceinline__ void load_twiddles(float2* th, const float2* __restrict__ tw, int M) {
   const int step = kMaxM / M;
-  for (int m = threadIdx.x; m < (M >> 2); m += blockDim.x) tq[m] = tw[m * step];
+  for (int m = threadIdx.x; m < (M >> 1); m += blockDim.x) th[m] = tw[m * step];
 }
 
 struct FftArgs {
@@ -197,7 +205,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_fwd(FftArgs A) {
   const GridDesc d = A.desc[g];
   const int M = d.M, ng = d.ng, Mh = M / 2 + 1;
   float2* bufA = lds;
-  float2* twl = lds + kFftBuf;  // quarter twiddle table
+  float2* twl = lds + kFftBuf;  // half twiddle table
   load_twiddles(twl, A.tw, M);
   const int S = kFftElems / M;  // sequences per block iteration (>= 1)
   const int nseq = 2 * ng + 2 * Mh;
@@ -316,7 +324,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_cols(FftArgs A) {
   const int M = d.M, ng = d.ng, Mh = M / 2 + 1;
   const int S = kFftElems / M;  // columns per block iteration
   float2* B0 = lds;
-  float2* twl = lds + kFftBuf;  // quarter twiddle table
+  float2* twl = lds + kFftBuf;  // half twiddle table
   load_twiddles(twl, A.tw, M);
   const float2* qt = A.qt + (size_t)g * A.s_q;
   const float* kt = A.kt + (size_t)g * A.s_k;
@@ -400,7 +408,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_inv(FftArgs A) {
   const GridDesc d = A.desc[g];
   const int M = d.M, ng = d.ng, Mh = M / 2 + 1;
   float2* bufA = lds;
-  float2* twl = lds + kFftBuf;  // quarter twiddle table
+  float2* twl = lds + kFftBuf;  // half twiddle table
   load_twiddles(twl, A.tw, M);
   const int S = kFftElems / M;
   const int jobs = ng * 4;
