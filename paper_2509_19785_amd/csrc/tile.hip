@@ -120,16 +120,17 @@ struct Carry {
 
 // Adds a finished row sum: into the tile accumulator, or into the wave's
 // parking slot when the row began in the previous wave's piece.
-__device__ __forceinline__ void flush(int row, float x, float y, int head, int wv, float2* acc,
+__device__ __forceinline__ void flush(int row, float x, float y, int head, int wv, float4* rec,
                                       int* hrow, float2* hval) {
   if (row == head) {
     hrow[wv] = row;
     hval[wv] = make_float2(x, y);
   } else {
-    float2 v = acc[row];
+    float2* acc = reinterpret_cast<float2*>(&rec[row].z);
+    float2 v = *acc;
     v.x += x;
     v.y += y;
-    acc[row] = v;
+    *acc = v;
   }
 }
 
@@ -152,14 +153,15 @@ __device__ __forceinline__ void seg_step(int key, float& sx, float& sy) {
 // is added to the tile accumulator at once, the lane's first and last slots
 // go through the scan across lanes below.
 __device__ __forceinline__ void tile_pass(const uint2 (&e)[kTileRun], int cnt, bool more, int lane,
-                                          int wv, int head, const float2* win, const float2* xrow,
-                                          float2* acc, int* hrow, float2* hval, Carry& cr) {
+                                          int wv, int head, const float2* win, float4* rec,
+                                          int* hrow, float2* hval, Carry& cr) {
   int r[kTileRun];
-  float2 xi[kTileRun], xj[kTileRun];
+  float4 ri[kTileRun];  // (x_i, sum so far) of the entry's row: one 16-byte read
+  float2 xj[kTileRun];
 #pragma unroll
   for (int k = 0; k < kTileRun; ++k) {  // all LDS reads in flight together
     r[k] = (int)(e[k].x >> kTileColBits);
-    xi[k] = xrow[r[k]];
+    ri[k] = rec[r[k]];
     xj[k] = win[e[k].x & (kTileCols - 1)];
   }
   const int r0 = r[0];
@@ -172,7 +174,7 @@ __device__ __forceinline__ void tile_pass(const uint2 (&e)[kTileRun], int cnt, b
   bool put[kTileRun];
 #pragma unroll
   for (int k = 0; k < kTileRun; ++k) {
-    const float dx = xi[k].x - xj[k].x, dy = xi[k].y - xj[k].y;
+    const float dx = ri[k].x - xj[k].x, dy = ri[k].y - xj[k].y;
     const float w = __uint_as_float(e[k].y) * __builtin_amdgcn_rcpf(1.0f + dx * dx + dy * dy);
     const bool valid = k < cnt;
     const bool same = k > 0 && r[k] == r[k - 1];
@@ -189,15 +191,13 @@ __device__ __forceinline__ void tile_pass(const uint2 (&e)[kTileRun], int cnt, b
     put[k] = ends && r[k] != r0 && r[k] != rl;
     own[k] = make_float2(cx, cy);
   }
-  // no other lane or wave touches those slots in this window: all their reads
-  // go out together (slots of the clamped tail entries are valid indices and
-  // are read but not written), then the writes
-  float2 old[kTileRun];
-#pragma unroll
-  for (int k = 0; k < kTileRun; ++k) old[k] = acc[r[k]];
+  // no other lane or wave touches those slots in this window, so the sums
+  // read with x_i above are current (slots of the clamped tail entries are
+  // valid indices and are read but not written)
 #pragma unroll
   for (int k = 0; k < kTileRun; ++k)
-    if (put[k]) acc[r[k]] = make_float2(old[k].x + own[k].x, old[k].y + own[k].y);
+    if (put[k])
+      *reinterpret_cast<float2*>(&rec[r[k]].z) = make_float2(ri[k].z + own[k].x, ri[k].w + own[k].y);
   const int frow = cnt > 0 && r0 != rl ? r0 : -1;
   const int cur = rl;
   // the last run of every lane: segmented inclusive scan over the lanes
@@ -220,7 +220,7 @@ __device__ __forceinline__ void tile_pass(const uint2 (&e)[kTileRun], int cnt, b
     pk = cr.row;
     px = cr.x;
     py = cr.y;
-    if (cr.row >= 0 && first != cr.row) flush(cr.row, cr.x, cr.y, head, wv, acc, hrow, hval);
+    if (cr.row >= 0 && first != cr.row) flush(cr.row, cr.x, cr.y, head, wv, rec, hrow, hval);
   }
   if (frow >= 0) {  // a lane with several runs: its first run ends here
     float tx = fx, ty = fy;
@@ -228,14 +228,14 @@ __device__ __forceinline__ void tile_pass(const uint2 (&e)[kTileRun], int cnt, b
       tx += px;
       ty += py;
     }
-    flush(frow, tx, ty, head, wv, acc, hrow, hval);
+    flush(frow, tx, ty, head, wv, rec, hrow, hval);
   }
   int nf = dpp_i<kDppWaveShl1, 0xF>(kTileNone, first);
   const float lx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sx), kWave - 1));
   const float ly = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sy), kWave - 1));
   const int lk = __builtin_amdgcn_readlane(key, kWave - 1);
   if (lane == kWave - 1) nf = more ? -2 : kTileNone;  // -2: the next pass decides
-  if (cnt > 0 && nf != key && nf != -2) flush(key, sx, sy, head, wv, acc, hrow, hval);
+  if (cnt > 0 && nf != key && nf != -2) flush(key, sx, sy, head, wv, rec, hrow, hval);
   if (more) {
     cr.row = lk;
     cr.x = lx;
@@ -248,8 +248,7 @@ __device__ __forceinline__ void tile_pass(const uint2 (&e)[kTileRun], int cnt, b
 __global__ __launch_bounds__(kTileThreads) void k_attract_tiled(TileArgs a) {
   constexpr int PRE = kTileCols / kTileThreads;
   __shared__ float2 win[kTileCols];
-  __shared__ float2 xrow[kTileMaxRows];
-  __shared__ float2 acc[kTileMaxRows];
+  __shared__ float4 rec[kTileMaxRows];  // per slot: x_i and the row's attraction sum
   __shared__ int hrow[kTileWaves];
   __shared__ float2 hval[kTileWaves];
   __shared__ int bst[kTileMaxNC + 1];
@@ -271,8 +270,7 @@ __global__ __launch_bounds__(kTileThreads) void k_attract_tiled(TileArgs a) {
     for (int q = 0; q < kTileRowsPerThread; ++q) {
       const int s = q * kTileThreads + tid;
       if (s < R) {
-        xrow[s] = iv[q] >= 0 ? xv[q] : make_float2(0.f, 0.f);
-        acc[s] = make_float2(0.f, 0.f);
+        rec[s] = iv[q] >= 0 ? make_float4(xv[q].x, xv[q].y, 0.f, 0.f) : make_float4(0.f, 0.f, 0.f, 0.f);
       }
     }
 #pragma unroll
@@ -319,7 +317,7 @@ __global__ __launch_bounds__(kTileThreads) void k_attract_tiled(TileArgs a) {
 #pragma unroll
         for (int k = 0; k < kTileRun; ++k) e2[k] = a.ent[min(s1 + k, a.last)];
       }
-      tile_pass(ec, cnt, two, lane, wv, head, win, xrow, acc, hrow, hval, cr);
+      tile_pass(ec, cnt, two, lane, wv, head, win, rec, hrow, hval, cr);
       for (int base = pc.p0 + kPass; base < pc.p1; base += kPass) {
         uint2 cur[kTileRun];
 #pragma unroll
@@ -332,7 +330,7 @@ __global__ __launch_bounds__(kTileThreads) void k_attract_tiled(TileArgs a) {
 #pragma unroll
           for (int k = 0; k < kTileRun; ++k) e2[k] = a.ent[min(s1 + k, a.last)];
         }
-        tile_pass(cur, cc, more, lane, wv, head, win, xrow, acc, hrow, hval, cr);
+        tile_pass(cur, cc, more, lane, wv, head, win, rec, hrow, hval, cr);
       }
     }
     __syncthreads();
@@ -351,10 +349,8 @@ __global__ __launch_bounds__(kTileThreads) void k_attract_tiled(TileArgs a) {
       int nr = dpp_i<kDppRowShl1, 0xF>(-2, r);
       if (lane == kTileWaves - 1) nr = -2;
       if (lane < kTileWaves && r >= 0 && nr != r) {
-        float2 q = acc[r];
-        q.x += v.x;
-        q.y += v.y;
-        acc[r] = q;
+        float2* q = reinterpret_cast<float2*>(&rec[r].z);
+        *q = make_float2(q->x + v.x, q->y + v.y);
       }
       if (lane < kTileWaves) hrow[lane] = -1;
     }
@@ -380,7 +376,8 @@ __global__ __launch_bounds__(kTileThreads) void k_attract_tiled(TileArgs a) {
   for (int q = 0; q < kTileRowsPerThread; ++q) {
     const int s = q * kTileThreads + tid, i = iv[q];
     if (i < 0) continue;
-    const float2 f = acc[s], xi = xrow[s];
+    const float4 rs = rec[s];
+    const float2 f = make_float2(rs.z, rs.w), xi = make_float2(rs.x, rs.y);
     const int g = a.G == 1 ? 0 : graph_of(a.goff, a.G, i);
     const double Z = a.zg[g];
     const float inv_z = Z > 0.0 ? (float)(1.0 / Z) : 0.0f;
