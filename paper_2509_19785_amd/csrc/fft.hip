@@ -199,7 +199,7 @@ struct FftArgs {
 // Row transforms of the charges and kernels. Sequence s of a graph:
 //   s < 2 ng:        charge row s / 2, part s % 2 (0: q0 + i q1, 1: q2)
 //   otherwise:       kernel row (s - 2 ng) / 2 in [0, M/2], part (0: K2 + i K1, 1: Ke + i Kln)
-__global__ __launch_bounds__(kFftThreads) void k_fft_rows_fwd(FftArgs A) {
+__global__ __launch_bounds__(kFftThreads, 4) void k_fft_rows_fwd(FftArgs A) {
   extern __shared__ float2 lds[];
   const int g = blockIdx.y;
   const GridDesc d = A.desc[g];
@@ -215,33 +215,57 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_fwd(FftArgs A) {
   const float sp = d.spacing;
   for (int s0 = blockIdx.x * S; s0 < nseq; s0 += gridDim.x * S) {
     const int ns = nseq - s0 < S ? nseq - s0 : S;
-    for (int idx = threadIdx.x; idx < ns * M; idx += blockDim.x) {
-      const int sl = idx / M, x = idx - sl * M;
-      const int sq = s0 + sl;
-      float2 v;
-      if (sq < 2 * ng) {
+    if (s0 + ns <= 2 * ng) {
+      // charge rows only: every load is issued before any is used
+      float2 vin[kPerThread];
+#pragma unroll
+      for (int q = 0; q < kPerThread; ++q) {
+        const int idx = threadIdx.x + q * kFftThreads;
+        vin[q] = make_float2(0.f, 0.f);
+        if (idx >= ns * M) continue;
+        const int sl = idx / M, x = idx - sl * M;
+        const int sq = s0 + sl;
         const int ry = sq >> 1, part = sq & 1;
         if (x < ng) {
           const size_t o = (size_t)ry * ng + x;
-          v = part == 0 ? make_float2(ch[o], ch[(size_t)ng * ng + o])
-                        : make_float2(ch[2 * (size_t)ng * ng + o], 0.f);
-        } else {
-          v = make_float2(0.f, 0.f);
-        }
-      } else {
-        const int t = sq - 2 * ng;
-        const int ry = t >> 1, part = t & 1;
-        const int xi = x < M - x ? x : M - x;
-        const float dy = (float)ry * sp, dx = (float)xi * sp;
-        const float r2 = dy * dy + dx * dx;
-        if (part == 0) {
-          const float w = 1.0f / (1.0f + r2);
-          v = make_float2(w * w, w);
-        } else {
-          v = make_float2(1.0f / (A.eps + r2), A.with_ln ? logf(A.eps + r2) : 0.f);
+          vin[q] = part == 0 ? make_float2(ch[o], ch[(size_t)ng * ng + o])
+                             : make_float2(ch[2 * (size_t)ng * ng + o], 0.f);
         }
       }
-      bufA[fft_pad(idx)] = v;
+#pragma unroll
+      for (int q = 0; q < kPerThread; ++q) {
+        const int idx = threadIdx.x + q * kFftThreads;
+        if (idx < ns * M) bufA[fft_pad(idx)] = vin[q];
+      }
+    } else {
+      for (int idx = threadIdx.x; idx < ns * M; idx += blockDim.x) {
+        const int sl = idx / M, x = idx - sl * M;
+        const int sq = s0 + sl;
+        float2 v;
+        if (sq < 2 * ng) {
+          const int ry = sq >> 1, part = sq & 1;
+          if (x < ng) {
+            const size_t o = (size_t)ry * ng + x;
+            v = part == 0 ? make_float2(ch[o], ch[(size_t)ng * ng + o])
+                          : make_float2(ch[2 * (size_t)ng * ng + o], 0.f);
+          } else {
+            v = make_float2(0.f, 0.f);
+          }
+        } else {  // kernel rows, generated
+          const int t = sq - 2 * ng;
+          const int ry = t >> 1, part = t & 1;
+          const int xi = x < M - x ? x : M - x;
+          const float dy = (float)ry * sp, dx = (float)xi * sp;
+          const float r2 = dy * dy + dx * dx;
+          if (part == 0) {
+            const float w = 1.0f / (1.0f + r2);
+            v = make_float2(w * w, w);
+          } else {
+            v = make_float2(1.0f / (A.eps + r2), A.with_ln ? logf(A.eps + r2) : 0.f);
+          }
+        }
+        bufA[fft_pad(idx)] = v;
+      }
     }
     __syncthreads();
     block_fft(bufA, ns, M, twl, -1.f);
@@ -417,21 +441,32 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_inv(FftArgs A) {
   const float scale = 1.0f / ((float)M * (float)M);
   for (int j0 = blockIdx.x * S; j0 < jobs; j0 += gridDim.x * S) {
     const int nj = jobs - j0 < S ? jobs - j0 : S;
-    for (int idx = threadIdx.x; idx < nj * M; idx += blockDim.x) {
+    // every load of the block's jobs is issued before any is used
+    float2 f0[kPerThread], f1[kPerThread];
+#pragma unroll
+    for (int q = 0; q < kPerThread; ++q) {
+      const int idx = threadIdx.x + q * kFftThreads;
+      f0[q] = f1[q] = make_float2(0.f, 0.f);
+      if (idx >= nj * M) continue;
       const int jl = idx / M, k = idx - jl * M;
       const int job = j0 + jl;
       const int ry = job >> 2, pr = job & 3;
       const int o0 = 2 * pr, o1 = 2 * pr + 1;
-      const bool conj_ = k > M / 2;
-      const int kk = conj_ ? M - k : k;
-      float2 f0 = orr[((size_t)o0 * ng + ry) * Mh + kk];
-      float2 f1 = (o1 == CH_KLN_1 && !A.with_ln) ? make_float2(0.f, 0.f)
-                                                  : orr[((size_t)o1 * ng + ry) * Mh + kk];
-      if (conj_) {
-        f0.y = -f0.y;
-        f1.y = -f1.y;
+      const int kk = k > M / 2 ? M - k : k;
+      f0[q] = orr[((size_t)o0 * ng + ry) * Mh + kk];
+      if (!(o1 == CH_KLN_1 && !A.with_ln)) f1[q] = orr[((size_t)o1 * ng + ry) * Mh + kk];
+    }
+#pragma unroll
+    for (int q = 0; q < kPerThread; ++q) {
+      const int idx = threadIdx.x + q * kFftThreads;
+      if (idx >= nj * M) continue;
+      const int k = idx - (idx / M) * M;
+      float2 a = f0[q], b = f1[q];
+      if (k > M / 2) {  // conjugate half of the Hermitian spectra
+        a.y = -a.y;
+        b.y = -b.y;
       }
-      bufA[fft_pad(idx)] = make_float2(f0.x - f1.y, f0.y + f1.x);
+      bufA[fft_pad(idx)] = make_float2(a.x - b.y, a.y + b.x);
     }
     __syncthreads();
     block_fft(bufA, nj, M, twl, +1.f);
