@@ -44,6 +44,8 @@ constexpr int kFftBuf = kFftElems + kFftElems / 16;  // the same, padded (one sp
 constexpr int kFftLds = (kFftBuf + kFftElems / 2) * 8;  // bytes of LDS per FFT block: buffer + half twiddles
 constexpr int kFftThreads = 256;
 constexpr int kPerThread = kFftElems / kFftThreads;  // register slots per thread
+constexpr int kColBatch = 4;                         // loads in flight per thread in the column stage
+static_assert(kPerThread % kColBatch == 0, "whole batches");
 
 // e^{-2 pi i m / L}, 0 <= m < L, from the half table th[r] = e^{-2 pi i r / L},
 // r < L / 2 (the second half is the negated first half).
@@ -341,7 +343,7 @@ __global__ __launch_bounds__(256) void k_fft_transpose(FftArgs A, int which) {
 }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kFftThreads) void k_fft_cols(FftArgs A) {
+__global__ __launch_bounds__(kFftThreads, 3) void k_fft_cols(FftArgs A) {
   extern __shared__ float2 lds[];
   const int g = blockIdx.y;
   const GridDesc d = A.desc[g];
@@ -360,11 +362,24 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_cols(FftArgs A) {
     float kh[4][kPerThread];
     // kernel spectra: two packed real columns per transform, kept in registers
     for (int pair = 0; pair < 2; ++pair) {
-      for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-        const int col = idx / M, y = idx - col * M;
-        const int ry = y < M - y ? y : M - y;
-        const size_t o = (size_t)(c0 + col) * Mh + ry;
-        B0[fft_pad(idx)] = make_float2(kt[(size_t)(2 * pair) * Mh * Mh + o], kt[(size_t)(2 * pair + 1) * Mh * Mh + o]);
+      // loads in groups of kColBatch in flight (registers are scarce here)
+#pragma unroll 1
+      for (int q0 = 0; q0 < kPerThread; q0 += kColBatch) {
+        float2 t[kColBatch];
+#pragma unroll
+        for (int j = 0; j < kColBatch; ++j) {
+          const int idx = threadIdx.x + (q0 + j) * kFftThreads;
+          if (idx >= tot) continue;
+          const int col = idx / M, y = idx - col * M;
+          const int ry = y < M - y ? y : M - y;
+          const size_t o = (size_t)(c0 + col) * Mh + ry;
+          t[j] = make_float2(kt[(size_t)(2 * pair) * Mh * Mh + o], kt[(size_t)(2 * pair + 1) * Mh * Mh + o]);
+        }
+#pragma unroll
+        for (int j = 0; j < kColBatch; ++j) {
+          const int idx = threadIdx.x + (q0 + j) * kFftThreads;
+          if (idx < tot) B0[fft_pad(idx)] = t[j];
+        }
       }
       __syncthreads();
       block_fft(B0, ncc, M, twl, -1.f);
@@ -379,9 +394,20 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_cols(FftArgs A) {
       __syncthreads();
     }
     for (int c = 0; c < 3; ++c) {
-      for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-        const int col = idx / M, y = idx - col * M;
-        B0[fft_pad(idx)] = y < ng ? qt[((size_t)c * Mh + c0 + col) * ng + y] : make_float2(0.f, 0.f);
+#pragma unroll 1
+      for (int q0 = 0; q0 < kPerThread; q0 += kColBatch) {
+        float2 t[kColBatch];
+#pragma unroll
+        for (int j = 0; j < kColBatch; ++j) {
+          const int idx = threadIdx.x + (q0 + j) * kFftThreads;
+          const int col = idx / M, y = idx - col * M;
+          t[j] = (idx < tot && y < ng) ? qt[((size_t)c * Mh + c0 + col) * ng + y] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int j = 0; j < kColBatch; ++j) {
+          const int idx = threadIdx.x + (q0 + j) * kFftThreads;
+          if (idx < tot) B0[fft_pad(idx)] = t[j];
+        }
       }
       __syncthreads();
       block_fft(B0, ncc, M, twl, -1.f);
