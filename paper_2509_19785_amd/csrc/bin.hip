@@ -332,13 +332,19 @@ __global__ __launch_bounds__(kRangeWaves * kWave) void k_spread_ranges(
   for (int r = blockIdx.x * kRangeWaves + wave_id(); r < nranges; r += nw) {
     const int p0 = r * kRange;
     const int p1 = p0 + kRange < n ? p0 + kRange : n;
+    // the range's keys, all loads in flight together; the key before a
+    // point comes from the neighbouring lane
+    constexpr int kSteps = kRange / kWave;
+    int kv[kSteps];
+#pragma unroll
+    for (int j = 0; j < kSteps; ++j) kv[j] = skeys[min(p0 + j * kWave + lane, p1 - 1)];
     int nseg = 0;
-    for (int c = p0; c < p1; c += kWave) {
-      const int p = c + lane;
-      const bool valid = p < p1;
-      const int key = skeys[min(p, p1 - 1)];
-      const int prev = skeys[max(min(p, p1 - 1) - 1, 0)];
-      const bool start = valid && (p == p0 || key != prev);
+#pragma unroll
+    for (int j = 0; j < kSteps; ++j) {
+      const int p = p0 + j * kWave + lane;  // steps past the range end find no start
+      const int carry = j > 0 ? __builtin_amdgcn_readlane(kv[j > 0 ? j - 1 : 0], kWave - 1) : -1;
+      const int prev = dpp_i<kDppWaveShr1, 0xF>(carry, kv[j]);
+      const bool start = p < p1 && (p == p0 || kv[j] != prev);
       const u64 m = __ballot(start);
       if (start) seg[nseg + __popcll(m & below)] = p;
       nseg += __popcll(m);

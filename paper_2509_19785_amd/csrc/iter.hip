@@ -22,6 +22,7 @@ namespace tsnet {
 // of every chunk go to part[chunk] and the last block to finish plans the
 // grids. One counter update per chunk: many more blocks would queue on it.
 constexpr int kChunkThreads = 1024;
+constexpr int kPartBatch = 8;  // chunk partials a lane of the final reduction loads at once
 
 __global__ __launch_bounds__(kChunkThreads) void k_bbox_plan(
     const float2* __restrict__ X, const int* __restrict__ chunk_start,
@@ -78,14 +79,22 @@ __global__ __launch_bounds__(kChunkThreads) void k_bbox_plan(
   for (int g = wave_id(); g < G; g += blockDim.x / kWave) {
     float a = FLT_MAX, b = -FLT_MAX, e = FLT_MAX, f = -FLT_MAX;
     int nonfinite = 0;
-    for (int k = gi[g].chunk_begin + lane_id(); k < gi[g].chunk_end; k += kWave) {
-      const float4 q = ld_coherent4(&part[k]);
-      if (isnan(q.x)) nonfinite = 1;
-      if (q.y >= q.x) {  // chunk had at least one finite point
-        a = fminf(a, q.x);
-        b = fmaxf(b, q.y);
-        e = fminf(e, q.z);
-        f = fmaxf(f, q.w);
+    const int c1 = gi[g].chunk_end;
+    for (int k0 = gi[g].chunk_begin + lane_id(); k0 < c1; k0 += kPartBatch * kWave) {
+      float4 q[kPartBatch];  // the batch's loads in flight together
+#pragma unroll
+      for (int j = 0; j < kPartBatch; ++j)
+        q[j] = k0 + j * kWave < c1 ? ld_coherent4(&part[k0 + j * kWave])
+                                   : make_float4(FLT_MAX, -FLT_MAX, FLT_MAX, -FLT_MAX);
+#pragma unroll
+      for (int j = 0; j < kPartBatch; ++j) {
+        if (isnan(q[j].x)) nonfinite = 1;
+        if (q[j].y >= q[j].x) {  // chunk had at least one finite point
+          a = fminf(a, q[j].x);
+          b = fmaxf(b, q[j].y);
+          e = fminf(e, q[j].z);
+          f = fmaxf(f, q[j].w);
+        }
       }
     }
     a = wave_min(a);
@@ -245,8 +254,15 @@ __global__ __launch_bounds__(kChunkThreads) void k_gather(
   __threadfence();
   for (int gg = wave_id(); gg < G; gg += blockDim.x / kWave) {
     double z = 0.0;
-    for (int k = gi[gg].chunk_begin + lane_id(); k < gi[gg].chunk_end; k += kWave)
-      z += ld_coherent(&zpart[k]);
+    const int c1 = gi[gg].chunk_end;
+    for (int k0 = gi[gg].chunk_begin + lane_id(); k0 < c1; k0 += kPartBatch * kWave) {
+      double q[kPartBatch];  // the batch's loads in flight together
+#pragma unroll
+      for (int j = 0; j < kPartBatch; ++j)
+        q[j] = k0 + j * kWave < c1 ? ld_coherent(&zpart[k0 + j * kWave]) : 0.0;
+#pragma unroll
+      for (int j = 0; j < kPartBatch; ++j) z += q[j];
+    }
     z = wave_sum(z);
     if (lane_id() == 0) {
       zg[gg] = z;
