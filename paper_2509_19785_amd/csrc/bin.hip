@@ -395,14 +395,40 @@ __global__ __launch_bounds__(kRangeWaves * kWave) void k_spread_ranges(
 
 // Phase 2: boxes whose points span several ranges add up the partials of
 // those ranges in FP64, in range order. Empty boxes keep the zeros the
-// binning wrote; boxes that phase 1 wrote whole are skipped. One lane per box; a box spanning more
-// than kDenseRanges ranges is summed by its whole wave instead, lanes over
-// ranges, lane sums joined in a fixed order.
+// binning wrote; boxes that phase 1 wrote whole are skipped. One lane per box;
+// a box spanning kDenseRanges ranges or more is summed by a wave of its own.
 constexpr int kDenseRanges = 4;
 
 __device__ __forceinline__ const float* partial_of(int r, int b, const int* head_box,
                                                    const float* head_val, const float* tail_val) {
   return head_box[r] == b ? head_val + (size_t)r * kVals : tail_val + (size_t)r * kVals;
+}
+
+// The whole wave sums the partials of dense box b (lanes over its ranges, lane
+// sums in FP64 in range order, joined by a DPP reduction in a fixed order).
+__device__ __forceinline__ void spread_dense_box(int b, const int* __restrict__ box_off,
+                                                 const GridDesc* __restrict__ desc, int G,
+                                                 float* charges, size_t stride,
+                                                 const int* __restrict__ head_box,
+                                                 const float* __restrict__ head_val,
+                                                 const float* __restrict__ tail_val) {
+  const int lane = lane_id();
+  const int r0 = box_off[b] / kRange, r1 = (box_off[b + 1] - 1) / kRange;
+  double acc[kVals];
+#pragma unroll
+  for (int q = 0; q < kVals; ++q) acc[q] = 0.0;
+  for (int r = r0 + lane; r <= r1; r += kWave) {
+    const float* src = partial_of(r, b, head_box, head_val, tail_val);
+#pragma unroll
+    for (int q = 0; q < kVals; ++q) acc[q] += (double)src[q];
+  }
+  float tot[kVals];
+#pragma unroll
+  for (int q = 0; q < kVals; ++q) tot[q] = wave_sum_to_last((float)acc[q]);
+  if (lane == kWave - 1) {
+    const BoxAt bx = box_at(desc, G, b);
+    node_store(charges + (size_t)bx.g * stride, bx.d.ng, bx.bx, bx.by, tot);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_spread_boxes(
@@ -413,7 +439,6 @@ __global__ __launch_bounds__(256) void k_spread_boxes(
   const int B = *btotal;
   const int lane = lane_id();
   const int nwaves = gridDim.x * (blockDim.x / kWave);
-  // every lane of a wave runs the same number of rounds (ballots below)
   for (int base = (blockIdx.x * (blockDim.x / kWave) + wave_id()) * kWave; base < B;
        base += nwaves * kWave) {
     const int b = base + lane;
@@ -427,8 +452,7 @@ __global__ __launch_bounds__(256) void k_spread_boxes(
       }
     }
     const bool mine = b < B && be > bs && r0 != r1;  // holds points, not written whole by phase 1
-    const bool dense = mine && r1 - r0 >= kDenseRanges;
-    if (mine && !dense) {
+    if (mine && r1 - r0 < kDenseRanges) {
       double acc[kVals];
 #pragma unroll
       for (int q = 0; q < kVals; ++q) acc[q] = 0.0;
@@ -440,26 +464,24 @@ __global__ __launch_bounds__(256) void k_spread_boxes(
       const BoxAt bx = box_at(desc, G, b);
       node_store(charges + (size_t)bx.g * stride, bx.d.ng, bx.bx, bx.by, acc);
     }
+  }
+  // dense boxes (clustered points) are dealt to waves round-robin, one wave
+  // per box: lanes over its ranges, lane sums (FP64, range order) joined by a
+  // DPP reduction in a fixed order
+  const int gw = blockIdx.x * (blockDim.x / kWave) + wave_id();
+  for (int base = gw; base < B; base += nwaves * kWave) {
+    const int bl = base + lane * nwaves;  // lane l checks box base + l * nwaves
+    bool dense = false;
+    if (bl < B) {
+      const int bs = box_off[bl], be = box_off[bl + 1];
+      dense = be > bs && (be - 1) / kRange - bs / kRange >= kDenseRanges;
+    }
     u64 todo = __ballot(dense);
     while (todo) {
       const int src_lane = __ffsll((long long)todo) - 1;
       todo &= todo - 1;
-      const int bd = __shfl(b, src_lane, kWave);
-      const int d0 = __shfl(r0, src_lane, kWave), d1 = __shfl(r1, src_lane, kWave);
-      double acc[kVals];
-#pragma unroll
-      for (int q = 0; q < kVals; ++q) acc[q] = 0.0;
-      for (int r = d0 + lane; r <= d1; r += kWave) {
-        const float* src = partial_of(r, bd, head_box, head_val, tail_val);
-#pragma unroll
-        for (int q = 0; q < kVals; ++q) acc[q] += (double)src[q];
-      }
-#pragma unroll
-      for (int q = 0; q < kVals; ++q) acc[q] = wave_sum(acc[q]);
-      if (lane == 0) {
-        const BoxAt bx = box_at(desc, G, bd);
-        node_store(charges + (size_t)bx.g * stride, bx.d.ng, bx.bx, bx.by, acc);
-      }
+      const int b = base + src_lane * nwaves;
+      spread_dense_box(b, box_off, desc, G, charges, stride, head_box, head_val, tail_val);
     }
   }
 }
