@@ -20,7 +20,8 @@
 //  transpose: Ot -> Or[o][y][kx].
 //  rows_inv:  two output channels share one complex inverse row transform
 //             (u + i v); the first N_g values of each row, times 1 / M^2, are
-//             the node potentials, stored node-major with 8 channels per node.
+//             the node potentials, stored as 4 planes (one per channel pair) of
+//             N_g x N_g float2 nodes, so each row transform writes contiguously.
 //
 // The transforms are Stockham autosort FFTs over LDS (fft_core.h): radix-16
 // passes (the last power-of-two pass 8, 4 or 2) and one radix-12 pass, each
@@ -502,7 +503,8 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_inv(FftArgs A) {
       const int job = j0 + jl;
       const int ry = job >> 2, pr = job & 3;
       const float2 v = res[fft_pad(jl * M + x)];
-      *reinterpret_cast<float2*>(pg + ((size_t)ry * ng + x) * kPotCh + 2 * pr) =
+      // plane pr of the potentials: contiguous float2 per node
+      reinterpret_cast<float2*>(pg)[(size_t)pr * ng * ng + (size_t)ry * ng + x] =
           make_float2(v.x * scale, v.y * scale);
     }
     __syncthreads();

@@ -201,22 +201,21 @@ __global__ __launch_bounds__(kChunkThreads) void k_gather(
     float phi[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) phi[k] = 0.f;
+    // the potentials are 4 planes (channel pairs) of ng^2 float2 nodes
+    const float2* pl = reinterpret_cast<const float2*>(pg);
+    const size_t plane = (size_t)d.ng * d.ng;
 #pragma unroll
     for (int ty = 0; ty < 3; ++ty) {
-      const float* row = pg + ((size_t)(3 * by + ty) * d.ng + 3 * bx) * kPotCh;
+      const size_t row = (size_t)(3 * by + ty) * d.ng + 3 * bx;
 #pragma unroll
       for (int tx = 0; tx < 3; ++tx) {
         const float w = ly[ty] * lx[tx];
-        const float4 a = *reinterpret_cast<const float4*>(row + tx * kPotCh);
-        const float4 b = *reinterpret_cast<const float4*>(row + tx * kPotCh + 4);
-        phi[0] += w * a.x;
-        phi[1] += w * a.y;
-        phi[2] += w * a.z;
-        phi[3] += w * a.w;
-        phi[4] += w * b.x;
-        phi[5] += w * b.y;
-        phi[6] += w * b.z;
-        phi[7] += w * b.w;
+#pragma unroll
+        for (int pr = 0; pr < kPotCh / 2; ++pr) {
+          const float2 v = pl[pr * plane + row + tx];
+          phi[2 * pr] += w * v.x;
+          phi[2 * pr + 1] += w * v.y;
+        }
       }
     }
     const float xt = x.x - d.cx, yt = x.y - d.cy;

@@ -16,7 +16,7 @@ constexpr int kNodes = 3;                 // interpolation nodes per box and axi
 constexpr int kMaxIntervals = 512;        // boxes per axis (power of two)
 constexpr int kMaxNg = kNodes * kMaxIntervals;
 constexpr int kMaxM = 2 * kMaxNg;         // FFT length per axis (3 * 2^b)
-constexpr int kPotCh = 8;                 // interleaved potential channels per node
+constexpr int kPotCh = 8;                 // potential channels per node (4 planes of pairs)
 constexpr int kCostTerms = 4;             // chunk sums of the cost reduction
 constexpr int kSpreadRange = 1024;        // sorted points per wave in the spread
 constexpr int kChunk = 2048;              // vertices per chunk of per-vertex kernels
@@ -141,7 +141,7 @@ struct Problem {
   float* kspec_t = nullptr;           // per graph the same, transposed
   float2* ospec_t = nullptr;          // per graph [8][M/2+1][ng] products after the column stage
   float2* ospec = nullptr;            // per graph [8][ng][M/2+1] the same, transposed
-  float* pot = nullptr;               // per graph ng^2 * 8
+  float* pot = nullptr;               // per graph 4 planes (channel pairs) of ng^2 float2
   size_t stride_charges = 0, stride_qspec = 0, stride_kspec = 0, stride_ospec = 0, stride_pot = 0;
   int* head_box = nullptr;            // [spread ranges] box of the leading partial, -1 if none
   int* tail_box = nullptr;            // [spread ranges] box of the trailing partial, -1 if none
