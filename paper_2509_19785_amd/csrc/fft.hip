@@ -301,13 +301,14 @@ __global__ __launch_bounds__(kFftThreads, 4) void k_fft_rows_fwd(FftArgs A) {
 
 // ---------------------------------------------------------------------------
 // Tiled transposes in[b][r][c] -> out[b][c][r], r < R, c < C (sizes per graph).
+// Blocks b0, b0 + nblk, ... of the launch take the tiles in turn.
 template <typename T>
 __device__ __forceinline__ void transpose_tiles(const T* __restrict__ in, T* out, int R, int C,
-                                                int nb, T (*tile)[33]) {
+                                                int nb, T (*tile)[33], int b0, int nblk) {
   const int tilesR = (R + 31) / 32, tilesC = (C + 31) / 32;
   const int per = tilesR * tilesC;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads
-  for (int t = blockIdx.x; t < nb * per; t += gridDim.x) {
+  for (int t = b0; t < nb * per; t += nblk) {
     const int b = t / per, rem = t - b * per;
     const int tr = rem / tilesC, tc = rem - tr * tilesC;
     const T* ib = in + (size_t)b * R * C;
@@ -325,21 +326,26 @@ __device__ __forceinline__ void transpose_tiles(const T* __restrict__ in, T* out
   }
 }
 
-// which = 0: Qr -> Qt; 1: Kr -> Kt; 2: Ot -> Or
+// which = 0: Qr -> Qt (the first half of the blocks) and Kr -> Kt (the
+// second half), one launch; which = 2: Ot -> Or.
 __global__ __launch_bounds__(256) void k_fft_transpose(FftArgs A, int which) {
   const int g = blockIdx.y;
   const GridDesc d = A.desc[g];
   const int ng = d.ng, Mh = d.M / 2 + 1;
-  if (which == 1) {
-    __shared__ float tf[32][33];
-    transpose_tiles<float>(A.kr + (size_t)g * A.s_k, A.kt + (size_t)g * A.s_k, Mh, Mh, 4, tf);
+  __shared__ float2 tc[32][33];
+  if (which == 0) {
+    const int half = gridDim.x / 2;
+    if ((int)blockIdx.x < half) {
+      transpose_tiles<float2>(A.qr + (size_t)g * A.s_q, A.qt + (size_t)g * A.s_q, ng, Mh, 3, tc,
+                              blockIdx.x, half);
+    } else {
+      float (*tf)[33] = reinterpret_cast<float (*)[33]>(&tc[0][0]);
+      transpose_tiles<float>(A.kr + (size_t)g * A.s_k, A.kt + (size_t)g * A.s_k, Mh, Mh, 4, tf,
+                             blockIdx.x - half, gridDim.x - half);
+    }
   } else {
-    __shared__ float2 tc[32][33];
-    if (which == 0)
-      transpose_tiles<float2>(A.qr + (size_t)g * A.s_q, A.qt + (size_t)g * A.s_q, ng, Mh, 3, tc);
-    else
-      transpose_tiles<float2>(A.ot + (size_t)g * A.s_o, A.orr + (size_t)g * A.s_o, Mh, ng,
-                              A.with_ln ? 8 : 7, tc);
+    transpose_tiles<float2>(A.ot + (size_t)g * A.s_o, A.orr + (size_t)g * A.s_o, Mh, ng,
+                            A.with_ln ? 8 : 7, tc, blockIdx.x, gridDim.x);
   }
 }
 
@@ -533,8 +539,7 @@ hipError_t launch_fft_conv(Problem& P, float eps, int with_ln, hipStream_t s) {
   const int bx = P.G >= 64 ? 4 : (P.G >= 8 ? 32 : 1024);
   const int tb = P.G >= 64 ? 16 : (P.G >= 8 ? 64 : 1024);
   hipLaunchKernelGGL(k_fft_rows_fwd, dim3(bx, P.G), dim3(kFftThreads), kFftLds, s, A);
-  hipLaunchKernelGGL(k_fft_transpose, dim3(tb, P.G), dim3(256), 0, s, A, 0);
-  hipLaunchKernelGGL(k_fft_transpose, dim3(tb, P.G), dim3(256), 0, s, A, 1);
+  hipLaunchKernelGGL(k_fft_transpose, dim3(2 * tb, P.G), dim3(256), 0, s, A, 0);
   hipLaunchKernelGGL(k_fft_cols, dim3(bx, P.G), dim3(kFftThreads), kFftLds, s, A);
   hipLaunchKernelGGL(k_fft_transpose, dim3(tb, P.G), dim3(256), 0, s, A, 2);
   hipLaunchKernelGGL(k_fft_rows_inv, dim3(bx, P.G), dim3(kFftThreads), kFftLds, s, A);

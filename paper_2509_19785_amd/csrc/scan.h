@@ -1,5 +1,7 @@
-// Exclusive prefix sums of a host-known length: tile sums, one-block scan of
-// the tile sums, then each tile scanned and offset. out may alias in.
+// Exclusive prefix sums of a host-known length: tile sums, then each tile
+// scanned and offset by the sum of the tile sums before it (the block adds
+// them itself while there are few tiles; beyond kScanDirectTiles a one-block
+// scan of the tile sums runs in between). out may alias in.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -48,11 +50,26 @@ __global__ __launch_bounds__(1024) void k_scan_sums(T* tsum, int T_) {
   }
 }
 
-// out[i] = exclusive prefix of in; out[N] = total.
-template <typename T>
+constexpr int kScanDirectTiles = 4096;
+
+// out[i] = exclusive prefix of in; out[N] = total. tsum holds the exclusive
+// prefix of the tile sums (SUMS_SCANNED) or the tile sums themselves, which
+// the block then adds up for the tiles before its own.
+template <typename T, bool SUMS_SCANNED>
 __global__ __launch_bounds__(256) void k_scan_out(const T* __restrict__ in, int64_t N,
                                                   const T* __restrict__ tsum, T* out) {
   constexpr int per = kTileScan / 256;
+  __shared__ T pre_sh[5];
+  T pre = 0;
+  if constexpr (SUMS_SCANNED) {
+    pre = tsum[blockIdx.x];
+  } else {
+    for (int k = threadIdx.x; k < (int)blockIdx.x; k += 256) pre += tsum[k];
+    pre = wave_sum(pre);
+    if (lane_id() == 0) pre_sh[wave_id()] = pre;
+    __syncthreads();
+    pre = pre_sh[0] + pre_sh[1] + pre_sh[2] + pre_sh[3];
+  }
   const int64_t first = (int64_t)blockIdx.x * kTileScan + threadIdx.x * per;
   T loc[per];
   T sum = 0;
@@ -75,7 +92,7 @@ __global__ __launch_bounds__(256) void k_scan_out(const T* __restrict__ in, int6
     }
   }
   __syncthreads();
-  T run = tsum[blockIdx.x] + sh[wave_id()] + inc - sum;
+  T run = pre + sh[wave_id()] + inc - sum;
 #pragma unroll
   for (int q = 0; q < per; ++q) {
     const int64_t i = first + q;
@@ -85,14 +102,27 @@ __global__ __launch_bounds__(256) void k_scan_out(const T* __restrict__ in, int6
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 255) out[N] = run;
 }
 
-// tsum needs ceil(N / kTileScan) entries; out needs N + 1.
+template <typename T>
+__global__ void k_scan_empty(T* out) {
+  if (threadIdx.x == 0) out[0] = 0;
+}
+
+// tsum needs ceil(N / kTileScan) entries; out needs N + 1. No memset: the
+// calls may be captured into a graph.
 template <typename T>
 inline hipError_t exclusive_scan(const T* in, int64_t N, T* out, T* tsum, hipStream_t s) {
   const int tiles = (int)((N + kTileScan - 1) / kTileScan);
-  if (tiles == 0) return hipMemsetAsync(out, 0, sizeof(T), s);
+  if (tiles == 0) {
+    hipLaunchKernelGGL(k_scan_empty<T>, dim3(1), dim3(64), 0, s, out);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_tile_sum<T>, dim3(tiles), dim3(256), 0, s, in, N, tsum);
-  hipLaunchKernelGGL(k_scan_sums<T>, dim3(1), dim3(1024), 0, s, tsum, tiles);
-  hipLaunchKernelGGL(k_scan_out<T>, dim3(tiles), dim3(256), 0, s, in, N, tsum, out);
+  if (tiles <= kScanDirectTiles) {
+    hipLaunchKernelGGL((k_scan_out<T, false>), dim3(tiles), dim3(256), 0, s, in, N, tsum, out);
+  } else {
+    hipLaunchKernelGGL(k_scan_sums<T>, dim3(1), dim3(1024), 0, s, tsum, tiles);
+    hipLaunchKernelGGL((k_scan_out<T, true>), dim3(tiles), dim3(256), 0, s, in, N, tsum, out);
+  }
   return hipGetLastError();
 }
 
