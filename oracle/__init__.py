@@ -20,6 +20,7 @@ Modules, each citing the passage of the paper it follows:
 * ``interp``     -- FP64 FFT-accelerated interpolation of the kernel sums
                     (Sec. 2.3, Sec. 3.3), the approximation the GPU path uses.
 * ``step``       -- the vertex move (Algorithm 3, last step of the loop).
+* ``pmds``       -- the Pivot MDS starting layout (Algorithms 1-3, first step).
 
 Parity pins (tests marked ``not gpu``) tie each function to something other
 than itself: closed-form BFS distances, brute-force selection, library root
@@ -27,4 +28,4 @@ finding, finite differences of the cost, zero-sum and symmetry invariants,
 polynomial exactness of the interpolation and library FFT convolution.
 """
 
-from . import tiebreak, neighbours, perplexity, affinities, gradient, interp, step  # noqa: F401
+from . import tiebreak, neighbours, perplexity, affinities, gradient, interp, step, pmds  # noqa: F401
