@@ -148,6 +148,52 @@ int tsnet_build_P(tsnet_ctx ctx, const int64_t* indptr, const int32_t* indices,
                   tsnet_P* out, void* stream);
 
 /*
+ * Pivot MDS settings (tsnet_pmds).
+ *  pivots: pivots per graph, 1..128 (a graph with fewer vertices uses all of
+ *    them); at least 2 are needed for a non-zero layout.
+ *  seed: picks each graph's first pivot.
+ *  scale: standard deviation of the first axis of each graph's layout (the
+ *    second axis takes the same factor), > 0.
+ */
+typedef struct {
+  int32_t  pivots;
+  uint64_t seed;
+  double   scale;
+} tsnet_pmds_params;
+
+/* Defaults: 50 pivots, seed 0, scale 1e-2 (the spread of the random start). */
+void tsnet_default_pmds_params(tsnet_pmds_params* p);
+
+/*
+ * Starting layout of Algorithms 1-3 (Sec. 3): Pivot MDS, as tsNET* uses
+ * (Sec. 2.1, Sec. 4.1), the eigensolver method of Brandes and Pich. The paper
+ * gives no settings; per graph of the batch this computes:
+ *  - k_g = min(pivots, n_g) pivots by max-min hop distance, the first at local
+ *    index mix64(seed ^ g) mod n_g (SplitMix64 finaliser), ties to the smallest
+ *    id, an unreachable vertex counting as infinitely far;
+ *  - full BFS hop distances from each pivot, a pair without a path taking 1 +
+ *    the graph's largest finite distance;
+ *  - C = the double-centred squared distances (n_g x k_g, FP64), the two
+ *    leading eigenvectors e1, e2 of C^T C (each signed so that
+ *    sum_j (j + 1) e_j > 0 over the pivot order), and X = C [e1 e2] scaled so
+ *    that the first axis has standard deviation scale. Fewer than two pivots
+ *    give zeros.
+ *  indptr, indices, n, num_arcs, graph_offsets_host, num_graphs: the graph
+ *    batch as in tsnet_build_P (checked the same way; TSNET_EINVAL if bad).
+ *  X: device float [n][2], written. pivots: device int32 [num_graphs][pivots]
+ *    (-1 past a graph's k_g) or NULL. eig_host: host double [num_graphs][2]
+ *    (lambda1, lambda2 of C^T C) or NULL. levels_host: host, total BFS levels
+ *    run, or NULL.
+ *  Synchronous: the host reads each BFS level's frontier size and solves the
+ *  small eigenproblems (cyclic Jacobi). Device workspace of about
+ *  4 n min(pivots, n) bytes is allocated for the call and freed.
+ */
+int tsnet_pmds(tsnet_ctx ctx, const int64_t* indptr, const int32_t* indices, int32_t n,
+               int64_t num_arcs, const int32_t* graph_offsets_host, int32_t num_graphs,
+               const tsnet_pmds_params* prm, float* X, int32_t* pivots, double* eig_host,
+               int32_t* levels_host, void* stream);
+
+/*
  * Make a problem from a host CSR of P (rows sorted, values >= 0, symmetric by
  * contract, not checked). For tests and callers that build P elsewhere.
  * Synchronous. beta/status/conditional rows are absent for such a problem.

@@ -17,8 +17,10 @@ batch (vertices a..b-1, n_g = b - a), in FP64:
 3. S = d^2 (n_g x k_g), double-centred: C_vj = -1/2 (S_vj - r_v - c_j + m),
    with r, c and m the row, column and grand means of S.
 4. e1, e2: unit eigenvectors of C^T C for its two largest eigenvalues
-   lambda1 >= lambda2, each signed so that its entry of largest magnitude
-   (the first of equal ones) is positive.
+   lambda1 >= lambda2, each signed so that sum_j (j + 1) e_j > 0 over the
+   pivot order (a symmetric graph can give an eigenvector two entries of
+   equal largest magnitude, so that entry alone cannot fix the sign); if that
+   sum is exactly 0, so that its entry of largest magnitude is positive.
 5. Y = C [e1 e2], scaled so that the first axis has population standard
    deviation ``scale`` (the spread of the random start, 1e-2); the second
    axis takes the same factor. Y is centred because C is. A graph with fewer
@@ -82,8 +84,10 @@ def select_pivots(A, a: int, b: int, k: int, p0: int):
 
 
 def signed(e: np.ndarray) -> np.ndarray:
-    i = int(np.argmax(np.abs(e)))
-    return e if e[i] >= 0 else -e
+    t = float(np.dot(np.arange(1, e.shape[0] + 1, dtype=np.float64), e))
+    if t == 0.0:
+        t = e[int(np.argmax(np.abs(e)))]
+    return e if t >= 0 else -e
 
 
 def double_centre(S: np.ndarray) -> np.ndarray:

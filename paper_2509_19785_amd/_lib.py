@@ -33,6 +33,7 @@ EXPORTS = (
     "tsnet_grad", "tsnet_grad_terms", "tsnet_step", "tsnet_cost", "tsnet_grad_direct_f64",
     "tsnet_grid_info", "tsnet_status", "tsnet_set_timing", "tsnet_stage_count",
     "tsnet_stage_name", "tsnet_stage_times", "tsnet_last_error",
+    "tsnet_default_pmds_params", "tsnet_pmds",
 )
 
 
@@ -52,6 +53,12 @@ class tsnet_step_params(ctypes.Structure):
         ("momentum_late", ctypes.c_double), ("min_gain", ctypes.c_double),
         ("gain_up", ctypes.c_double), ("gain_down", ctypes.c_double),
         ("momentum_switch_iter", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+
+class tsnet_pmds_params(ctypes.Structure):
+    _fields_ = [
+        ("pivots", ctypes.c_int32), ("seed", ctypes.c_uint64), ("scale", ctypes.c_double),
     ]
 
 
@@ -81,6 +88,9 @@ _P = ctypes.POINTER
 _SIGS = {
     "tsnet_default_params": (None, [_P(tsnet_params)]),
     "tsnet_default_step_params": (None, [_P(tsnet_step_params)]),
+    "tsnet_default_pmds_params": (None, [_P(tsnet_pmds_params)]),
+    "tsnet_pmds": (_i32, [_vp, _vp, _vp, _i32, _i64, _vp, _i32, _P(tsnet_pmds_params), _vp, _vp,
+                          _vp, _vp, _vp]),
     "tsnet_ctx_create": (_i32, [_P(_vp), _i32]),
     "tsnet_ctx_destroy": (_i32, [_vp]),
     "tsnet_build_P": (_i32, [_vp, _vp, _vp, _i32, _i64, _vp, _i32, _dbl, _i32, _u64, _i32,

@@ -289,6 +289,33 @@ class Problem:
         return (G, Z, T) if with_terms else (G, Z)
 
 
+def pmds(ctx: Context, indptr, indices, pivots: int = 50, seed: int = 0, scale: float = 1e-2,
+         graph_offsets=None, stream=None) -> dict:
+    """Pivot MDS starting layout of a graph batch (tsnet_pmds): returns the layout
+    X (float32 [n, 2] on the device), the pivots (int32 [graphs, pivots], -1 past
+    a graph's count), the two leading eigenvalues per graph and the BFS levels run."""
+    dev = torch.device("cuda", ctx.device)
+    ip = torch.as_tensor(np.asarray(indptr, dtype=np.int64)).to(dev) \
+        if not isinstance(indptr, torch.Tensor) else indptr
+    ix = torch.as_tensor(np.asarray(indices, dtype=np.int32)).to(dev) \
+        if not isinstance(indices, torch.Tensor) else indices
+    n = ip.shape[0] - 1
+    go, G = _offsets(graph_offsets, n)
+    prm = _lib.tsnet_pmds_params()
+    lib.tsnet_default_pmds_params(ctypes.byref(prm))
+    prm.pivots, prm.seed, prm.scale = int(pivots), seed & ((1 << 64) - 1), float(scale)
+    X = torch.empty((n, 2), dtype=torch.float32, device=dev)
+    piv = torch.empty((G, int(pivots)), dtype=torch.int32, device=dev)
+    eig = np.zeros((G, 2), dtype=np.float64)
+    levels = ctypes.c_int32()
+    check(lib.tsnet_pmds(ctx.handle, _dev(ip, torch.int64, None, "indptr"),
+                         ix.data_ptr() if ix.numel() else None, n, ix.numel(),
+                         None if go is None else go.ctypes.data, G, ctypes.byref(prm),
+                         X.data_ptr(), piv.data_ptr(), eig.ctypes.data, ctypes.byref(levels),
+                         _stream(stream)))
+    return {"X": X, "pivots": piv, "eig": eig, "levels": levels.value}
+
+
 class StepGraph:
     """k iterations of (gradient, step) recorded once as a HIP graph and replayed.
 

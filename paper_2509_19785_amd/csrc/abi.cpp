@@ -31,7 +31,7 @@ int fail(int code, const std::string& msg) {
 
 static const char* kStageNames[ST_COUNT] = {"bbox_plan", "bin_sort", "spread", "fft_conv",
                                              "gather", "z_reduce", "attract_assemble", "step",
-                                             "cost", "direct_f64", "build_P"};
+                                             "cost", "direct_f64", "build_P", "pmds"};
 
 template <typename T>
 static int dmalloc(T** p, size_t count, const char* what) {
@@ -493,6 +493,45 @@ int tsnet_build_P(tsnet_ctx ctx, const int64_t* indptr, const int32_t* indices, 
   }
   *out = P;
   return TSNET_OK;
+}
+
+void tsnet_default_pmds_params(tsnet_pmds_params* p) {
+  if (!p) return;
+  p->pivots = 50;
+  p->seed = 0;
+  p->scale = 1e-2;
+}
+
+int tsnet_pmds(tsnet_ctx ctx, const int64_t* indptr, const int32_t* indices, int32_t n,
+               int64_t num_arcs, const int32_t* graph_offsets_host, int32_t num_graphs,
+               const tsnet_pmds_params* prm, float* X, int32_t* pivots, double* eig_host,
+               int32_t* levels_host, void* stream) {
+  if (!ctx || !prm || !X) return fail(TSNET_EINVAL, "ctx, params and X must not be NULL");
+  if (!indptr || (num_arcs > 0 && !indices)) return fail(TSNET_EINVAL, "CSR pointers are NULL");
+  if (n < 1) return fail(TSNET_EINVAL, "n must be >= 1");
+  if (num_arcs < 0 || num_arcs >= ((int64_t)1 << 31)) return fail(TSNET_EINVAL, "bad num_arcs");
+  if (prm->pivots < 1 || prm->pivots > 128) return fail(TSNET_EINVAL, "pivots must be in [1, 128]");
+  if (!(prm->scale > 0) || !std::isfinite(prm->scale))
+    return fail(TSNET_EINVAL, "scale must be positive and finite");
+  if ((int64_t)std::min<int64_t>(prm->pivots, n) * n >= ((int64_t)1 << 31))
+    return fail(TSNET_EINVAL, "n * pivots too large");
+  std::vector<int> goff;
+  int rc = check_offsets(n, graph_offsets_host, num_graphs, goff);
+  if (rc) return rc;
+  TSNET_HIP(hipSetDevice(ctx->c.device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int* goff_d = nullptr;
+  TSNET_HIP(hipMalloc(reinterpret_cast<void**>(&goff_d), sizeof(int) * (num_graphs + 1)));
+  hipError_t e = hipMemcpyAsync(goff_d, goff.data(), sizeof(int) * (num_graphs + 1),
+                                hipMemcpyHostToDevice, s);
+  rc = e != hipSuccess ? fail(TSNET_EHIP, hipGetErrorString(e))
+                       : validate_csr(indptr, indices, n, num_arcs, goff_d, num_graphs, s);
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(goff_d);
+  if (rc) return rc;
+  StageScope t(ctx->c, ST_PMDS, s);
+  return run_pmds(indptr, indices, n, goff, prm->pivots, prm->seed, prm->scale, X, pivots,
+                  eig_host, levels_host, s);
 }
 
 int tsnet_P_from_host(tsnet_ctx ctx, int32_t n, const int64_t* rowptr_host,

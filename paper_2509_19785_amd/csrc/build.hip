@@ -748,10 +748,8 @@ static void launch_sort_own(Problem& P, const double* pcond, int* ocol, double* 
                      P.n, P.k, ocol, oval);
 }
 
-int build_affinities(Problem& P, const int64_t* indptr, const int* indices, int64_t num_arcs,
-                     double perplexity, uint64_t seed, int tie_mode, hipStream_t s) {
-  const int n = P.n, k = P.k;
-  const int64_t nk = (int64_t)n * k;
+int validate_csr(const int64_t* indptr, const int* indices, int n, int64_t num_arcs,
+                 const int* goff_d, int G, hipStream_t s) {
   Scratch S;
   unsigned* flag = nullptr;
   int rc;
@@ -764,7 +762,7 @@ int build_affinities(Problem& P, const int64_t* indptr, const int* indices, int6
   BUILD_CHECK(hipStreamSynchronize(s));
   if (hflag) return fail(TSNET_EINVAL, "invalid CSR row pointers");
   if (num_arcs > 0) {
-    hipLaunchKernelGGL(k_check_cols, dim3(vb), dim3(256), 0, s, indptr, indices, n, P.goff_d, P.G,
+    hipLaunchKernelGGL(k_check_cols, dim3(vb), dim3(256), 0, s, indptr, indices, n, goff_d, G,
                        flag);
     BUILD_CHECK(hipMemcpyAsync(&hflag, flag, sizeof(unsigned), hipMemcpyDeviceToHost, s));
     BUILD_CHECK(hipStreamSynchronize(s));
@@ -778,6 +776,16 @@ int build_affinities(Problem& P, const int64_t* indptr, const int* indices, int6
       return fail(TSNET_EINVAL, "invalid CSR:" + why);
     }
   }
+  return TSNET_OK;
+}
+
+int build_affinities(Problem& P, const int64_t* indptr, const int* indices, int64_t num_arcs,
+                     double perplexity, uint64_t seed, int tie_mode, hipStream_t s) {
+  const int n = P.n, k = P.k;
+  const int64_t nk = (int64_t)n * k;
+  Scratch S;
+  int rc;
+  if ((rc = validate_csr(indptr, indices, n, num_arcs, P.goff_d, P.G, s))) return rc;
   // persistent outputs
   if ((rc = tmalloc(&P.cond_len, n)) || (rc = tmalloc(&P.cond_nbr, nk)) ||
       (rc = tmalloc(&P.cond_dist, nk)) || (rc = tmalloc(&P.beta, n)) ||

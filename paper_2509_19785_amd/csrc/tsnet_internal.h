@@ -69,7 +69,7 @@ struct PlanParams {
 // Stage ids for optional per-stage timing.
 enum Stage {
   ST_BBOX = 0, ST_BIN, ST_SPREAD, ST_FFT, ST_GATHER, ST_ZRED, ST_ATTR, ST_STEP, ST_COST,
-  ST_DIRECT, ST_BUILD, ST_COUNT
+  ST_DIRECT, ST_BUILD, ST_PMDS, ST_COUNT
 };
 
 // ---------------------------------------------------------------- contexts
@@ -208,7 +208,18 @@ hipError_t launch_fft_conv(Problem& P, float eps, int with_ln, hipStream_t s);
 hipError_t launch_direct(Problem& P, const double2* X, const tsnet_params& prm, double2* G,
                          double* Z_out, const int* rows, int nrows, double* terms, hipStream_t s);
 
+// Pivot MDS starting layout (pmds.hip). goff: host graph offsets [G+1].
+// Synchronous; X [n][2] on the device, pivots_out [G][pivots] device or NULL,
+// eig_host [G][2] or NULL, levels_host: BFS levels run (or NULL).
+int run_pmds(const int64_t* indptr, const int* indices, int n, const std::vector<int>& goff,
+             int pivots, uint64_t seed, double scale, float* X, int* pivots_out, double* eig_host,
+             int* levels_host, hipStream_t s);
+
 // affinity build (build.hip)
+// Checks a device CSR graph batch (row pointers, ranges, order, symmetry, no self loops or
+// edges between graphs); TSNET_EINVAL with the reason otherwise. Synchronous.
+int validate_csr(const int64_t* indptr, const int* indices, int n, int64_t num_arcs,
+                 const int* goff_d, int G, hipStream_t s);
 int build_affinities(Problem& P, const int64_t* indptr, const int* indices, int64_t num_arcs,
                      double perplexity, uint64_t seed, int tie_mode, hipStream_t s);
 

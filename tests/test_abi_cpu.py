@@ -43,8 +43,36 @@ def test_null_arguments_are_rejected():
     assert b"NULL" in _lib.lib.tsnet_last_error()
     assert _lib.lib.tsnet_grad(None, None, None, None, None, None, None) == _lib.TSNET_EINVAL
     assert _lib.lib.tsnet_P_free(None) == 0 and _lib.lib.tsnet_ctx_destroy(None) == 0
-    assert _lib.lib.tsnet_stage_count() == 11
+    assert _lib.lib.tsnet_stage_count() == 12
     assert _lib.lib.tsnet_stage_name(6) == b"attract_assemble"
+    assert _lib.lib.tsnet_stage_name(11) == b"pmds"
+
+
+def test_pmds_arguments_checked_on_the_host():
+    import ctypes
+    from paper_2509_19785_amd import _lib
+    prm = _lib.tsnet_pmds_params()
+    _lib.lib.tsnet_default_pmds_params(ctypes.byref(prm))
+    assert (prm.pivots, prm.seed, prm.scale) == (50, 0, 1e-2)
+    L = _lib.lib
+    # NULL context / params / X, bad sizes: rejected before any device work
+    assert L.tsnet_pmds(None, None, None, 1, 0, None, 1, ctypes.byref(prm), None, None, None, None,
+                        None) == _lib.TSNET_EINVAL
+    fake_ctx, fake_ptr = ctypes.c_void_p(1), ctypes.c_void_p(8)
+    assert L.tsnet_pmds(fake_ctx, fake_ptr, fake_ptr, 0, 0, None, 1, ctypes.byref(prm), fake_ptr,
+                        None, None, None, None) == _lib.TSNET_EINVAL
+    assert b"n must be" in L.tsnet_last_error()
+    for bad in ({"pivots": 0}, {"pivots": 129}, {"scale": 0.0}, {"scale": float("inf")}):
+        q = _lib.tsnet_pmds_params()
+        L.tsnet_default_pmds_params(ctypes.byref(q))
+        for k, v in bad.items():
+            setattr(q, k, v)
+        assert L.tsnet_pmds(fake_ctx, fake_ptr, fake_ptr, 10, 0, None, 1, ctypes.byref(q),
+                            fake_ptr, None, None, None, None) == _lib.TSNET_EINVAL
+    # graph offsets that do not cover n
+    offs = (ctypes.c_int32 * 3)(0, 4, 9)
+    assert L.tsnet_pmds(fake_ctx, fake_ptr, fake_ptr, 10, 0, offs, 2, ctypes.byref(prm), fake_ptr,
+                        None, None, None, None) == _lib.TSNET_EINVAL
 
 
 def test_stage_names_unique():
