@@ -21,6 +21,8 @@ Modules, each citing the passage of the paper it follows:
                     (Sec. 2.3, Sec. 3.3), the approximation the GPU path uses.
 * ``step``       -- the vertex move (Algorithm 3, last step of the loop).
 * ``pmds``       -- the Pivot MDS starting layout (Algorithms 1-3, first step).
+* ``metrics``    -- neighbourhood preservation (r = 2) and stress of a layout
+                    (Sec. 4.3.1, Sec. 4.3.2).
 
 Parity pins (tests marked ``not gpu``) tie each function to something other
 than itself: closed-form BFS distances, brute-force selection, library root
