@@ -30,4 +30,4 @@ finding, finite differences of the cost, zero-sum and symmetry invariants,
 polynomial exactness of the interpolation and library FFT convolution.
 """
 
-from . import tiebreak, neighbours, perplexity, affinities, gradient, interp, step, pmds  # noqa: F401
+from . import tiebreak, neighbours, perplexity, affinities, gradient, interp, step, pmds, metrics  # noqa: F401
