@@ -194,6 +194,61 @@ int tsnet_pmds(tsnet_ctx ctx, const int64_t* indptr, const int32_t* indices, int
                int32_t* levels_host, void* stream);
 
 /*
+ * Neighbourhood preservation with r = 2 (Sec. 4.3.1), the first quality
+ * measure of the experiments. The paper gives the formula; the readings are:
+ *  - N_G(v): the vertices 1 or 2 hops from v, v excluded; k_v = |N_G(v)|;
+ *  - N_D(v): the k_v vertices of v's own graph nearest to v in the layout, v
+ *    excluded, ranked by the FP32 squared distance dx*dx + dy*dy (dx = x_w -
+ *    x_v, dy = y_w - y_v, each operation rounded on its own, no fused
+ *    multiply-add), equal distances by increasing id;
+ *  - hits_v = |N_G(v) & N_D(v)|, so the Jaccard ratio is hits / (2k - hits);
+ *  - NP of a graph: the mean of that ratio over its evaluated vertices with
+ *    k_v > 0 (NaN if there are none).
+ *  indptr, indices, n, num_arcs, graph_offsets_host, num_graphs: the graph
+ *    batch as in tsnet_build_P (checked the same way; TSNET_EINVAL if bad).
+ *  X: device float [n][2], finite (TSNET_EINVAL otherwise).
+ *  vertices: device int32 [num_vertices], strictly increasing vertex ids to
+ *    evaluate (TSNET_EINVAL if not), or NULL for every vertex (num_vertices
+ *    must then be n).
+ *  ball, hits: device int32 [num_vertices], written: k_v and hits_v of each
+ *    evaluated vertex, exact integers.
+ *  np_host: host double [num_graphs] or NULL.
+ *  Synchronous. Device workspace (grid, sorted points, per-worker bitmaps of
+ *  the largest graph's vertices, at most about 512 MB of them) is allocated
+ *  for the call and freed.
+ */
+int tsnet_np(tsnet_ctx ctx, const int64_t* indptr, const int32_t* indices, int32_t n,
+             int64_t num_arcs, const int32_t* graph_offsets_host, int32_t num_graphs,
+             const float* X, const int32_t* vertices, int32_t num_vertices, int32_t* ball,
+             int32_t* hits, double* np_host, void* stream);
+
+/*
+ * Stress (Sec. 4.3.2), the second quality measure, over the ordered pairs
+ * (s, j) with s a source, j != s reachable from s, d the hop distance and e
+ * the Euclidean layout distance (FP64 from the FP32 coordinates). Per graph
+ * g, sums_host[6g + q] holds:
+ *  q = 0: the number of pairs; 1: S1 = sum (1 - e/d)^2 (the paper's term
+ *  ((d - e)/d)^2); 2: B = sum e/d; 3: C = sum (e/d)^2;
+ *  q = 4: the stress S1 / pairs (NaN without pairs);
+ *  q = 5: the stress of the layout scaled by alpha = B / C, the factor that
+ *  minimises it: (pairs - B^2 / C) / pairs (q = 4's value if C = 0).
+ * With every vertex of a connected graph a source the pairs are its n(n-1)
+ * ordered pairs and q = 4 is the paper's stress; a sample of sources
+ * estimates it. Pairs without a path are left out.
+ *  indptr ... num_graphs, X: as in tsnet_np.
+ *  sources: device int32 [num_sources] (any order, repeats count again);
+ *    an id out of range gives TSNET_EINVAL.
+ *  sums_host: host double [num_graphs][6], written. levels_host: host, BFS
+ *    levels run in all, or NULL.
+ *  Synchronous: the host reads after each BFS level whether it reached a new
+ *  vertex. Device workspace of about 48 n bytes is allocated and freed.
+ */
+int tsnet_stress(tsnet_ctx ctx, const int64_t* indptr, const int32_t* indices, int32_t n,
+                 int64_t num_arcs, const int32_t* graph_offsets_host, int32_t num_graphs,
+                 const float* X, const int32_t* sources, int32_t num_sources, double* sums_host,
+                 int32_t* levels_host, void* stream);
+
+/*
  * Make a problem from a host CSR of P (rows sorted, values >= 0, symmetric by
  * contract, not checked). For tests and callers that build P elsewhere.
  * Synchronous. beta/status/conditional rows are absent for such a problem.

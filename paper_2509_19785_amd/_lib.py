@@ -33,7 +33,7 @@ EXPORTS = (
     "tsnet_grad", "tsnet_grad_terms", "tsnet_step", "tsnet_cost", "tsnet_grad_direct_f64",
     "tsnet_grid_info", "tsnet_status", "tsnet_set_timing", "tsnet_stage_count",
     "tsnet_stage_name", "tsnet_stage_times", "tsnet_last_error",
-    "tsnet_default_pmds_params", "tsnet_pmds",
+    "tsnet_default_pmds_params", "tsnet_pmds", "tsnet_np", "tsnet_stress",
 )
 
 
@@ -91,6 +91,8 @@ _SIGS = {
     "tsnet_default_pmds_params": (None, [_P(tsnet_pmds_params)]),
     "tsnet_pmds": (_i32, [_vp, _vp, _vp, _i32, _i64, _vp, _i32, _P(tsnet_pmds_params), _vp, _vp,
                           _vp, _vp, _vp]),
+    "tsnet_np": (_i32, [_vp, _vp, _vp, _i32, _i64, _vp, _i32, _vp, _vp, _i32, _vp, _vp, _vp, _vp]),
+    "tsnet_stress": (_i32, [_vp, _vp, _vp, _i32, _i64, _vp, _i32, _vp, _vp, _i32, _vp, _vp, _vp]),
     "tsnet_ctx_create": (_i32, [_P(_vp), _i32]),
     "tsnet_ctx_destroy": (_i32, [_vp]),
     "tsnet_build_P": (_i32, [_vp, _vp, _vp, _i32, _i64, _vp, _i32, _dbl, _i32, _u64, _i32,

@@ -316,6 +316,62 @@ def pmds(ctx: Context, indptr, indices, pivots: int = 50, seed: int = 0, scale: 
     return {"X": X, "pivots": piv, "eig": eig, "levels": levels.value}
 
 
+def _graph_dev(ctx: Context, indptr, indices):
+    dev = torch.device("cuda", ctx.device)
+    ip = torch.as_tensor(np.asarray(indptr, dtype=np.int64)).to(dev) \
+        if not isinstance(indptr, torch.Tensor) else indptr
+    ix = torch.as_tensor(np.asarray(indices, dtype=np.int32)).to(dev) \
+        if not isinstance(indices, torch.Tensor) else indices
+    return dev, ip, ix
+
+
+def _ids_dev(ids, dev, name):
+    t = torch.as_tensor(np.asarray(ids, dtype=np.int32)).to(dev) \
+        if not isinstance(ids, torch.Tensor) else ids
+    _dev(t, torch.int32, None, name)
+    return t
+
+
+def neighbourhood_preservation(ctx: Context, indptr, indices, X, vertices=None,
+                               graph_offsets=None, stream=None) -> dict:
+    """Neighbourhood preservation with r = 2 (tsnet_np): per evaluated vertex the
+    2-hop ball size k and the hits (int32 on the device), and NP per graph."""
+    dev, ip, ix = _graph_dev(ctx, indptr, indices)
+    n = ip.shape[0] - 1
+    go, G = _offsets(graph_offsets, n)
+    _dev(X, torch.float32, (n, 2), "X")
+    vt = None if vertices is None else _ids_dev(vertices, dev, "vertices")
+    nv = n if vt is None else vt.numel()
+    ball = torch.empty(nv, dtype=torch.int32, device=dev)
+    hits = torch.empty(nv, dtype=torch.int32, device=dev)
+    npg = np.zeros(G, dtype=np.float64)
+    check(lib.tsnet_np(ctx.handle, _dev(ip, torch.int64, None, "indptr"),
+                       ix.data_ptr() if ix.numel() else None, n, ix.numel(),
+                       None if go is None else go.ctypes.data, G, X.data_ptr(),
+                       None if vt is None else vt.data_ptr(), nv, ball.data_ptr(), hits.data_ptr(),
+                       npg.ctypes.data, _stream(stream)))
+    return {"ball": ball, "hits": hits, "np": npg}
+
+
+def stress(ctx: Context, indptr, indices, X, sources, graph_offsets=None, stream=None) -> dict:
+    """Stress over the pairs of the given sources (tsnet_stress): per graph the
+    sums [pairs, sum (1 - e/d)^2, sum e/d, sum (e/d)^2], the stress, the stress
+    at the best uniform scale, and the BFS levels run."""
+    dev, ip, ix = _graph_dev(ctx, indptr, indices)
+    n = ip.shape[0] - 1
+    go, G = _offsets(graph_offsets, n)
+    _dev(X, torch.float32, (n, 2), "X")
+    st = _ids_dev(sources, dev, "sources")
+    out = np.zeros((G, 6), dtype=np.float64)
+    levels = ctypes.c_int32()
+    check(lib.tsnet_stress(ctx.handle, _dev(ip, torch.int64, None, "indptr"),
+                           ix.data_ptr() if ix.numel() else None, n, ix.numel(),
+                           None if go is None else go.ctypes.data, G, X.data_ptr(), st.data_ptr(),
+                           st.numel(), out.ctypes.data, ctypes.byref(levels), _stream(stream)))
+    return {"sums": out[:, :4].copy(), "stress": out[:, 4].copy(),
+            "stress_best_scale": out[:, 5].copy(), "levels": levels.value}
+
+
 class StepGraph:
     """k iterations of (gradient, step) recorded once as a HIP graph and replayed.
 

@@ -31,7 +31,8 @@ int fail(int code, const std::string& msg) {
 
 static const char* kStageNames[ST_COUNT] = {"bbox_plan", "bin_sort", "spread", "fft_conv",
                                              "gather", "z_reduce", "attract_assemble", "step",
-                                             "cost", "direct_f64", "build_P", "pmds"};
+                                             "cost", "direct_f64", "build_P", "pmds",
+                                             "np", "stress"};
 
 template <typename T>
 static int dmalloc(T** p, size_t count, const char* what) {
@@ -532,6 +533,57 @@ int tsnet_pmds(tsnet_ctx ctx, const int64_t* indptr, const int32_t* indices, int
   StageScope t(ctx->c, ST_PMDS, s);
   return run_pmds(indptr, indices, n, goff, prm->pivots, prm->seed, prm->scale, X, pivots,
                   eig_host, levels_host, s);
+}
+
+// Shared checks of the metric calls: pointers, sizes, offsets and the graph.
+static int metric_graph(tsnet_ctx ctx, const int64_t* indptr, const int32_t* indices, int32_t n,
+                        int64_t num_arcs, const int32_t* graph_offsets_host, int32_t num_graphs,
+                        const float* X, std::vector<int>& goff, hipStream_t s) {
+  if (!ctx || !X) return fail(TSNET_EINVAL, "ctx and X must not be NULL");
+  if (!indptr || (num_arcs > 0 && !indices)) return fail(TSNET_EINVAL, "CSR pointers are NULL");
+  if (n < 1) return fail(TSNET_EINVAL, "n must be >= 1");
+  if (num_arcs < 0 || num_arcs >= ((int64_t)1 << 31)) return fail(TSNET_EINVAL, "bad num_arcs");
+  int rc = check_offsets(n, graph_offsets_host, num_graphs, goff);
+  if (rc) return rc;
+  TSNET_HIP(hipSetDevice(ctx->c.device));
+  int* goff_d = nullptr;
+  TSNET_HIP(hipMalloc(reinterpret_cast<void**>(&goff_d), sizeof(int) * (num_graphs + 1)));
+  hipError_t e = hipMemcpyAsync(goff_d, goff.data(), sizeof(int) * (num_graphs + 1),
+                                hipMemcpyHostToDevice, s);
+  rc = e != hipSuccess ? fail(TSNET_EHIP, hipGetErrorString(e))
+                       : validate_csr(indptr, indices, n, num_arcs, goff_d, num_graphs, s);
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(goff_d);
+  return rc;
+}
+
+int tsnet_np(tsnet_ctx ctx, const int64_t* indptr, const int32_t* indices, int32_t n,
+             int64_t num_arcs, const int32_t* graph_offsets_host, int32_t num_graphs,
+             const float* X, const int32_t* vertices, int32_t num_vertices, int32_t* ball,
+             int32_t* hits, double* np_host, void* stream) {
+  if (!ball || !hits) return fail(TSNET_EINVAL, "ball and hits must not be NULL");
+  if (vertices ? num_vertices < 1 : num_vertices != n)
+    return fail(TSNET_EINVAL, "num_vertices must be >= 1, or n when vertices is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  std::vector<int> goff;
+  int rc = metric_graph(ctx, indptr, indices, n, num_arcs, graph_offsets_host, num_graphs, X, goff, s);
+  if (rc) return rc;
+  StageScope t(ctx->c, ST_NP, s);
+  return run_np(indptr, indices, n, goff, X, vertices, num_vertices, ball, hits, np_host, s);
+}
+
+int tsnet_stress(tsnet_ctx ctx, const int64_t* indptr, const int32_t* indices, int32_t n,
+                 int64_t num_arcs, const int32_t* graph_offsets_host, int32_t num_graphs,
+                 const float* X, const int32_t* sources, int32_t num_sources, double* sums_host,
+                 int32_t* levels_host, void* stream) {
+  if (!sources || num_sources < 1) return fail(TSNET_EINVAL, "sources must name at least one vertex");
+  if (!sums_host) return fail(TSNET_EINVAL, "sums_host must not be NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  std::vector<int> goff;
+  int rc = metric_graph(ctx, indptr, indices, n, num_arcs, graph_offsets_host, num_graphs, X, goff, s);
+  if (rc) return rc;
+  StageScope t(ctx->c, ST_STRESS, s);
+  return run_stress(indptr, indices, n, goff, X, sources, num_sources, sums_host, levels_host, s);
 }
 
 int tsnet_P_from_host(tsnet_ctx ctx, int32_t n, const int64_t* rowptr_host,

@@ -69,7 +69,7 @@ struct PlanParams {
 // Stage ids for optional per-stage timing.
 enum Stage {
   ST_BBOX = 0, ST_BIN, ST_SPREAD, ST_FFT, ST_GATHER, ST_ZRED, ST_ATTR, ST_STEP, ST_COST,
-  ST_DIRECT, ST_BUILD, ST_PMDS, ST_COUNT
+  ST_DIRECT, ST_BUILD, ST_PMDS, ST_NP, ST_STRESS, ST_COUNT
 };
 
 // ---------------------------------------------------------------- contexts
@@ -214,6 +214,16 @@ hipError_t launch_direct(Problem& P, const double2* X, const tsnet_params& prm, 
 int run_pmds(const int64_t* indptr, const int* indices, int n, const std::vector<int>& goff,
              int pivots, uint64_t seed, double scale, float* X, int* pivots_out, double* eig_host,
              int* levels_host, hipStream_t s);
+
+// layout quality metrics (metrics.hip); synchronous. Neighbourhood preservation:
+// verts (device, strictly increasing) or NULL for all n, ball/hits [nv] on the
+// device, np_host [G]. Stress: sources [nsrc] on the device, sums_host [G][6].
+int run_np(const int64_t* indptr, const int* indices, int n, const std::vector<int>& goff,
+           const float* X, const int* verts, int nv, int* ball, int* hits, double* np_host,
+           hipStream_t s);
+int run_stress(const int64_t* indptr, const int* indices, int n, const std::vector<int>& goff,
+               const float* X, const int* sources, int nsrc, double* sums_host, int* levels_host,
+               hipStream_t s);
 
 // affinity build (build.hip)
 // Checks a device CSR graph batch (row pointers, ranges, order, symmetry, no self loops or

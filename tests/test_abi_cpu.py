@@ -43,9 +43,10 @@ def test_null_arguments_are_rejected():
     assert b"NULL" in _lib.lib.tsnet_last_error()
     assert _lib.lib.tsnet_grad(None, None, None, None, None, None, None) == _lib.TSNET_EINVAL
     assert _lib.lib.tsnet_P_free(None) == 0 and _lib.lib.tsnet_ctx_destroy(None) == 0
-    assert _lib.lib.tsnet_stage_count() == 12
+    assert _lib.lib.tsnet_stage_count() == 14
     assert _lib.lib.tsnet_stage_name(6) == b"attract_assemble"
     assert _lib.lib.tsnet_stage_name(11) == b"pmds"
+    assert _lib.lib.tsnet_stage_name(12) == b"np" and _lib.lib.tsnet_stage_name(13) == b"stress"
 
 
 def test_pmds_arguments_checked_on_the_host():
@@ -73,6 +74,35 @@ def test_pmds_arguments_checked_on_the_host():
     offs = (ctypes.c_int32 * 3)(0, 4, 9)
     assert L.tsnet_pmds(fake_ctx, fake_ptr, fake_ptr, 10, 0, offs, 2, ctypes.byref(prm), fake_ptr,
                         None, None, None, None) == _lib.TSNET_EINVAL
+
+
+def test_metric_arguments_checked_on_the_host():
+    import ctypes
+    from paper_2509_19785_amd import _lib
+    L = _lib.lib
+    fake_ctx, fake_ptr = ctypes.c_void_p(1), ctypes.c_void_p(8)
+    # NULL context / X / outputs, bad sizes: rejected before any device work
+    assert L.tsnet_np(None, fake_ptr, fake_ptr, 4, 0, None, 1, fake_ptr, None, 4, fake_ptr,
+                      fake_ptr, None, None) == _lib.TSNET_EINVAL
+    assert L.tsnet_np(fake_ctx, fake_ptr, fake_ptr, 4, 0, None, 1, fake_ptr, None, 4, None,
+                      fake_ptr, None, None) == _lib.TSNET_EINVAL
+    assert L.tsnet_np(fake_ctx, fake_ptr, fake_ptr, 4, 0, None, 1, fake_ptr, None, 3, fake_ptr,
+                      fake_ptr, None, None) == _lib.TSNET_EINVAL
+    assert b"num_vertices" in L.tsnet_last_error()
+    assert L.tsnet_np(fake_ctx, fake_ptr, fake_ptr, 4, 0, None, 1, fake_ptr, fake_ptr, 0, fake_ptr,
+                      fake_ptr, None, None) == _lib.TSNET_EINVAL
+    offs = (ctypes.c_int32 * 3)(0, 2, 3)
+    assert L.tsnet_np(fake_ctx, fake_ptr, fake_ptr, 4, 0, offs, 2, fake_ptr, None, 4, fake_ptr,
+                      fake_ptr, None, None) == _lib.TSNET_EINVAL
+    sums = (ctypes.c_double * 6)()
+    assert L.tsnet_stress(fake_ctx, fake_ptr, fake_ptr, 4, 0, None, 1, fake_ptr, None, 1, sums,
+                          None, None) == _lib.TSNET_EINVAL
+    assert b"sources" in L.tsnet_last_error()
+    assert L.tsnet_stress(fake_ctx, fake_ptr, fake_ptr, 4, 0, None, 1, fake_ptr, fake_ptr, 1, None,
+                          None, None) == _lib.TSNET_EINVAL
+    assert L.tsnet_stress(fake_ctx, fake_ptr, fake_ptr, 0, 0, None, 1, fake_ptr, fake_ptr, 1, sums,
+                          None, None) == _lib.TSNET_EINVAL
+    assert b"n must be" in L.tsnet_last_error()
 
 
 def test_stage_names_unique():
