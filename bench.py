@@ -109,6 +109,25 @@ def pmds_cpu_baseline(g, pivots: int, sample: int = 3):
                       f"extrapolated; the eigen-solve and projection are not counted"}
 
 
+def metrics_cpu_baseline(g, X, np_sample: int = 16, stress_sample: int = 2, sources: int = 64):
+    """The oracle's metrics on the host: neighbourhood preservation of `np_sample`
+    vertices extrapolated to all n, stress of `stress_sample` sources extrapolated
+    to `sources`."""
+    from oracle import metrics as om
+    rng = np.random.default_rng(5)
+    verts = np.sort(rng.choice(g.n, np_sample, replace=False))
+    t0 = time.perf_counter()
+    om.neighbourhood_preservation(g.indptr, g.indices, X, vertices=verts)
+    np_per = (time.perf_counter() - t0) / np_sample
+    t0 = time.perf_counter()
+    om.stress_sums(g.indptr, g.indices, X, rng.choice(g.n, stress_sample, replace=False))
+    st_per = (time.perf_counter() - t0) / stress_sample
+    return {"np_ms": np_per * g.n * 1e3, "stress_ms": st_per * sources * 1e3, "cores": 1,
+            "kind": "oracle",
+            "sample": f"NP of {np_sample} vertices extrapolated to all {g.n}; stress of "
+                      f"{stress_sample} sources (scipy BFS, one core) extrapolated to {sources}"}
+
+
 # --------------------------------------------------------------------------- per-kernel table
 FIXED_GRID_STDS = (6.0, 12.0)   # layouts N(0, std^2): 256 and 512 intervals at n = 1e6
 FIXED_GRID_EVALS = 20
@@ -207,6 +226,8 @@ def main():
     ap.add_argument("--max-intervals", type=int, default=512)
     ap.add_argument("--pmds-pivots", type=int, default=50,
                     help="pivots of the Pivot MDS leg (0: skip it)")
+    ap.add_argument("--metric-sources", type=int, default=64,
+                    help="stress sources for the quality-metric leg on the final layout (0: skip the leg)")
     ap.add_argument("--runs", type=int, default=5,
                     help="timed runs from the initial layout (plain launches); value is their mean")
     ap.add_argument("--last", type=int, default=100,
@@ -413,6 +434,41 @@ def main():
         grid_span.append(float(g_i["n_intervals"][0]) * float(g_i["box_side"][0]))
     log("grid per iteration (it span n_int M): " + "; ".join(
         f"{i} {grid_span[i]:.2f} {grid_ni[i]} {6 * grid_ni[i]}" for i in range(len(grid_ni))))
+    # quality metrics of the layout the run ended with (not part of the timed steps):
+    # neighbourhood preservation of every vertex, stress over sampled sources
+    met = None
+    if args.metric_sources > 0:
+        ipm = torch.as_tensor(g.indptr).to(dev)
+        ixm = torch.as_tensor(g.indices).to(dev)
+        Xf = X.clone()
+        src = np.random.default_rng(3).choice(g.n, min(args.metric_sources, g.n),
+                                              replace=False).astype(np.int32)
+        for rep in range(2):  # the second calls are timed (the first allocate)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r_np = api.neighbourhood_preservation(ctx, ipm, ixm, Xf)
+            torch.cuda.synchronize()
+            np_s = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            r_st = api.stress(ctx, ipm, ixm, Xf, src)
+            torch.cuda.synchronize()
+            st_s = time.perf_counter() - t0
+        ball = r_np["ball"].to(torch.int64)
+        met = {
+            "layout": f"after {args.warmup + args.steps} steps",
+            "np": {"value": float(r_np["np"][0]), "ms": np_s * 1e3, "vertices_per_s": g.n / np_s,
+                   "sum_ball": int(ball.sum()), "max_ball": int(ball.max())},
+            "stress": {"value": float(r_st["stress"][0]),
+                       "best_scale": float(r_st["stress_best_scale"][0]),
+                       "ms": st_s * 1e3, "sources": int(len(src)), "levels": r_st["levels"],
+                       "pairs": float(r_st["sums"][0, 0]),
+                       "pairs_per_s": float(r_st["sums"][0, 0]) / st_s},
+        }
+        if not args.no_cpu_baseline:
+            met["cpu_oracle"] = metrics_cpu_baseline(g, Xf.cpu().numpy(), sources=len(src))
+        log(f"metrics: NP {met['np']['value']:.6f} in {np_s * 1e3:.1f} ms; stress "
+            f"{met['stress']['value']:.4f} ({len(src)} sources) in {st_s * 1e3:.1f} ms")
+        del ipm, ixm, Xf, r_np, ball
     timed_ni = grid_ni[args.warmup:]
     ni_runs = []
     for v in timed_ni:
@@ -501,6 +557,7 @@ def main():
         },
         "build_P_ms": build_ms,
         "pmds": pm,
+        "metrics": met,
         "stages_ms": stages,
         "direct_f64": direct,
     }

@@ -13,14 +13,19 @@
 //  * N_G(v) is marked in a bitmap of the graph's vertices that the worker
 //    (a wave, or a block for vertices with many 2-hop walks) owns; walking
 //    the 2-hop paths a second time clears it again and counts the hits.
-//  * N_D(v): the points are counting-sorted into a uniform grid of about one
-//    point per cell (square cells over the graph's bounding box), with a
-//    summed-area table of the cell counts. The smallest square of cells
-//    around v's cell holding k others bounds the k-th distance; every point
-//    that can be nearer lies in the cells of a disc around v (widened by one
-//    cell plus a slack for the FP32 cell assignment). The k-th smallest key
-//    (squared distance bits, id) over that disc is found by an 8-bit radix
-//    select; a vertex is among the k nearest iff its key is not above it.
+//  * N_D(v): the points are counting-sorted into a grid whose cell
+//    boundaries are quantiles of each coordinate (about sqrt(n_g) cells per
+//    axis, so cells follow the density of clustered layouts), with a
+//    summed-area table of the cell counts. Cell membership is decided by
+//    exact comparisons with the boundaries, so any boundaries give the same
+//    result. The smallest square of cells around v's cell holding k others
+//    bounds the k-th distance: a first radix select over that square finds
+//    the k-th key there (key = squared-distance bits, id), whose distance
+//    bounds the k-th nearest of the whole graph. Every point that can be
+//    nearer lies in the cells meeting the disc of that radius (widened for
+//    the FP32 rounding of the keys); a second radix select over those cells
+//    gives the k-th smallest key, and a vertex is among the k nearest iff its
+//    key is not above it.
 //
 // Stress over the ordered pairs (s, j), s a source, j != s reachable from s:
 // d = hop distance, e = Euclidean distance in FP64 from the FP32 coordinates,
@@ -48,12 +53,14 @@ namespace {
 
 typedef unsigned long long u64;
 constexpr int kNpMaxGrid = 2048;       // cells per axis at most
-constexpr int kNpChunk = 1024;         // vertices per chunk of the bounding boxes
 constexpr int kNpHeavyWalks = 4096;    // 2-hop walks above which a vertex gets a whole block
 constexpr int kNpLightWaves = 4;       // waves (one vertex each) per block of the light kernel
 constexpr int kNpHeavyThreads = 1024;  // threads per vertex of the heavy kernel
-constexpr float kCellSlack = 1.002f;   // one cell plus the FP32 cell-assignment slack
 constexpr int kStressSources = 64;     // sources per bit-parallel BFS
+// The select over the square keeps going until the top 24 key bits (the
+// squared distance to 15 mantissa bits) are fixed, so the radius it gives is
+// within 2e-5 of the k-th distance in the square.
+constexpr int kSquareExitShift = 40;
 
 enum { NP_ERR_COORD = 1, NP_ERR_VERTEX = 2, NP_ERR_ORDER = 4, NP_ERR_SELECT = 8 };
 
@@ -78,13 +85,16 @@ struct NpDev {
   const int* gcell;     // [G] cells per axis
   const int* cbase;     // [G+1] first cell of each graph
   const int* sbase;     // [G] first summed-area entry of each graph
-  const int* colbase;   // [G+1] first summed-area column of each graph
-  float4* gparam;       // [G] (x0, y0, cells per unit length, unused)
+  const int* colbase;   // [G+1] first boundary (and summed-area column) of each graph
+  float* bx;            // cell boundaries along x: G_g + 1 per graph, from colbase[g]
+  float* by;            // the same along y
   int* cell_of;         // [n]
   int* cnt;             // [cells + 1] counts, then the fill cursors
   int* cstart;          // [cells + 1] first sorted point of each cell
   int* sat;             // summed-area tables, (G_g + 1)^2 per graph
   float4* sorted;       // [n] (x, y, id bits, 0) in cell order
+  unsigned* skey;       // [n] sort keys (coordinate order, then graph)
+  unsigned* sval;       // [n] vertex of each sorted key
   const int* verts;     // evaluated vertices (strictly increasing) or NULL for all
   int nv;               // number of evaluated vertices
   unsigned* bits;       // per-worker bitmaps of `words` words
@@ -98,16 +108,14 @@ __device__ __forceinline__ int np_graph(const NpDev& a, int v) {
   return a.G == 1 ? 0 : graph_of(a.goff, a.G, v);
 }
 
-// Cell of a point: floor((x - x0) * cells per unit), clamped to the grid
-// (NaN, from an overflowing difference with a zero scale, goes to cell 0).
-__device__ __forceinline__ int np_cell1(float x, float x0, float inv, int Gg) {
-  const float u = (x - x0) * inv;
-  return u >= 0.f ? (int)fminf(u, (float)(Gg - 1)) : 0;
-}
-
-__device__ __forceinline__ void np_cell_xy(const float4& p, int Gg, float x, float y, int& cx, int& cy) {
-  cx = np_cell1(x, p.x, p.z, Gg);
-  cy = np_cell1(y, p.y, p.z, Gg);
+// Cell along one axis: the largest c in [0, G_g - 1] with b[c] <= x, or 0.
+__device__ __forceinline__ int qcell(const float* b, int Gg, double x) {
+  int l = 1, h = Gg;  // the first index in [1, G_g) with b > x, else G_g
+  while (l < h) {
+    const int m = (l + h) >> 1;
+    if ((double)b[m] > x) h = m; else l = m + 1;
+  }
+  return l - 1;
 }
 
 __global__ void k_fill_u32(unsigned* p, size_t count, unsigned v) {
@@ -116,69 +124,51 @@ __global__ void k_fill_u32(unsigned* p, size_t count, unsigned v) {
     p[i] = v;
 }
 
-// Bounding box of each chunk (one graph, up to kNpChunk vertices).
-__global__ __launch_bounds__(256) void k_np_bbox(NpDev a, const int* cs, const int* ce, float4* part) {
-  __shared__ float red[4][256 / kWave];
-  const int c = blockIdx.x;
-  float mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
+__global__ __launch_bounds__(256) void k_np_check(NpDev a) {
   bool bad = false;
-  for (int v = cs[c] + threadIdx.x; v < ce[c]; v += blockDim.x) {
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += gridDim.x * blockDim.x) {
     const float2 p = a.X[v];
     if (!isfinite(p.x) || !isfinite(p.y)) bad = true;
-    mnx = fminf(mnx, p.x);
-    mny = fminf(mny, p.y);
-    mxx = fmaxf(mxx, p.x);
-    mxy = fmaxf(mxy, p.y);
   }
   if (bad) atomicOr(a.err, NP_ERR_COORD);
-  mnx = wave_min(mnx);
-  mny = wave_min(mny);
-  mxx = wave_max(mxx);
-  mxy = wave_max(mxy);
-  if (lane_id() == 0) {
-    red[0][wave_id()] = mnx;
-    red[1][wave_id()] = mny;
-    red[2][wave_id()] = mxx;
-    red[3][wave_id()] = mxy;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < 256 / kWave; ++w) {
-      mnx = fminf(mnx, red[0][w]);
-      mny = fminf(mny, red[1][w]);
-      mxx = fmaxf(mxx, red[2][w]);
-      mxy = fmaxf(mxy, red[3][w]);
-    }
-    part[c] = make_float4(mnx, mny, mxx, mxy);
+}
+
+// Sort keys of one axis: the float bits mapped so that unsigned order is the
+// order of the values.
+__global__ __launch_bounds__(256) void k_np_axis_keys(NpDev a, int axis) {
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += gridDim.x * blockDim.x) {
+    const float2 p = a.X[v];
+    const unsigned u = __float_as_uint(axis ? p.y : p.x);
+    a.skey[v] = u ^ ((u >> 31) ? 0xFFFFFFFFu : 0x80000000u);
+    a.sval[v] = (unsigned)v;
   }
 }
 
-// Per graph: the box from its chunks and the cell size (square cells over the
-// larger side). A zero or unusable span puts every point in cell (0, 0).
-__global__ void k_np_plan(NpDev a, const int* gcb, const int* gce, const float4* part) {
-  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < a.G; g += gridDim.x * blockDim.x) {
-    float mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
-    for (int c = gcb[g]; c < gce[g]; ++c) {
-      const float4 p = part[c];
-      mnx = fminf(mnx, p.x);
-      mny = fminf(mny, p.y);
-      mxx = fmaxf(mxx, p.z);
-      mxy = fmaxf(mxy, p.w);
-    }
-    const float span = fmaxf(mxx - mnx, mxy - mny);
-    float inv = span > 0.f ? (float)a.gcell[g] / span : 0.f;
-    if (!isfinite(inv)) inv = 0.f;
-    a.gparam[g] = make_float4(mnx, mny, inv, 0.f);
+// After the sort by coordinate: the graph of each entry, for a stable sort by graph.
+__global__ __launch_bounds__(256) void k_np_graph_keys(NpDev a) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += gridDim.x * blockDim.x)
+    a.skey[i] = (unsigned)graph_of(a.goff, a.G, (int)a.sval[i]);
+}
+
+// Boundaries of graph g along one axis: b[c] = the coordinate of rank
+// c n_g / G_g in the graph (b[0] its smallest, b[G_g] its largest).
+__global__ __launch_bounds__(256) void k_np_bounds(NpDev a, int axis, int total) {
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < total; c += gridDim.x * blockDim.x) {
+    const int g = graph_of(a.colbase, a.G, c);
+    const int j = c - a.colbase[g], Gg = a.gcell[g];
+    const int lo = a.goff[g], ng = a.goff[g + 1] - lo;
+    const int pos = j == Gg ? lo + ng - 1 : lo + (int)((int64_t)j * ng / Gg);
+    const float2 p = a.X[a.sval[pos]];
+    (axis ? a.by : a.bx)[c] = axis ? p.y : p.x;
   }
 }
 
 __global__ __launch_bounds__(256) void k_np_cells(NpDev a) {
   for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += gridDim.x * blockDim.x) {
     const int g = np_graph(a, v);
-    const int Gg = a.gcell[g];
+    const int Gg = a.gcell[g], cb = a.colbase[g];
     const float2 x = a.X[v];
-    int cx, cy;
-    np_cell_xy(a.gparam[g], Gg, x.x, x.y, cx, cy);
+    const int cx = qcell(a.bx + cb, Gg, x.x), cy = qcell(a.by + cb, Gg, x.y);
     const int cell = a.cbase[g] + cy * Gg + cx;
     a.cell_of[v] = cell;
     atomicAdd(&a.cnt[cell], 1);
@@ -277,6 +267,16 @@ struct Grp<kWave> {
     *total = uni(__shfl(inc, kWave - 1, kWave));
     return inc - v;
   }
+  static __device__ __forceinline__ u64 max64(u64 v, int*) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+      const unsigned hi = __shfl_xor((unsigned)(v >> 32), o, kWave);
+      const unsigned lo = __shfl_xor((unsigned)v, o, kWave);
+      const u64 w = ((u64)hi << 32) | lo;
+      v = w > v ? w : v;
+    }
+    return ((u64)(unsigned)uni((int)(v >> 32)) << 32) | (unsigned)uni((int)(unsigned)v);
+  }
   // smallest r in [base, base + 64) with ok, or INT_MAX
   static __device__ __forceinline__ int first(bool ok, int r, int*) {
     const u64 m = __ballot(ok);
@@ -311,6 +311,23 @@ struct Grp<kNpHeavyThreads> {
     *total = uni(tot);
     return ex;
   }
+  static __device__ __forceinline__ u64 max64(u64 v, int* red) {
+    constexpr int NW = kNpHeavyThreads / kWave;
+    v = Grp<kWave>::max64(v, nullptr);
+    if (lane_id() == 0) {
+      red[wave_id()] = (int)(unsigned)(v >> 32);
+      red[NW + wave_id()] = (int)(unsigned)v;
+    }
+    __syncthreads();
+    u64 m = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const u64 x = ((u64)(unsigned)red[w] << 32) | (unsigned)red[NW + w];
+      m = x > m ? x : m;
+    }
+    __syncthreads();
+    return ((u64)(unsigned)uni((int)(m >> 32)) << 32) | (unsigned)uni((int)(unsigned)m);
+  }
   static __device__ __forceinline__ int first(bool ok, int r, int* red) {
     if (threadIdx.x == 0) red[0] = INT_MAX;
     __syncthreads();
@@ -322,43 +339,143 @@ struct Grp<kNpHeavyThreads> {
   }
 };
 
-// Calls f(pos) for every position of nseg index segments with all T threads
-// of the group: segments go T at a time through LDS (start, exclusive prefix
-// of lengths), and each position finds its segment by binary search.
-template <int T, class SegF, class ElemF>
-__device__ __forceinline__ void for_segments(int nseg, SegF seg, ElemF f, int* pre, int64_t* st,
-                                             int* red) {
+// The positions of a batch of up to T index segments (segment t held by
+// thread t) visited with all T threads of the group: the lengths' exclusive
+// prefix goes through LDS and each position finds its segment by binary search.
+template <int T, class ElemF>
+__device__ __forceinline__ void seg_batch(int cnt, int64_t s0, int len, ElemF f, int* pre, int64_t* st,
+                                          int* red) {
   const int t = Grp<T>::tid();
-  for (int base = 0; base < nseg; base += T) {
-    const int cnt = min(T, nseg - base);
-    int64_t s0 = 0;
-    int len = 0;
-    if (t < cnt) seg(base + t, s0, len);
-    int tot;
-    const int ex = Grp<T>::excl_scan(len, red, &tot);
-    pre[t] = ex;
-    st[t] = s0;
-    Grp<T>::sync();
-    for (int q = t; q < tot; q += T) {
-      int lo = 0, hi = cnt;  // pre[lo] <= q < pre[hi]
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (pre[mid] <= q) lo = mid; else hi = mid;
-      }
-      f(st[lo] + (q - pre[lo]));
+  int tot;
+  const int ex = Grp<T>::excl_scan(t < cnt ? len : 0, red, &tot);
+  pre[t] = ex;
+  st[t] = s0;
+  Grp<T>::sync();
+  for (int q = t; q < tot; q += T) {
+    int lo = 0, hi = cnt;  // pre[lo] <= q < pre[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (pre[mid] <= q) lo = mid; else hi = mid;
     }
-    Grp<T>::sync();
+    f(st[lo] + (q - pre[lo]));
   }
+  Grp<T>::sync();
 }
+
+// nseg segments given by seg(j, start, len): kept in registers (one per
+// thread) when they fit one batch, else computed again on every visit.
+template <int T, class SegF>
+struct SegSet {
+  int nseg;
+  SegF seg;
+  int64_t s0 = 0;
+  int len = 0;
+  __device__ SegSet(int n_, SegF s_) : nseg(n_), seg(s_) {
+    if (nseg <= T && Grp<T>::tid() < nseg) seg(Grp<T>::tid(), s0, len);
+  }
+  template <class ElemF>
+  __device__ void each(ElemF f, int* pre, int64_t* st, int* red) {
+    if (nseg <= T) {
+      seg_batch<T>(nseg, s0, len, f, pre, st, red);
+      return;
+    }
+    const int t = Grp<T>::tid();
+    for (int base = 0; base < nseg; base += T) {
+      const int cnt = min(T, nseg - base);
+      int64_t b0 = 0;
+      int bl = 0;
+      if (t < cnt) seg(base + t, b0, bl);
+      seg_batch<T>(cnt, b0, bl, f, pre, st, red);
+    }
+  }
+};
 
 template <int T>
 struct NpLds {
   int hist[256];
   int pre[T];
   int64_t st[T];
-  int red[kNpHeavyThreads / kWave + 1];
+  int red[2 * (kNpHeavyThreads / kWave) + 1];
   int bucket[3];
 };
+
+// The want-th smallest key K (want >= 1) among the points of `set` other
+// than v, 8 bits at a time from the top; no early exit while shift >
+// exit_shift. On return the keys of `set` among the want smallest are those
+// with (key >> shift) <= lim. With exact, shift is 0 and lim is K itself (a
+// last pass takes the largest key of the final bucket), so the test holds for
+// any key, not only for those of `set`. Returns false if there are fewer
+// than want keys.
+template <int T, class Set>
+__device__ bool radix_select(Set& set, const NpDev& a, int v, float xv, float yv, int want,
+                             int exit_shift, bool exact, NpLds<T>& L, int& shift_out, u64& lim_out) {
+  const int t = Grp<T>::tid();
+  u64 prefix = 0, mask = 0;
+  int shift = 56;
+  while (true) {
+    for (int b = t; b < 256; b += T) L.hist[b] = 0;
+    Grp<T>::sync();
+    set.each([&](int64_t pos) {
+      const float4 rec = a.sorted[pos];
+      const int w = __float_as_int(rec.z);
+      if (w == v) return;
+      const u64 key = np_key(np_d2(rec.x, rec.y, xv, yv), w);
+      if ((key & mask) == prefix) atomicAdd(&L.hist[(key >> shift) & 255], 1);
+    }, L.pre, L.st, L.red);
+    if (t < kWave) {
+      int c4[4], s = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        c4[q] = L.hist[4 * t + q];
+        s += c4[q];
+      }
+      const int inc = wave_incl_scan(s);
+      int below = inc - s;
+      int hit = -1, hb = 0, hc = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (hit < 0 && below < want && want <= below + c4[q]) {
+          hit = 4 * t + q;
+          hb = below;
+          hc = c4[q];
+        }
+        below += c4[q];
+      }
+      const int all = __shfl(inc, kWave - 1, kWave);
+      if (hit >= 0) {  // exactly one lane
+        L.bucket[0] = hit;
+        L.bucket[1] = hb;
+        L.bucket[2] = hc;
+      }
+      if (t == 0 && all < want) L.bucket[0] = -1;
+    }
+    Grp<T>::sync();
+    const int bsel = uni(L.bucket[0]), bbelow = uni(L.bucket[1]), bcnt = uni(L.bucket[2]);
+    Grp<T>::sync();
+    if (bsel < 0) return false;
+    prefix |= (u64)bsel << shift;
+    mask |= (u64)255 << shift;
+    want -= bbelow;
+    if ((bcnt == want && shift <= exit_shift) || shift == 0) break;
+    shift -= 8;
+  }
+  if (exact && shift > 0) {
+    const u64 p = prefix >> shift;
+    u64 m = 0;
+    set.each([&](int64_t pos) {
+      const float4 rec = a.sorted[pos];
+      const int w = __float_as_int(rec.z);
+      if (w == v) return;
+      const u64 key = np_key(np_d2(rec.x, rec.y, xv, yv), w);
+      if ((key >> shift) == p && key > m) m = key;
+    }, L.pre, L.st, L.red);
+    prefix = Grp<T>::max64(m, L.red);
+    shift = 0;
+  }
+  shift_out = shift;
+  lim_out = prefix >> shift;
+  return true;
+}
 
 // One vertex per group; worker w takes entries w, w + W, ... of its list (W
 // workers), and its bitmap is all zero between vertices. Nothing at the level
@@ -388,9 +505,10 @@ __global__ __launch_bounds__(T == kWave ? kNpLightWaves * kWave : T) void k_np_e
       s0 = a.indptr[u];
       len = (int)(a.indptr[u + 1] - s0);
     };
+    SegSet<T, decltype(walk_seg)> walks(deg + 1, walk_seg);
     // pass 1: mark N_G(v), count its members
     int kl = 0;
-    for_segments<T>(deg + 1, walk_seg, [&](int64_t pos) {
+    walks.each([&](int64_t pos) {
       const int u = a.indices[pos];
       if (u == v) return;
       const int lu = u - ga;
@@ -404,13 +522,13 @@ __global__ __launch_bounds__(T == kWave ? kNpLightWaves * kWave : T) void k_np_e
       a.hits[i] = 0;
       continue;
     }
-    // the smallest square of cells around v's cell that holds k others
-    const float4 p = a.gparam[g];
     const int Gg = a.gcell[g], cb = a.cbase[g];
+    const float* bx = a.bx + a.colbase[g];
+    const float* by = a.by + a.colbase[g];
     const int* S = a.sat + a.sbase[g];
     const float2 xv = a.X[v];
-    int cx, cy;
-    np_cell_xy(p, Gg, xv.x, xv.y, cx, cy);
+    const int cx = uni(qcell(bx, Gg, xv.x)), cy = uni(qcell(by, Gg, xv.y));
+    // the smallest square of cells around v's cell that holds k others
     int r = INT_MAX;
     for (int base = 0; base < Gg && r == INT_MAX; base += T) {
       const int rr = base + t;
@@ -425,82 +543,50 @@ __global__ __launch_bounds__(T == kWave ? kNpLightWaves * kWave : T) void k_np_e
       r = Grp<T>::first(ok, rr, L.red);
     }
     if (r == INT_MAX) r = Gg - 1;  // not reached: the whole grid holds n_g >= k + 1 points
-    // every point that can be among the k nearest lies within rho cells of v
-    const float rho = 1.41421356f * ((float)r + kCellSlack) * 1.00001f;
-    const int Ry = (int)floorf(rho + kCellSlack);
-    const int ylo = max(0, cy - Ry), yhi = min(Gg - 1, cy + Ry);
-    auto cand_seg = [&](int j, int64_t& s0, int& len) {
-      const int y = ylo + j;
-      const float dy = fmaxf(0.f, fabsf((float)(y - cy)) - kCellSlack);
-      s0 = 0;
-      len = 0;
-      if (dy > rho) return;
-      const int wx = (int)floorf(sqrtf(fmaxf(0.f, rho * rho - dy * dy)) + kCellSlack);
-      const int x1 = max(0, cx - wx), x2 = min(Gg - 1, cx + wx);
-      const int row = cb + y * Gg;
+    const int x1 = max(0, cx - r), x2 = min(Gg - 1, cx + r);
+    const int y1 = max(0, cy - r), y2 = min(Gg - 1, cy + r);
+    // phase A: the k-th smallest key in the square bounds the k-th distance
+    auto square_seg = [&](int j, int64_t& s0, int& len) {
+      const int row = cb + (y1 + j) * Gg;
       s0 = a.cstart[row + x1];
       len = a.cstart[row + x2 + 1] - (int)s0;
     };
-    // radix select of the k-th smallest key, 8 bits at a time from the top
-    u64 prefix = 0, mask = 0;
-    int want = k, shift = 56;
-    while (true) {
-      for (int b = t; b < 256; b += T) L.hist[b] = 0;
-      Grp<T>::sync();
-      for_segments<T>(yhi - ylo + 1, cand_seg, [&](int64_t pos) {
-        const float4 rec = a.sorted[pos];
-        const int w = __float_as_int(rec.z);
-        if (w == v) return;
-        const u64 key = np_key(np_d2(rec.x, rec.y, xv.x, xv.y), w);
-        if ((key & mask) == prefix) atomicAdd(&L.hist[(key >> shift) & 255], 1);
-      }, L.pre, L.st, L.red);
-      if (t < kWave) {
-        int c4[4], s = 0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          c4[q] = L.hist[4 * t + q];
-          s += c4[q];
-        }
-        const int inc = wave_incl_scan(s);
-        int below = inc - s;
-        int hit = -1, hb = 0, hc = 0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (hit < 0 && below < want && want <= below + c4[q]) {
-            hit = 4 * t + q;
-            hb = below;
-            hc = c4[q];
-          }
-          below += c4[q];
-        }
-        const int all = __shfl(inc, kWave - 1, kWave);
-        if (hit >= 0) {  // exactly one lane
-          L.bucket[0] = hit;
-          L.bucket[1] = hb;
-          L.bucket[2] = hc;
-        }
-        if (t == 0 && all < want) L.bucket[0] = -1;
-      }
-      Grp<T>::sync();
-      const int bsel = uni(L.bucket[0]), bbelow = uni(L.bucket[1]), bcnt = uni(L.bucket[2]);
-      Grp<T>::sync();
-      if (bsel < 0) {  // fewer candidates than k: cannot happen; reported, nothing counted
-        atomicOr(a.err, NP_ERR_SELECT);
-        prefix = 0;
-        shift = 64;
-        break;
-      }
-      prefix |= (u64)bsel << shift;
-      mask |= (u64)255 << shift;
-      want -= bbelow;
-      if (bcnt == want || shift == 0) break;
-      shift -= 8;
+    SegSet<T, decltype(square_seg)> square(y2 - y1 + 1, square_seg);
+    int shift = 64;
+    u64 lim = 0;
+    bool okA = radix_select<T>(square, a, v, xv.x, xv.y, k, kSquareExitShift, false, L, shift, lim);
+    bool okB = false;
+    if (okA) {
+      // an upper bound of the k-th key's squared distance (bits below `shift` set)
+      const u64 ub = (lim << shift) | ((shift > 0) ? (~0ull >> (64 - shift)) : 0ull);
+      const unsigned ubits = (unsigned)(ub >> 32);  // past +inf's bits the bound is +inf, not NaN
+      const double d2 = ubits >= 0x7F800000u ? (double)INFINITY : (double)__uint_as_float(ubits);
+      // a point whose FP32 key is at most that lies within rho (relative
+      // rounding of the key below 1e-6, underflow below 1e-44)
+      const double rho2 = d2 * (1.0 + 1e-5) + 1e-44;
+      const double rho = sqrt(rho2);
+      const double vx = xv.x, vy = xv.y;
+      const int ylo = uni(qcell(by, Gg, vy - rho)), yhi = uni(qcell(by, Gg, vy + rho));
+      // phase B: every point of the cells that meet the disc
+      auto disc_seg = [&](int j, int64_t& s0, int& len) {
+        const int c = ylo + j;
+        const double dy = fmax(0.0, fmax((double)by[c] - vy, vy - (double)by[c + 1]));
+        s0 = 0;
+        len = 0;
+        if (dy * dy > rho2) return;
+        const double w = sqrt(rho2 - dy * dy);
+        const int xl = qcell(bx, Gg, vx - w), xh = qcell(bx, Gg, vx + w);
+        const int row = cb + c * Gg;
+        s0 = a.cstart[row + xl];
+        len = a.cstart[row + xh + 1] - (int)s0;
+      };
+      SegSet<T, decltype(disc_seg)> disc(yhi - ylo + 1, disc_seg);
+      okB = radix_select<T>(disc, a, v, xv.x, xv.y, k, 64, true, L, shift, lim);
     }
-    // a key is among the k nearest iff its bits above `shift` do not exceed the prefix's
-    const u64 lim = shift >= 64 ? 0 : (prefix >> shift);
+    if (!okB) atomicOr(a.err, NP_ERR_SELECT);  // cannot happen: reported, nothing counted
     // pass 2: clear the bitmap, count the members among the k nearest
     int hl = 0;
-    for_segments<T>(deg + 1, walk_seg, [&](int64_t pos) {
+    walks.each([&](int64_t pos) {
       const int u = a.indices[pos];
       if (u == v) return;
       const int lu = u - ga;
@@ -509,7 +595,7 @@ __global__ __launch_bounds__(T == kWave ? kNpLightWaves * kWave : T) void k_np_e
       if (old & bit) {
         const float2 xu = a.X[u];
         const u64 key = np_key(np_d2(xu.x, xu.y, xv.x, xv.y), u);
-        if (shift < 64 && (key >> shift) <= lim) ++hl;
+        if (okB && (key >> shift) <= lim) ++hl;
       }
     }, L.pre, L.st, L.red);
     const int h = Grp<T>::sum(hl, L.red);
@@ -710,9 +796,8 @@ int run_np(const int64_t* indptr, const int* indices, int n, const std::vector<i
            const float* X, const int* verts, int nv, int* ball, int* hits, double* np_host,
            hipStream_t s) {
   const int G = (int)goff.size() - 1;
-  // grid plan and chunks (host: the cell counts depend on n_g only)
+  // grid sizes (they depend on n_g only)
   std::vector<int> gcell(G), cbase(G + 1, 0), sbase(G, 0), colbase(G + 1, 0);
-  std::vector<int> cs, ce, gcb(G), gce(G);
   int64_t cells = 0, satn = 0, maxng = 1;
   for (int g = 0; g < G; ++g) {
     const int ng = goff[g + 1] - goff[g];
@@ -724,22 +809,19 @@ int run_np(const int64_t* indptr, const int* indices, int n, const std::vector<i
     satn += (int64_t)(Gg + 1) * (Gg + 1);
     cbase[g + 1] = (int)std::min<int64_t>(cells, INT_MAX);
     colbase[g + 1] = colbase[g] + Gg + 1;
-    gcb[g] = (int)cs.size();
-    for (int v = goff[g]; v < goff[g + 1]; v += kNpChunk) {
-      cs.push_back(v);
-      ce.push_back(std::min(goff[g + 1], v + kNpChunk));
-    }
-    gce[g] = (int)cs.size();
   }
   if (cells >= INT_MAX / 2 || satn >= INT_MAX / 2) return fail(TSNET_EINVAL, "tsnet_np: graph too large");
-  const int nc = (int)cs.size();
   const int words = (int)((maxng + 31) / 32);
-  // workers of the light kernel: as many as 512 MB of bitmaps allow, 256..8192 blocks' worth
+  // workers of the light kernel: as many as 512 MB of bitmaps allow, 256..8192
   const int64_t per_worker = (int64_t)words * 4;
   const int light_blocks = (int)std::max<int64_t>(
       64, std::min<int64_t>(2048, ((int64_t)512 << 20) / (per_worker * kNpLightWaves)));
   const int heavy_blocks = 256;
-  const int64_t workers = (int64_t)light_blocks * kNpLightWaves;
+  const int64_t workers = std::max<int64_t>((int64_t)light_blocks * kNpLightWaves, heavy_blocks);
+  const int rtiles = (n + kRadixTile - 1) / kRadixTile;
+  const int64_t rhist_len = (int64_t)256 * rtiles;
+  int gbits = 1;
+  while ((1 << gbits) < G) ++gbits;
   Owned own;
   NpDev a;
   a.indptr = indptr;
@@ -752,24 +834,24 @@ int run_np(const int64_t* indptr, const int* indices, int n, const std::vector<i
   a.words = words;
   a.ball = ball;
   a.hits = hits;
-  int *goff_d, *gcell_d, *cbase_d, *sbase_d, *colbase_d, *cs_d, *ce_d, *gcb_d, *gce_d;
-  int *tsum, *light, *heavy, *counts;
-  float4 *gparam, *part;
+  int *goff_d, *gcell_d, *cbase_d, *sbase_d, *colbase_d, *tsum, *light, *heavy, *counts, *rhist, *rtsum;
+  unsigned *kt, *vt;
   double* npd;
   int rc;
   if ((rc = own.alloc(&goff_d, G + 1, "offsets")) || (rc = own.alloc(&gcell_d, G, "grid")) ||
       (rc = own.alloc(&cbase_d, G + 1, "grid")) || (rc = own.alloc(&sbase_d, G, "grid")) ||
-      (rc = own.alloc(&colbase_d, G + 1, "grid")) || (rc = own.alloc(&cs_d, nc, "chunks")) ||
-      (rc = own.alloc(&ce_d, nc, "chunks")) || (rc = own.alloc(&gcb_d, G, "chunks")) ||
-      (rc = own.alloc(&gce_d, G, "chunks")) || (rc = own.alloc(&gparam, G, "grid")) ||
-      (rc = own.alloc(&part, nc, "boxes")) || (rc = own.alloc(&a.cell_of, n, "cells")) ||
+      (rc = own.alloc(&colbase_d, G + 1, "grid")) || (rc = own.alloc(&a.bx, colbase[G], "bounds")) ||
+      (rc = own.alloc(&a.by, colbase[G], "bounds")) || (rc = own.alloc(&a.cell_of, n, "cells")) ||
       (rc = own.alloc(&a.cnt, cells + 1, "cells")) || (rc = own.alloc(&a.cstart, cells + 1, "cells")) ||
       (rc = own.alloc(&tsum, (cells + kTileScan) / kTileScan + 1, "scan")) ||
       (rc = own.alloc(&a.sat, satn, "summed-area tables")) ||
-      (rc = own.alloc(&a.sorted, n, "sorted points")) || (rc = own.alloc(&light, nv, "lists")) ||
-      (rc = own.alloc(&heavy, nv, "lists")) || (rc = own.alloc(&counts, 8, "counters")) ||
-      (rc = own.alloc(&npd, G, "means")) ||
-      (rc = own.alloc(&a.bits, (size_t)std::max<int64_t>(workers, heavy_blocks) * words, "bitmaps")))
+      (rc = own.alloc(&a.sorted, n, "sorted points")) || (rc = own.alloc(&a.skey, n, "sort")) ||
+      (rc = own.alloc(&a.sval, n, "sort")) || (rc = own.alloc(&kt, n, "sort")) ||
+      (rc = own.alloc(&vt, n, "sort")) || (rc = own.alloc(&rhist, rhist_len + 1, "sort")) ||
+      (rc = own.alloc(&rtsum, (rhist_len + kTileScan) / kTileScan + 1, "sort")) ||
+      (rc = own.alloc(&light, nv, "lists")) || (rc = own.alloc(&heavy, nv, "lists")) ||
+      (rc = own.alloc(&counts, 8, "counters")) || (rc = own.alloc(&npd, G, "means")) ||
+      (rc = own.alloc(&a.bits, (size_t)workers * words, "bitmaps")))
     return rc;
   a.err = counts + 2;
   a.goff = goff_d;
@@ -777,24 +859,19 @@ int run_np(const int64_t* indptr, const int* indices, int n, const std::vector<i
   a.cbase = cbase_d;
   a.sbase = sbase_d;
   a.colbase = colbase_d;
-  a.gparam = gparam;
   MET_HIP(to_dev(goff_d, goff, s));
   MET_HIP(to_dev(gcell_d, gcell, s));
   MET_HIP(to_dev(cbase_d, cbase, s));
   MET_HIP(to_dev(sbase_d, sbase, s));
   MET_HIP(to_dev(colbase_d, colbase, s));
-  MET_HIP(to_dev(cs_d, cs, s));
-  MET_HIP(to_dev(ce_d, ce, s));
-  MET_HIP(to_dev(gcb_d, gcb, s));
-  MET_HIP(to_dev(gce_d, gce, s));
-  const size_t nbits = (size_t)std::max<int64_t>(workers, heavy_blocks) * words;
+  const size_t nbits = (size_t)workers * words;
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_blocks(nbits, 256, 8192)), dim3(256), 0, s, a.bits, nbits, 0u);
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_blocks(cells + 1, 256, 8192)), dim3(256), 0, s,
                      reinterpret_cast<unsigned*>(a.cnt), (size_t)cells + 1, 0u);
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, reinterpret_cast<unsigned*>(counts), (size_t)8, 0u);
   MET_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_np_bbox, dim3(nc), dim3(256), 0, s, a, cs_d, ce_d, part);
-  hipLaunchKernelGGL(k_np_plan, dim3(grid_blocks(G, 256, 1024)), dim3(256), 0, s, a, gcb_d, gce_d, part);
+  const int vb = grid_blocks(n, 256, 8192);
+  hipLaunchKernelGGL(k_np_check, dim3(vb), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_np_classify, dim3(grid_blocks(nv, 256, 8192)), dim3(256), 0, s, a, light, heavy, counts);
   MET_HIP(hipGetLastError());
   int hc[3];
@@ -803,13 +880,27 @@ int run_np(const int64_t* indptr, const int* indices, int n, const std::vector<i
   if (hc[2] & NP_ERR_COORD) return fail(TSNET_EINVAL, "tsnet_np: X holds a non-finite coordinate");
   if (hc[2] & NP_ERR_VERTEX) return fail(TSNET_EINVAL, "tsnet_np: a vertex id is out of range");
   if (hc[2] & NP_ERR_ORDER) return fail(TSNET_EINVAL, "tsnet_np: vertices must be strictly increasing");
+  // cell boundaries: per axis, a sort by coordinate (then, stably, by graph)
+  for (int axis = 0; axis < 2; ++axis) {
+    hipLaunchKernelGGL(k_np_axis_keys, dim3(vb), dim3(256), 0, s, a, axis);
+    MET_HIP(hipGetLastError());
+    MET_HIP(radix_sort(a.skey, a.sval, kt, vt, n, 32, rhist, rtsum, s));
+    if (G > 1) {
+      hipLaunchKernelGGL(k_np_graph_keys, dim3(vb), dim3(256), 0, s, a);
+      MET_HIP(hipGetLastError());
+      MET_HIP(radix_sort(a.skey, a.sval, kt, vt, n, gbits, rhist, rtsum, s));
+    }
+    hipLaunchKernelGGL(k_np_bounds, dim3(grid_blocks(colbase[G], 256, 4096)), dim3(256), 0, s, a, axis,
+                       colbase[G]);
+    MET_HIP(hipGetLastError());
+  }
   // counting sort into cells, cell starts, summed-area tables
-  hipLaunchKernelGGL(k_np_cells, dim3(grid_blocks(n, 256, 8192)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_np_cells, dim3(vb), dim3(256), 0, s, a);
   MET_HIP(hipGetLastError());
   MET_HIP(exclusive_scan<int>(a.cnt, cells, a.cstart, tsum, s));
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_blocks(cells + 1, 256, 8192)), dim3(256), 0, s,
                      reinterpret_cast<unsigned*>(a.cnt), (size_t)cells + 1, 0u);
-  hipLaunchKernelGGL(k_np_scatter, dim3(grid_blocks(n, 256, 8192)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_np_scatter, dim3(vb), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_np_sat, dim3(grid_blocks(colbase[G], 256, 4096)), dim3(256), 0, s, a, colbase[G]);
   MET_HIP(hipGetLastError());
   if (hc[0] > 0)

@@ -7,9 +7,9 @@ Stress: the pair counts exactly, the FP64 sums to 1e-12 relative (1e-10 at
 n = 1e6, where a million terms are summed in different orders).
 
 Layouts: uniform, clustered (90% of the points in a cloud 1e4 times smaller),
-coincident points, points on a quarter lattice (many equal distances), a
-grid drawn on its own lattice and on a line, a far outlier, coordinates near
-the float range; graphs: SBM, grid, tree, star (its leaves take the heavy
+two far clumps, coincident points, points on a quarter lattice (many equal
+distances), a grid drawn on its own lattice, on a line and on a diagonal, a
+far outlier, coordinates near the float range and at scale 1e-30; graphs: SBM, grid, tree, star (its leaves take the heavy
 path: more than 4096 two-hop walks), a batch with a single vertex, isolated
 vertices and a disconnected graph, and the Barabasi-Albert graph of the
 benchmark (n = 1e6) on sampled vertices and sources.
@@ -93,6 +93,18 @@ def test_np_sbm_layouts(api, ctx, layout):
     _np_compare(api, ctx, g, _layouts(g.n, 3)[layout], label=f"sbm 900 {layout}")
 
 
+def test_np_member_outside_candidates(api, ctx):
+    # vertex 1 of this drawing has a 2-hop neighbour outside the cells searched
+    # whose key shares the top bits of the k-th key: it must not count as a hit
+    g = graphs.sbm([100, 100, 100], 0.05, 0.003, 1)
+    X = np.random.default_rng(0).uniform(-1, 1, (g.n, 2))
+    got = _np_compare(api, ctx, g, X, label="sbm 300 uniform")
+    assert int(got["hits"][1]) == 1 and int(got["ball"][1]) == 35
+    rng = np.random.default_rng(1)
+    two = rng.normal(size=(g.n, 2)) * 1e-3 + np.where(rng.random((g.n, 1)) < 0.5, 0, 50)
+    _np_compare(api, ctx, g, two, label="sbm 300 two far clumps")
+
+
 def test_np_grid_drawings(api, ctx):
     rows, cols = 31, 45
     g = graphs.grid(rows, cols)
@@ -106,6 +118,10 @@ def test_np_grid_drawings(api, ctx):
     _np_compare(api, ctx, g, X, label="grid with an outlier")
     big = np.random.default_rng(6).uniform(-3e38, 3e38, (g.n, 2))
     _np_compare(api, ctx, g, big, label="grid near the float range")
+    _np_compare(api, ctx, g, np.random.default_rng(7).normal(size=(g.n, 2)) * 1e-30,
+                label="grid at scale 1e-30 (squared distances underflow)")
+    diag = np.stack([np.arange(g.n), np.arange(g.n)], 1) * 1e-3
+    _np_compare(api, ctx, g, diag, label="grid on a diagonal")
 
 
 def test_np_heavy_star_and_tree(api, ctx):
