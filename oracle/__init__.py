@@ -23,6 +23,8 @@ Modules, each citing the passage of the paper it follows:
 * ``pmds``       -- the Pivot MDS starting layout (Algorithms 1-3, first step).
 * ``metrics``    -- neighbourhood preservation (r = 2) and stress of a layout
                     (Sec. 4.3.1, Sec. 4.3.2).
+* ``quadtree``   -- Barnes-Hut quadtree sums of the repulsion and entropy terms
+                    (BH-tsNET and FIt-tsNET, Algorithms 1-2, Eq. 7).
 
 Parity pins (tests marked ``not gpu``) tie each function to something other
 than itself: closed-form BFS distances, brute-force selection, library root
@@ -30,4 +32,4 @@ finding, finite differences of the cost, zero-sum and symmetry invariants,
 polynomial exactness of the interpolation and library FFT convolution.
 """
 
-from . import tiebreak, neighbours, perplexity, affinities, gradient, interp, step, pmds, metrics  # noqa: F401
+from . import tiebreak, neighbours, perplexity, affinities, gradient, interp, step, pmds, metrics, quadtree  # noqa: F401
