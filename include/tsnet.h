@@ -50,6 +50,10 @@ extern "C" {
 #define TSNET_ATTRACT_ROWS  1  /* one wave per CSR row, x_j gathered from HBM     */
 #define TSNET_ATTRACT_TILED 2  /* row tiles x column windows, x_j read from LDS   */
 
+/* How the repulsion (with Z) and the entropy sums are computed (tsnet_params). */
+#define TSNET_TERMS_INTERP   0  /* FFT-accelerated interpolation (L-tsNET, Sec. 3.3) */
+#define TSNET_TERMS_QUADTREE 1  /* Barnes-Hut quadtree (BH-tsNET / FIt-tsNET, Eq. 7) */
+
 /* bits of the device status word (tsnet_status) */
 #define TSNET_STATUS_NONFINITE   0x1u  /* NaN/Inf in X at some grid set-up          */
 #define TSNET_STATUS_GRID_CAPPED 0x2u  /* span / interval_width > max_intervals      */
@@ -78,6 +82,20 @@ typedef struct tsnet_P_s*   tsnet_P;     /* one problem: graph batch, P, workspa
  *    supports up to about 5.8 million vertices (TSNET_EINVAL beyond). Both
  *    layouts compute the same sums in different orders (FP32 results differ
  *    by rounding only).
+ *  repulsion, entropy: TSNET_TERMS_*, the method of each sum. Both
+ *    interpolated is L-tsNET (Algorithm 3); interpolated repulsion with the
+ *    quadtree entropy is FIt-tsNET (Algorithm 2); both by quadtree is
+ *    BH-tsNET (Algorithm 1). The quadtree is rebuilt on every evaluation:
+ *    per graph, the bounding square split into 2^16 cells per axis (cell of a
+ *    coordinate = floor((x - x_min) 2^16 / side) in FP64), points ordered by
+ *    the interleaved cell bits (y above x) and then by id, a node per
+ *    non-empty 2-bit prefix below a node with two or more points, leaves at
+ *    one point or level 16. For point i a node of width w is a summary of
+ *    its points (their count at their FP64 centre of mass c) when
+ *    w^2 < theta^2 ||X_i - c||^2, tested in FP64; leaves are summed point by
+ *    point; the terms are summed in FP32.
+ *  theta: the opening threshold, in (0, 0.7] when a quadtree is used (then a
+ *    node holding X_i is never a summary).
  */
 typedef struct {
   double  lambda_kl;
@@ -89,6 +107,9 @@ typedef struct {
   int32_t max_intervals;
   int32_t nodes_per_interval;
   int32_t attract_layout;
+  int32_t repulsion;
+  int32_t entropy;
+  double  theta;
 } tsnet_params;
 
 /*

@@ -100,8 +100,9 @@ def _terms(dx, dy, eps, cnt, acc):
     acc[5] += cnt * np.log(eps + r2)
 
 
-def sums(X, theta: float = 0.5, eps: float = 0.05, graph_offsets=None):
-    """Per vertex (z_i, F_rep,i, F_ent,i, L_i) by the quadtree rule, FP64."""
+def sums(X, theta: float = 0.5, eps: float = 0.05, graph_offsets=None, rows=None):
+    """Per vertex (z_i, F_rep,i, F_ent,i, L_i) by the quadtree rule, FP64.
+    With rows (vertex ids), only those vertices are evaluated (others stay 0)."""
     if not 0.0 < theta <= THETA_MAX:
         raise ValueError("theta must be in (0, 0.7]")
     X = np.asarray(X, dtype=np.float32)
@@ -112,11 +113,16 @@ def sums(X, theta: float = 0.5, eps: float = 0.05, graph_offsets=None):
     fent = np.zeros((n, 2))
     lnv = np.zeros(n)
     th2 = theta * theta
+    want = None if rows is None else set(int(r) for r in rows)
     for g in range(len(off) - 1):
         a, b = int(off[g]), int(off[g + 1])
+        if want is not None and not any(a <= r < b for r in want):
+            continue
         root, order, _, side = build(X[a:b])
         pts = X[a:b].astype(np.float64)[order]
         for p in range(b - a):
+            if want is not None and a + int(order[p]) not in want:
+                continue
             xi, yi = pts[p]
             acc = [0.0] * 6
             stack = [root]

@@ -43,7 +43,8 @@ class tsnet_params(ctypes.Structure):
         ("lambda_r", ctypes.c_double), ("eps_r", ctypes.c_double),
         ("interval_width", ctypes.c_double), ("min_intervals", ctypes.c_int32),
         ("max_intervals", ctypes.c_int32), ("nodes_per_interval", ctypes.c_int32),
-        ("attract_layout", ctypes.c_int32),
+        ("attract_layout", ctypes.c_int32), ("repulsion", ctypes.c_int32),
+        ("entropy", ctypes.c_int32), ("theta", ctypes.c_double),
     ]
 
 

@@ -28,6 +28,17 @@ class Params:
     max_intervals: int = 512
     nodes_per_interval: int = 3
     attract_layout: int = 0   # 0 automatic, 1 CSR rows, 2 tiled (row tiles x column windows)
+    repulsion: int = 0        # 0 interpolation, 1 quadtree (Barnes-Hut)
+    entropy: int = 0          # 0 interpolation, 1 quadtree (Eq. 7)
+    theta: float = 0.5        # quadtree opening threshold, (0, 0.7]
+
+    @classmethod
+    def variant(cls, name: str, **kw) -> "Params":
+        """The settings of one of the paper's three algorithms: "L-tsNET"
+        (interpolation), "FIt-tsNET" (quadtree entropy), "BH-tsNET" (quadtree
+        repulsion and entropy)."""
+        rep, ent = {"L-tsNET": (0, 0), "FIt-tsNET": (0, 1), "BH-tsNET": (1, 1)}[name]
+        return cls(repulsion=rep, entropy=ent, **kw)
 
     def to_c(self) -> _lib.tsnet_params:
         p = _lib.tsnet_params()

@@ -32,7 +32,7 @@ int fail(int code, const std::string& msg) {
 static const char* kStageNames[ST_COUNT] = {"bbox_plan", "bin_sort", "spread", "fft_conv",
                                              "gather", "z_reduce", "attract_assemble", "step",
                                              "cost", "direct_f64", "build_P", "pmds",
-                                             "np", "stress"};
+                                             "np", "stress", "quadtree"};
 
 template <typename T>
 static int dmalloc(T** p, size_t count, const char* what) {
@@ -120,6 +120,7 @@ static void free_problem(Problem& P) {
     P.ctx = nullptr;
   }
   free_grid(P);
+  free_quadtree(P);
   dfree(P.ginfo);
   dfree(P.goff_d);
   dfree(P.chunk_graph);
@@ -296,6 +297,12 @@ static int check_params(const tsnet_params* p) {
     return fail(TSNET_EINVAL, "lambda values must be finite");
   if (p->attract_layout < TSNET_ATTRACT_AUTO || p->attract_layout > TSNET_ATTRACT_TILED)
     return fail(TSNET_EINVAL, "attract_layout must be 0, 1 or 2");
+  if ((p->repulsion != TSNET_TERMS_INTERP && p->repulsion != TSNET_TERMS_QUADTREE) ||
+      (p->entropy != TSNET_TERMS_INTERP && p->entropy != TSNET_TERMS_QUADTREE))
+    return fail(TSNET_EINVAL, "repulsion and entropy must be TSNET_TERMS_INTERP or TSNET_TERMS_QUADTREE");
+  if ((p->repulsion == TSNET_TERMS_QUADTREE || p->entropy == TSNET_TERMS_QUADTREE) &&
+      !(p->theta > 0.0 && p->theta <= 0.7))
+    return fail(TSNET_EINVAL, "theta must be in (0, 0.7] with a quadtree");
   return TSNET_OK;
 }
 
@@ -345,6 +352,27 @@ static int run_interp(Problem& P, const float2* X, const tsnet_params& prm, int 
   return TSNET_OK;
 }
 
+// The repulsion (with Z) and entropy sums by the methods prm selects: the
+// interpolation fills all of them; a quadtree evaluation then replaces the
+// ones it is chosen for (both: the interpolation is skipped).
+static int run_terms(Problem& P, const float2* X, const tsnet_params& prm, int with_ln, int with_zi,
+                     double* Z_out, hipStream_t s) {
+  const bool qrep = prm.repulsion == TSNET_TERMS_QUADTREE;
+  const bool qent = prm.entropy == TSNET_TERMS_QUADTREE;
+  int rc;
+  if (!qrep || !qent) {
+    if ((rc = run_interp(P, X, prm, with_ln, with_zi, Z_out, s))) return rc;
+  }
+  if (qrep || qent) {
+    const int terms = (qrep ? QT_REP : 0) | (qent ? QT_ENT : 0) | (qent && with_ln ? QT_LN : 0);
+    StageScope t(*P.ctx, ST_QUADTREE, s);
+    if ((rc = run_quadtree(P, X, prm.theta, (float)prm.eps_r, terms, qrep && with_zi,
+                           qrep ? Z_out : nullptr, s)))
+      return rc;
+  }
+  return TSNET_OK;
+}
+
 static int grad_impl(tsnet_ctx ctx, tsnet_P Pp, const float* X, const tsnet_params* prm, float* G,
                      double* Z_out, float* F_attr, float* F_rep, float* F_ent, float* Z_i,
                      void* stream) {
@@ -358,7 +386,7 @@ static int grad_impl(tsnet_ctx ctx, tsnet_P Pp, const float* X, const tsnet_para
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const float2* X2 = reinterpret_cast<const float2*>(X);
   // the gather also reduces Z; Z_i is stored only when asked for
-  if ((rc = run_interp(P, X2, *prm, 0, Z_i != nullptr, Z_out, s))) return rc;
+  if ((rc = run_terms(P, X2, *prm, 0, Z_i != nullptr, Z_out, s))) return rc;
   const bool tiled = use_tiles(P, *prm);
   if (tiled && P.tile_T == 0 && (rc = build_tiles(P, s))) return rc;
   {
@@ -393,6 +421,9 @@ void tsnet_default_params(tsnet_params* p) {
   p->min_intervals = 50;
   p->max_intervals = 512;
   p->nodes_per_interval = 3;
+  p->repulsion = TSNET_TERMS_INTERP;
+  p->entropy = TSNET_TERMS_INTERP;
+  p->theta = 0.5;
 }
 
 void tsnet_default_step_params(tsnet_step_params* p) {
@@ -712,7 +743,7 @@ int tsnet_cost(tsnet_ctx ctx, tsnet_P Pp, const float* X, const tsnet_params* pr
   if (!X || !cost) return fail(TSNET_EINVAL, "X and cost must not be NULL");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const float2* X2 = reinterpret_cast<const float2*>(X);
-  if ((rc = run_interp(Pp->p, X2, *prm, 1, 0, nullptr, s))) return rc;
+  if ((rc = run_terms(Pp->p, X2, *prm, 1, 0, nullptr, s))) return rc;
   StageScope t(ctx->c, ST_COST, s);
   TSNET_LAUNCH(launch_cost(Pp->p, X2, *prm, cost, s));
   return TSNET_OK;

@@ -69,7 +69,7 @@ struct PlanParams {
 // Stage ids for optional per-stage timing.
 enum Stage {
   ST_BBOX = 0, ST_BIN, ST_SPREAD, ST_FFT, ST_GATHER, ST_ZRED, ST_ATTR, ST_STEP, ST_COST,
-  ST_DIRECT, ST_BUILD, ST_PMDS, ST_NP, ST_STRESS, ST_COUNT
+  ST_DIRECT, ST_BUILD, ST_PMDS, ST_NP, ST_STRESS, ST_QUADTREE, ST_COUNT
 };
 
 // ---------------------------------------------------------------- contexts
@@ -86,6 +86,8 @@ struct Ctx {
   double stage_ms[ST_COUNT] = {0};
   int64_t stage_calls[ST_COUNT] = {0};
 };
+
+struct QuadWs;  // quadtree workspace (quadtree.hip), allocated on first use
 
 struct Problem {
   Ctx* ctx = nullptr;
@@ -155,6 +157,7 @@ struct Problem {
   double* cost_part = nullptr;        // [num_chunks * 5]
   double* direct_part = nullptr;      // scratch of the FP64 direct kernel
   size_t direct_part_len = 0;
+  QuadWs* qt = nullptr;               // quadtree sums (repulsion / entropy by quadtree)
 };
 
 // ---------------------------------------------------------------- errors
@@ -214,6 +217,17 @@ hipError_t launch_direct(Problem& P, const double2* X, const tsnet_params& prm, 
 int run_pmds(const int64_t* indptr, const int* indices, int n, const std::vector<int>& goff,
              int pivots, uint64_t seed, double scale, float* X, int* pivots_out, double* eig_host,
              int* levels_host, hipStream_t s);
+
+// Barnes-Hut quadtree sums (quadtree.hip): the tree is rebuilt from X and
+// each point's sums are written where the interpolation puts them: QT_REP
+// fills rep_ent.xy, the per-vertex z (into zi when with_zi) and Z per graph
+// (zg, and Z_out when not NULL); QT_ENT fills rep_ent.zw; QT_LN fills lnv
+// (with the self term ln(eps), as the gather does).
+// Enqueues only (no host synchronisation), so it may be captured.
+enum { QT_REP = 1, QT_ENT = 2, QT_LN = 4 };
+void free_quadtree(Problem& P);
+int run_quadtree(Problem& P, const float2* X, double theta, float eps, int terms, int with_zi,
+                 double* Z_out, hipStream_t s);
 
 // layout quality metrics (metrics.hip); synchronous. Neighbourhood preservation:
 // verts (device, strictly increasing) or NULL for all n, ball/hits [nv] on the
