@@ -228,6 +228,8 @@ def main():
                     help="pivots of the Pivot MDS leg (0: skip it)")
     ap.add_argument("--metric-sources", type=int, default=64,
                     help="stress sources for the quality-metric leg on the final layout (0: skip the leg)")
+    ap.add_argument("--variant-steps", type=int, default=100,
+                    help="timed steps of the FIt-tsNET and BH-tsNET variants (0: skip them)")
     ap.add_argument("--runs", type=int, default=5,
                     help="timed runs from the initial layout (plain launches); value is their mean")
     ap.add_argument("--last", type=int, default=100,
@@ -505,6 +507,66 @@ def main():
         log(f"direct f64: {dwall * 1e3:.1f} ms/iter; interp speedup {iters_per_s * dwall:.1f}x; "
             f"rel L2 {err:.2e}")
 
+    # the paper's other two algorithms on the same problem: FIt-tsNET (quadtree
+    # entropy) and BH-tsNET (quadtree repulsion and entropy), each from the initial
+    # layout with the same warm-up, then --variant-steps timed steps
+    variants = None
+    if args.variant_steps > 0:
+        variants = {}
+        if direct is not None:
+            # exact FP64 terms at the same layout: errors of the repulsion F_rep / Z and of
+            # F_ent per method (the gradient error grows where attraction and repulsion cancel)
+            _, Zd_t, Td = prob.grad_direct_f64(X64, prm, with_terms=True)
+            rep_d = Td[:, 2:4] / Zd_t[0]
+            ent_d = Td[:, 4:6]
+
+            def term_errors(pv):
+                t = prob.grad_terms(X, pv)
+                torch.cuda.synchronize()
+                rep = t["F_rep"].double() / t["Z"][0]
+                return {"rel_l2_vs_direct": float(torch.linalg.norm(t["G"].double() - Gd) / torch.linalg.norm(Gd)),
+                        "rep_over_Z_rel_l2": float(torch.linalg.norm(rep - rep_d) / torch.linalg.norm(rep_d)),
+                        "F_ent_rel_l2": float(torch.linalg.norm(t["F_ent"].double() - ent_d) / torch.linalg.norm(ent_d))}
+            direct["terms_L-tsNET"] = term_errors(prm)
+            direct["BH-tsNET_theta_0.25"] = term_errors(api.Params.variant("BH-tsNET", theta=0.25,
+                                                                             max_intervals=args.max_intervals))
+        names = ("FIt-tsNET", "BH-tsNET")
+        for name in names:  # accuracy first, all at the layout the direct kernel saw
+            pv = api.Params.variant(name, max_intervals=args.max_intervals)
+            variants[name] = {"theta": pv.theta}
+            if direct is not None:
+                variants[name].update(term_errors(pv))
+        for name in names:
+            pv = api.Params.variant(name, max_intervals=args.max_intervals)
+            entry = variants[name]
+            restart()
+            for it in range(args.warmup):
+                prob.grad(X, pv, G=G, Z=Z, stream=stream)
+                prob.step(X, upd, gains, G, it, sp, stream=stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for it in range(args.warmup, args.warmup + args.variant_steps):
+                prob.grad(X, pv, G=G, Z=Z, stream=stream)
+                prob.step(X, upd, gains, G, it, sp, stream=stream)
+            torch.cuda.synchronize()
+            vw = time.perf_counter() - t0
+            ctx.set_timing("all")
+            for it in range(args.warmup + args.variant_steps, args.warmup + args.variant_steps + 10):
+                prob.grad(X, pv, G=G, Z=Z, stream=stream)
+                prob.step(X, upd, gains, G, it, sp, stream=stream)
+            torch.cuda.synchronize()
+            vst = {k: v[0] / v[1] for k, v in ctx.stage_times().items() if v[1]}
+            ctx.set_timing(None)
+            entry.update({"iters_per_s": args.variant_steps / vw, "steps": args.variant_steps,
+                          "ms_per_step": vw / args.variant_steps * 1e3, "stages_ms": vst})
+            log(f"{name}: {entry['iters_per_s']:.1f} iters/s, quadtree stage "
+                f"{vst.get('quadtree', 0.0):.3f} ms" +
+                (f", rel L2 vs direct: G {entry['rel_l2_vs_direct']:.2e}, F_rep/Z "
+                 f"{entry['rep_over_Z_rel_l2']:.2e}, F_ent {entry['F_ent_rel_l2']:.2e}"
+                 if "rel_l2_vs_direct" in entry else ""))
+        if direct is not None:
+            log(f"L-tsNET terms vs direct: {direct['terms_L-tsNET']}; BH theta 0.25: {direct['BH-tsNET_theta_0.25']}")
+
     out = {
         "metric": METRIC,
         "value": iters_per_s,
@@ -560,6 +622,7 @@ def main():
         "metrics": met,
         "stages_ms": stages,
         "direct_f64": direct,
+        "variants": variants,
     }
     print(json.dumps(out), flush=True)
 

@@ -133,15 +133,36 @@ __global__ __launch_bounds__(256) void k_qt_bbox(QtDev a, const int* cs, const i
   }
 }
 
-__global__ void k_qt_plan(QtDev a, const GraphInfo* gi) {
-  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < a.G; g += gridDim.x * blockDim.x) {
-    float mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
-    for (int c = gi[g].chunk_begin; c < gi[g].chunk_end; ++c) {
-      const float4 p = a.w.part[c];
-      mnx = fminf(mnx, p.x);
-      mny = fminf(mny, p.y);
-      mxx = fmaxf(mxx, p.z);
-      mxy = fmaxf(mxy, p.w);
+// One block per graph: its box from the chunk partials (block-strided, then
+// a wave reduction), then the cell scale.
+__global__ __launch_bounds__(256) void k_qt_plan(QtDev a, const GraphInfo* gi) {
+  __shared__ float red[4][256 / kWave];
+  const int g = blockIdx.x;
+  float mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
+  for (int c = gi[g].chunk_begin + threadIdx.x; c < gi[g].chunk_end; c += blockDim.x) {
+    const float4 p = a.w.part[c];
+    mnx = fminf(mnx, p.x);
+    mny = fminf(mny, p.y);
+    mxx = fmaxf(mxx, p.z);
+    mxy = fmaxf(mxy, p.w);
+  }
+  mnx = wave_min(mnx);
+  mny = wave_min(mny);
+  mxx = wave_max(mxx);
+  mxy = wave_max(mxy);
+  if (lane_id() == 0) {
+    red[0][wave_id()] = mnx;
+    red[1][wave_id()] = mny;
+    red[2][wave_id()] = mxx;
+    red[3][wave_id()] = mxy;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 256 / kWave; ++w) {
+      mnx = fminf(mnx, red[0][w]);
+      mny = fminf(mny, red[1][w]);
+      mxx = fmaxf(mxx, red[2][w]);
+      mxy = fmaxf(mxy, red[3][w]);
     }
     double side = fmax((double)mxx - (double)mnx, (double)mxy - (double)mny);
     if (!(side > 0.0) || !isfinite(side)) side = 1.0;
@@ -318,12 +339,23 @@ __global__ __launch_bounds__(256) void k_qt_zchunks(QtDev a, const int* cs, cons
   if (threadIdx.x == 0) zpart[c] = red[0];
 }
 
-__global__ void k_qt_zgraphs(QtDev a, const GraphInfo* gi, const double* zpart, double* zg, double* Z_out) {
-  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < a.G; g += gridDim.x * blockDim.x) {
-    double z = 0.0;
-    for (int c = gi[g].chunk_begin; c < gi[g].chunk_end; ++c) z += zpart[c];
-    zg[g] = z;
-    if (Z_out) Z_out[g] = z;
+// One block per graph: its chunk sums in a fixed order (block-strided, then a
+// tree reduction).
+__global__ __launch_bounds__(256) void k_qt_zgraphs(const GraphInfo* gi, const double* zpart, double* zg,
+                                                    double* Z_out) {
+  __shared__ double red[256];
+  const int g = blockIdx.x;
+  double z = 0.0;
+  for (int c = gi[g].chunk_begin + threadIdx.x; c < gi[g].chunk_end; c += blockDim.x) z += zpart[c];
+  red[threadIdx.x] = z;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    zg[g] = red[0];
+    if (Z_out) Z_out[g] = red[0];
   }
 }
 
@@ -402,9 +434,8 @@ int run_quadtree(Problem& P, const float2* X, double theta, float eps, int terms
   a.w = *P.qt;
   const int n = P.n;
   const int vb = (int)std::max<int64_t>(1, std::min<int64_t>(8192, (n + 255) / 256));
-  const int gb = std::max(1, std::min(1024, (P.G + 255) / 256));
   QT_LAUNCH(hipLaunchKernelGGL(k_qt_bbox, dim3(P.num_chunks), dim3(256), 0, s, a, P.chunk_start, P.chunk_end));
-  QT_LAUNCH(hipLaunchKernelGGL(k_qt_plan, dim3(gb), dim3(256), 0, s, a, P.ginfo));
+  QT_LAUNCH(hipLaunchKernelGGL(k_qt_plan, dim3(P.G), dim3(256), 0, s, a, P.ginfo));
   QT_LAUNCH(hipLaunchKernelGGL(k_qt_codes, dim3(vb), dim3(256), 0, s, a));
   hipError_t e = radix_sort(a.w.key, a.w.val, a.w.kt, a.w.vt, n, 32, a.w.rhist, a.w.rtsum, s);
   if (e != hipSuccess) return fail(TSNET_EHIP, std::string("quadtree sort: ") + hipGetErrorString(e));
@@ -425,7 +456,7 @@ int run_quadtree(Problem& P, const float2* X, double theta, float eps, int terms
   if (terms & QT_REP) {
     QT_LAUNCH(hipLaunchKernelGGL(k_qt_zchunks, dim3(P.num_chunks), dim3(256), 0, s, a, P.chunk_start,
                                  P.chunk_end, P.zpart));
-    QT_LAUNCH(hipLaunchKernelGGL(k_qt_zgraphs, dim3(gb), dim3(256), 0, s, a, P.ginfo, P.zpart, P.zg, Z_out));
+    QT_LAUNCH(hipLaunchKernelGGL(k_qt_zgraphs, dim3(P.G), dim3(256), 0, s, P.ginfo, P.zpart, P.zg, Z_out));
   }
   return TSNET_OK;
 }
