@@ -215,6 +215,35 @@ int tsnet_pmds(tsnet_ctx ctx, const int64_t* indptr, const int32_t* indices, int
                int32_t* levels_host, void* stream);
 
 /*
+ * One stage of a layout run: `iterations` gradient + step iterations with
+ * `params` (cost weights, interpolation settings and the L-tsNET / FIt-tsNET
+ * / BH-tsNET choice of the sums).
+ */
+typedef struct {
+  int32_t      iterations;
+  int32_t      reserved;       /* 0 */
+  tsnet_params params;
+} tsnet_stage;
+
+/*
+ * The gradient-descent loop of Algorithms 1-3 over a table of stages: for
+ * each stage and each of its iterations, tsnet_grad with the stage's
+ * parameters, then tsnet_step with iteration number first_iter + (iterations
+ * run so far). The paper changes the multipliers lambda between stages of
+ * the descent (Sec. 2.1) without giving values; a two-stage table expresses
+ * such a schedule. X, update, gains: device float [n][2], updated in place;
+ * G: device float [n][2] (the last gradient); Z: device double [num_graphs]
+ * (the last Z) or NULL. Every stage's parameters are checked before anything
+ * is enqueued (TSNET_EINVAL: the message names the stage). Enqueues only, on
+ * the stream, the same kernels in the same order as the per-iteration calls
+ * (results are bit-identical to them); run one gradient first if the run is
+ * to be captured into a graph (the first evaluation sizes the workspace).
+ */
+int tsnet_run(tsnet_ctx ctx, tsnet_P P, float* X, float* update, float* gains, float* G, double* Z,
+              const tsnet_stage* stages, int32_t num_stages, int32_t first_iter,
+              const tsnet_step_params* sp, void* stream);
+
+/*
  * Neighbourhood preservation with r = 2 (Sec. 4.3.1), the first quality
  * measure of the experiments. The paper gives the formula; the readings are:
  *  - N_G(v): the vertices 1 or 2 hops from v, v excluded; k_v = |N_G(v)|;

@@ -33,7 +33,7 @@ EXPORTS = (
     "tsnet_grad", "tsnet_grad_terms", "tsnet_step", "tsnet_cost", "tsnet_grad_direct_f64",
     "tsnet_grid_info", "tsnet_status", "tsnet_set_timing", "tsnet_stage_count",
     "tsnet_stage_name", "tsnet_stage_times", "tsnet_last_error",
-    "tsnet_default_pmds_params", "tsnet_pmds", "tsnet_np", "tsnet_stress",
+    "tsnet_default_pmds_params", "tsnet_pmds", "tsnet_np", "tsnet_stress", "tsnet_run",
 )
 
 
@@ -46,6 +46,10 @@ class tsnet_params(ctypes.Structure):
         ("attract_layout", ctypes.c_int32), ("repulsion", ctypes.c_int32),
         ("entropy", ctypes.c_int32), ("theta", ctypes.c_double),
     ]
+
+
+class tsnet_stage(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("reserved", ctypes.c_int32), ("params", tsnet_params)]
 
 
 class tsnet_step_params(ctypes.Structure):
@@ -92,6 +96,7 @@ _SIGS = {
     "tsnet_default_pmds_params": (None, [_P(tsnet_pmds_params)]),
     "tsnet_pmds": (_i32, [_vp, _vp, _vp, _i32, _i64, _vp, _i32, _P(tsnet_pmds_params), _vp, _vp,
                           _vp, _vp, _vp]),
+    "tsnet_run": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _P(tsnet_step_params), _vp]),
     "tsnet_np": (_i32, [_vp, _vp, _vp, _i32, _i64, _vp, _i32, _vp, _vp, _i32, _vp, _vp, _vp, _vp]),
     "tsnet_stress": (_i32, [_vp, _vp, _vp, _i32, _i64, _vp, _i32, _vp, _vp, _i32, _vp, _vp, _vp]),
     "tsnet_ctx_create": (_i32, [_P(_vp), _i32]),

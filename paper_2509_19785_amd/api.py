@@ -270,6 +270,24 @@ class Problem:
                              _dev(G, torch.float32, (n, 2), "G"), ctypes.byref(spc), int(it),
                              _stream(stream)))
 
+    def run(self, X, update, gains, G, stages, first_iter: int = 0, sp: StepParams = StepParams(),
+            Z=None, stream=None):
+        """tsnet_run: the descent over a table of stages, each (iterations, Params);
+        X, update and gains are updated in place, G and Z hold the last gradient."""
+        n = self.n
+        arr = (_lib.tsnet_stage * len(stages))()
+        for k, (iters, prm) in enumerate(stages):
+            arr[k].iterations = int(iters)
+            arr[k].reserved = 0
+            arr[k].params = prm.to_c()
+        spc = sp.to_c()
+        check(lib.tsnet_run(self.ctx.handle, self.handle, _dev(X, torch.float32, (n, 2), "X"),
+                            _dev(update, torch.float32, (n, 2), "update"),
+                            _dev(gains, torch.float32, (n, 2), "gains"),
+                            _dev(G, torch.float32, (n, 2), "G"),
+                            _opt(Z, torch.float64, (self.num_graphs,), "Z"), arr, len(stages),
+                            int(first_iter), ctypes.byref(spc), _stream(stream)))
+
     def cost(self, X: torch.Tensor, params: Params = Params(), out=None, stream=None):
         if out is None:
             out = torch.empty((self.num_graphs, 4), dtype=torch.float64, device=X.device)
@@ -325,6 +343,16 @@ def pmds(ctx: Context, indptr, indices, pivots: int = 50, seed: int = 0, scale: 
                          X.data_ptr(), piv.data_ptr(), eig.ctypes.data, ctypes.byref(levels),
                          _stream(stream)))
     return {"X": X, "pivots": piv, "eig": eig, "levels": levels.value}
+
+
+def staged_schedule(total: int = 500, switch: int = 250, variant: str = "L-tsNET", **kw) -> list:
+    """A two-stage table for Problem.run: compression without entropy up to
+    `switch` (lambda_c 1.2, lambda_r 0), then light compression with entropy
+    (lambda_c 0.01, lambda_r 0.01). The paper changes the multipliers between
+    stages of the descent without giving values; these are this project's."""
+    first = Params.variant(variant, lambda_c=1.2, lambda_r=0.0, **kw)
+    second = Params.variant(variant, lambda_c=0.01, lambda_r=0.01, **kw)
+    return [(min(switch, total), first), (max(0, total - switch), second)]
 
 
 def _graph_dev(ctx: Context, indptr, indices):

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -732,6 +733,32 @@ int tsnet_step(tsnet_ctx ctx, tsnet_P Pp, float* X, float* update, float* gains,
   TSNET_LAUNCH(launch_step(Pp->p, reinterpret_cast<float2*>(X), reinterpret_cast<float2*>(update),
                            reinterpret_cast<float2*>(gains), reinterpret_cast<const float2*>(G), *sp,
                            iter, s));
+  return TSNET_OK;
+}
+
+int tsnet_run(tsnet_ctx ctx, tsnet_P P, float* X, float* update, float* gains, float* G, double* Z,
+              const tsnet_stage* stages, int32_t num_stages, int32_t first_iter,
+              const tsnet_step_params* sp, void* stream) {
+  int rc = check_call(ctx, P);
+  if (rc) return rc;
+  if (!stages || num_stages < 1) return fail(TSNET_EINVAL, "stages must hold at least one stage");
+  if (first_iter < 0) return fail(TSNET_EINVAL, "first_iter must be >= 0");
+  int64_t total = 0;
+  for (int k = 0; k < num_stages; ++k) {
+    if (stages[k].iterations < 0 || stages[k].reserved != 0)
+      return fail(TSNET_EINVAL, "stage " + std::to_string(k) + ": iterations must be >= 0, reserved 0");
+    if ((rc = check_params(&stages[k].params)))
+      return fail(rc, "stage " + std::to_string(k) + ": " + g_err);
+    total += stages[k].iterations;
+  }
+  if (first_iter + total > INT_MAX) return fail(TSNET_EINVAL, "too many iterations");
+  int it = first_iter;
+  for (int k = 0; k < num_stages; ++k)
+    for (int i = 0; i < stages[k].iterations; ++i, ++it) {
+      if ((rc = grad_impl(ctx, P, X, &stages[k].params, G, Z, nullptr, nullptr, nullptr, nullptr, stream)))
+        return rc;
+      if ((rc = tsnet_step(ctx, P, X, update, gains, G, sp, it, stream))) return rc;
+    }
   return TSNET_OK;
 }
 

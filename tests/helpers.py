@@ -31,3 +31,11 @@ class P32:
         self.rowptr = P.rowptr
         self.col = P.col
         self.val = P.val.astype(np.float32).astype(np.float64)
+
+
+def ulp_diff(a32, b64):
+    """Distance in FP32 ulps between GPU values and the oracle's FP64 values."""
+    b32 = np.asarray(b64).astype(np.float32)
+    ai = np.asarray(a32, dtype=np.float32).view(np.int32).astype(np.int64)
+    bi = b32.view(np.int32).astype(np.int64)
+    return np.abs(ai - bi)

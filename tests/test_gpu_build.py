@@ -10,7 +10,7 @@ import math
 import numpy as np
 import pytest
 
-from helpers import say
+from helpers import say, ulp_diff
 from oracle import affinities, perplexity
 from synth import graphs
 
@@ -35,14 +35,6 @@ def ctx(api):
 def _build(api, ctx, g, u, k=0, seed=0, mode="hash", goff=None):
     return api.Problem.build(ctx, g.indptr, g.indices, u, k=k, seed=seed, tie_mode=mode,
                              graph_offsets=goff)
-
-
-def ulp_diff(a32, b64):
-    """Distance in FP32 ulps between GPU values and the oracle's FP64 values."""
-    b32 = b64.astype(np.float32)
-    ai = a32.view(np.int32).astype(np.int64)
-    bi = b32.view(np.int32).astype(np.int64)
-    return np.abs(ai - bi)
 
 
 def compare(api, ctx, g, u, k=0, seed=0, mode="hash", goff=None, label=""):
