@@ -109,6 +109,51 @@ def pmds_cpu_baseline(g, pivots: int, sample: int = 3):
                       f"extrapolated; the eigen-solve and projection are not counted"}
 
 
+def small_n_leg(api, ctx, iters: int):
+    """The 32 x 32 grid (n = 1024): L-tsNET (P from k = 120) against the original
+    tsNET's full P (k = n - 1), both from the same Pivot MDS start with the
+    two-stage schedule, then the quality of each final layout (NP of every
+    vertex, stress over every source) and the FP64 direct gradient's rate."""
+    import torch
+    from synth import graphs
+    g = graphs.workload_grid32()
+    start = api.pmds(ctx, g.indptr, g.indices, pivots=50, seed=0)["X"]
+    sched = api.staged_schedule(iters)
+    res = {"workload": "grid 32 x 32, perplexity 40, Pivot MDS start, "
+                       f"{iters} iterations ({sched[0][0]} + {sched[1][0]})"}
+    for name, k in (("L-tsNET k=120", 120), ("tsNET full P k=1023", g.n - 1)):
+        prob = api.Problem.build(ctx, g.indptr, g.indices, 40.0, k=k, seed=0)
+        X = start.clone()
+        U, Ga, G = torch.zeros_like(X), torch.ones_like(X), torch.empty_like(X)
+        prob.run(X, U, Ga, G, [(1, sched[0][1])])          # first evaluation sizes the workspace
+        X.copy_(start)
+        U.zero_()
+        Ga.fill_(1.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prob.run(X, U, Ga, G, sched)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        q = api.neighbourhood_preservation(ctx, g.indptr, g.indices, X)
+        st = api.stress(ctx, g.indptr, g.indices, X, np.arange(g.n, dtype=np.int32))
+        entry = {"nnz_P": prob.nnz, "iters_per_s": iters / wall, "np": float(q["np"][0]),
+                 "stress": float(st["stress"][0]), "stress_best_scale": float(st["stress_best_scale"][0])}
+        if k == g.n - 1:
+            X64 = X.double()
+            prob.grad_direct_f64(X64)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(20):
+                prob.grad_direct_f64(X64)
+            torch.cuda.synchronize()
+            entry["direct_f64_grads_per_s"] = 20 / (time.perf_counter() - t0)
+        res[name] = entry
+        log(f"small n, {name}: {entry['iters_per_s']:.0f} iters/s, NP {entry['np']:.4f}, "
+            f"stress {entry['stress']:.4f} (best scale {entry['stress_best_scale']:.4f})")
+        prob.free()
+    return res
+
+
 def metrics_cpu_baseline(g, X, np_sample: int = 16, stress_sample: int = 2, sources: int = 64):
     """The oracle's metrics on the host: neighbourhood preservation of `np_sample`
     vertices extrapolated to all n, stress of `stress_sample` sources extrapolated
@@ -228,6 +273,8 @@ def main():
                     help="pivots of the Pivot MDS leg (0: skip it)")
     ap.add_argument("--metric-sources", type=int, default=64,
                     help="stress sources for the quality-metric leg on the final layout (0: skip the leg)")
+    ap.add_argument("--small-iters", type=int, default=500,
+                    help="iterations of the 32 x 32 grid comparison of L-tsNET and full-P tsNET (0: skip)")
     ap.add_argument("--variant-steps", type=int, default=100,
                     help="timed steps of the FIt-tsNET and BH-tsNET variants (0: skip them)")
     ap.add_argument("--runs", type=int, default=5,
@@ -567,6 +614,8 @@ def main():
         if direct is not None:
             log(f"L-tsNET terms vs direct: {direct['terms_L-tsNET']}; BH theta 0.25: {direct['BH-tsNET_theta_0.25']}")
 
+    small = small_n_leg(api, ctx, args.small_iters) if args.small_iters > 0 else None
+
     out = {
         "metric": METRIC,
         "value": iters_per_s,
@@ -623,6 +672,7 @@ def main():
         "stages_ms": stages,
         "direct_f64": direct,
         "variants": variants,
+        "small_n": small,
     }
     print(json.dumps(out), flush=True)
 
