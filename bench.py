@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 # (FETCH_SIZE x 2 + WRITE_SIZE x 1, KiB x 1024; the factors from a 1 GiB device
 # copy), summarised under profiles/. They hold for the kernel source with the
 # hash below only: for any other source the traffic is reported as null.
-ATTRACT_TRAFFIC_BYTES = 1_821_298_001
+ATTRACT_TRAFFIC_BYTES = 1_822_643_104
 ATTRACT_TRAFFIC_SOURCE_SHA256 = "3e09ae0f20769c8f26ed83598c5b41605f888b4fed5a6877bd6978d66814e0a1"
 
 
