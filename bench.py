@@ -547,6 +547,12 @@ def main():
             "ms_per_iter": dwall * 1e3,
             "pairs_per_s": pairs / dwall,
             "speedup_of_interp": iters_per_s * dwall,
+            # per pair: 2 differences, r2 (an fma and a product), 1 + r2 and eps + r2,
+            # their product, a reciprocal with Newton steps (5), w, ke, w^2, the z sum
+            # and four fmas: 25 FP64 operations, an fma counted as 2
+            "flop_per_pair": 25,
+            "fp64_tflops": pairs / dwall * 25 / 1e12,
+            "frac_of_fp64_peak": pairs / dwall * 25 / 78.6e12,
             "rel_l2_interp_vs_direct": err,
             "Z_direct": float(Zd.item()),
             "Z_interp": float(Z.item()),
@@ -613,6 +619,17 @@ def main():
                  if "rel_l2_vs_direct" in entry else ""))
         if direct is not None:
             log(f"L-tsNET terms vs direct: {direct['terms_L-tsNET']}; BH theta 0.25: {direct['BH-tsNET_theta_0.25']}")
+        # the paper's whole-run speed-ups (CPU implementations, hardware not named),
+        # beside the ratios of the iteration rates measured here
+        variants["paper_speedups"] = {
+            "source": "Sec. 4.2, averages over its benchmark graphs, 500 iterations, CPU (hardware not named)",
+            "L-tsNET / tsNET runtime": "98.6 % less (about 71x)", "FIt-tsNET / tsNET runtime": "96 % less (about 25x)",
+            "BH-tsNET / tsNET runtime": "93.5 % less (about 15x)",
+            "L-tsNET vs BH-tsNET": 4.7, "L-tsNET vs FIt-tsNET": 3.0, "FIt-tsNET vs BH-tsNET": 1.58}
+        variants["measured_ratios"] = {
+            "L-tsNET vs BH-tsNET": iters_per_s / variants["BH-tsNET"]["iters_per_s"],
+            "L-tsNET vs FIt-tsNET": iters_per_s / variants["FIt-tsNET"]["iters_per_s"],
+            "FIt-tsNET vs BH-tsNET": variants["FIt-tsNET"]["iters_per_s"] / variants["BH-tsNET"]["iters_per_s"]}
 
     small = small_n_leg(api, ctx, args.small_iters) if args.small_iters > 0 else None
 
