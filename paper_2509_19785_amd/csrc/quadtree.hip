@@ -45,6 +45,13 @@ struct QtParam {
   double x0, y0, side, scale;
 };
 
+// One node, 32 bytes: its sorted range, the first node after its subtree and
+// its level, then its centre of mass (one record, so one line per visit).
+struct __align__(32) QtNode {
+  int4 b;      // (start, count, first node after the subtree, level)
+  double2 c;   // centre of mass
+};
+
 struct QuadWs {
   int n = 0, G = 0, max_nodes = 0, gbits = 1;
   QtParam* gp = nullptr;     // [G]
@@ -57,8 +64,7 @@ struct QuadWs {
   double* dtsum = nullptr;
   int* base = nullptr;       // [n + 1] nodes starting at each position, then the first node index
   int* itsum = nullptr;
-  int4* nb = nullptr;        // [max_nodes] (start, count, first node after the subtree, level)
-  double2* nc = nullptr;     // [max_nodes] centre of mass
+  QtNode* nodes = nullptr;   // [max_nodes]
   float* zv = nullptr;       // [n] sum_j z_ij per vertex
 };
 
@@ -255,8 +261,10 @@ __global__ __launch_bounds__(256) void k_qt_nodes(QtDev a) {
       lo_hint = e;
       const int idx = b0 + (l - lmin);
       const int cnt = e - p;
-      a.w.nb[idx] = make_int4(p, cnt, a.w.base[e], l);
-      a.w.nc[idx] = make_double2((a.w.px[e] - sx) / cnt, (a.w.py[e] - sy) / cnt);
+      QtNode nd;
+      nd.b = make_int4(p, cnt, a.w.base[e], l);
+      nd.c = make_double2((a.w.px[e] - sx) / cnt, (a.w.py[e] - sy) / cnt);
+      a.w.nodes[idx] = nd;
     }
   }
 }
@@ -291,7 +299,13 @@ __global__ __launch_bounds__(256) void k_qt_traverse(QtDev a, double th2, float 
     QtAcc acc;
     int node = a.w.base[a.goff[g]];
     while (node < end) {
-      const int4 b = a.w.nb[node];
+      // the whole record at once: the centre is not needed for a leaf, but
+      // loading it with the rest costs no extra round trip (the empty asm
+      // takes its registers, so both halves are in flight together)
+      const int4* rp = reinterpret_cast<const int4*>(a.w.nodes + node);
+      const int4 b = rp[0];
+      const int4 h = rp[1];
+      asm volatile("" ::"v"(h.x), "v"(h.y), "v"(h.z), "v"(h.w));
       if (b.y == 1 || b.w == kQtLevels) {  // leaf: its points one by one
         for (int q = b.x; q < b.x + b.y; ++q) {
           if (q == sp) continue;
@@ -301,7 +315,7 @@ __global__ __launch_bounds__(256) void k_qt_traverse(QtDev a, double th2, float 
         node = b.z;
         continue;
       }
-      const double2 cm = a.w.nc[node];
+      const double2 cm = make_double2(__hiloint2double(h.y, h.x), __hiloint2double(h.w, h.z));
       const double dx = (double)xi.x - cm.x, dy = (double)xi.y - cm.y;
       const double wd = ldexp(side, -b.w);
       if (wd * wd < th2 * (dx * dx + dy * dy)) {
@@ -394,8 +408,7 @@ int ensure_quadtree(Problem& P) {
       (rc = qt_alloc(&w->dtsum, (size_t)n / kTileScan + 2, "sums")) ||
       (rc = qt_alloc(&w->base, (size_t)n + 1, "nodes")) ||
       (rc = qt_alloc(&w->itsum, (size_t)n / kTileScan + 2, "nodes")) ||
-      (rc = qt_alloc(&w->nb, (size_t)w->max_nodes, "nodes")) ||
-      (rc = qt_alloc(&w->nc, (size_t)w->max_nodes, "nodes")) || (rc = qt_alloc(&w->zv, n, "z"))) {
+      (rc = qt_alloc(&w->nodes, (size_t)w->max_nodes, "nodes")) || (rc = qt_alloc(&w->zv, n, "z"))) {
     free_quadtree(P);
     return rc;
   }
@@ -408,7 +421,7 @@ void free_quadtree(Problem& P) {
   QuadWs* w = P.qt;
   if (!w) return;
   void* ptrs[] = {w->gp, w->part, w->key, w->val, w->kt, w->vt, w->rhist, w->rtsum, w->code,
-                  w->xs, w->px, w->py, w->dtsum, w->base, w->itsum, w->nb, w->nc, w->zv};
+                  w->xs, w->px, w->py, w->dtsum, w->base, w->itsum, w->nodes, w->zv};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete w;
