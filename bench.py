@@ -109,7 +109,24 @@ def pmds_cpu_baseline(g, pivots: int, sample: int = 3):
                       f"extrapolated; the eigen-solve and projection are not counted"}
 
 
-def small_n_leg(api, ctx, iters: int):
+def small_n_oracle(g, iters: int = 20):
+    """The oracle's exact FP64 gradient + step on the 32 x 32 grid (P from k = 120),
+    timed over `iters` iterations on one host core."""
+    from oracle import affinities, gradient, step as ostep
+    from synth import graphs
+    P = affinities.build_P(g.indptr, g.indices, 40.0, seed=0)
+    X = graphs.initial_layout(g.n, 0).astype(np.float64)
+    U, Ga = np.zeros_like(X), np.ones_like(X)
+    t0 = time.perf_counter()
+    for it in range(iters):
+        G = gradient.grad_terms(X, P).G
+        X, U, Ga = ostep.step(X, U, Ga, G, it)
+    dt = time.perf_counter() - t0
+    return {"iters_per_s": iters / dt, "cores": 1, "kind": "oracle",
+            "sample": f"{iters} iterations of the exact FP64 gradient and step (n = {g.n}, k = 120)"}
+
+
+def small_n_leg(api, ctx, iters: int, cpu: bool = True):
     """The 32 x 32 grid (n = 1024): L-tsNET (P from k = 120) against the original
     tsNET's full P (k = n - 1), both from the same Pivot MDS start with the
     two-stage schedule, then the quality of each final layout (NP of every
@@ -148,6 +165,8 @@ def small_n_leg(api, ctx, iters: int):
             torch.cuda.synchronize()
             entry["direct_f64_grads_per_s"] = 20 / (time.perf_counter() - t0)
         res[name] = entry
+        if cpu and k == 120:
+            entry["cpu_oracle"] = small_n_oracle(g)
         log(f"small n, {name}: {entry['iters_per_s']:.0f} iters/s, NP {entry['np']:.4f}, "
             f"stress {entry['stress']:.4f} (best scale {entry['stress_best_scale']:.4f})")
         prob.free()
@@ -631,7 +650,8 @@ def main():
             "L-tsNET vs FIt-tsNET": iters_per_s / variants["FIt-tsNET"]["iters_per_s"],
             "FIt-tsNET vs BH-tsNET": variants["FIt-tsNET"]["iters_per_s"] / variants["BH-tsNET"]["iters_per_s"]}
 
-    small = small_n_leg(api, ctx, args.small_iters) if args.small_iters > 0 else None
+    small = small_n_leg(api, ctx, args.small_iters, cpu=not args.no_cpu_baseline) \
+        if args.small_iters > 0 else None
 
     out = {
         "metric": METRIC,
