@@ -1,6 +1,8 @@
 """Graph replay of (gradient, step): every replay equals the same iterations
 run eagerly, bit for bit (the kernels are deterministic), with eager work and
-synchronisations between the replays; both momentum phases are covered."""
+synchronisations between the replays; both momentum phases are covered, for
+L-tsNET and for the quadtree path of FIt-tsNET and BH-tsNET (its tree is
+rebuilt inside the graph on every replay)."""
 import numpy as np
 import pytest
 
@@ -12,13 +14,14 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def test_step_graph_replays_match_eager():
+@pytest.mark.parametrize("variant", ["L-tsNET", "FIt-tsNET", "BH-tsNET"])
+def test_step_graph_replays_match_eager(variant):
     from paper_2509_19785_amd import api
     ctx = api.Context(0)
     n = 20000
     rowptr, col, val = graphs.random_affinity(n, 30.0, 3, hub_rows=2, hub_len=5000)
     prob = api.Problem.from_host(ctx, rowptr, col, val.astype(np.float32))
-    prm = api.Params(max_intervals=128, attract_layout=2)
+    prm = api.Params.variant(variant, max_intervals=128, attract_layout=2)
     sp = api.StepParams(momentum_switch_iter=4)
     dev = torch.device("cuda", 0)
     X0 = torch.tensor(graphs.initial_layout(n, 3, std=1.0), device=dev)
@@ -45,7 +48,7 @@ def test_step_graph_replays_match_eager():
         it += k
         prob.grad(Xscratch, prm)               # unrelated eager work between replays
         torch.cuda.synchronize()
-        say(f"[graph] replay {rep}: max |dX| {float((Xg - Xe).abs().max()):.3e}")
+        say(f"[graph] {variant} replay {rep}: max |dX| {float((Xg - Xe).abs().max()):.3e}")
         assert torch.equal(Xg, Xe) and torch.equal(ug, ue) and torch.equal(kg, ke)
         assert torch.equal(Gg, Ge) and torch.equal(Zg, Ze)
     del g_early, g_late
