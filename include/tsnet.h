@@ -86,14 +86,16 @@ typedef struct tsnet_P_s*   tsnet_P;     /* one problem: graph batch, P, workspa
  *    interpolated is L-tsNET (Algorithm 3); interpolated repulsion with the
  *    quadtree entropy is FIt-tsNET (Algorithm 2); both by quadtree is
  *    BH-tsNET (Algorithm 1). The quadtree is rebuilt on every evaluation:
- *    per graph, the bounding square split into 2^16 cells per axis (cell of a
- *    coordinate = floor((x - x_min) 2^16 / side) in FP64), points ordered by
+ *    per graph, the bounding square split into 2^32 cells per axis (cell of a
+ *    coordinate = floor((x - x_min) 2^32 / side) in FP64), points ordered by
  *    the interleaved cell bits (y above x) and then by id, a node per
  *    non-empty 2-bit prefix below a node with two or more points, leaves at
- *    one point or level 16. For point i a node of width w is a summary of
+ *    one point or level 32. For point i a node of width w is a summary of
  *    its points (their count at their FP64 centre of mass c) when
  *    w^2 < theta^2 ||X_i - c||^2, tested in FP64; leaves are summed point by
- *    point; the terms are summed in FP32.
+ *    point; the terms are summed in FP32. The tree needs up to 33 n + 1
+ *    nodes of 32 bytes, allocated on first use: n at most 65,075,262
+ *    (TSNET_EINVAL beyond).
  *  theta: the opening threshold, in (0, 0.7] when a quadtree is used (then a
  *    node holding X_i is never a summary).
  */

@@ -10,12 +10,14 @@ below are this project's, shared with the GPU path. Per graph [a, b):
 
 1. Tree. x0, y0 = the smallest coordinates; side = max(x_max - x0, y_max - y0)
    in FP64 from the FP32 coordinates (1 if it is 0). Each point gets the cell
-   q = min(2^16 - 1, floor((x - x0) * 2^16 / side)) per axis, computed in
-   FP64 one operation at a time; its code interleaves the bits of qy and qx
-   (2 bits per level, y above x, level 1 first). Points are ordered by
+   q = min(2^32 - 1, floor((x - x0) * 2^32 / side)) per axis, computed in
+   FP64 one operation at a time; its 64-bit code interleaves the bits of qy
+   and qx (2 bits per level, y above x, level 1 first). Points are ordered by
    (code, id). The root holds all points at level 0; a node with more than
-   one point below level 16 has one child per non-empty next 2-bit digit, in
-   digit order. Nodes with one point, or at level 16, are leaves. A node of
+   one point below level 32 has one child per non-empty next 2-bit digit, in
+   digit order. Nodes with one point, or at level 32, are leaves. (32 levels
+   keep leaves small when a few far points stretch the square: then the bulk
+   of the layout covers a tiny corner of it.) A node of
    level l has width w = side / 2^l, and its centre of mass is the FP64 mean
    of its points.
 2. Traversal for point i, depth first from the root in child order: a leaf
@@ -36,7 +38,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-LEVELS = 16
+LEVELS = 32
 THETA_MAX = 0.7
 
 
@@ -56,13 +58,14 @@ def _codes(X64: np.ndarray):
     if not side > 0:
         side = 1.0
     scale = float(1 << LEVELS) / side
-    lim = (1 << LEVELS) - 1
-    qx = np.minimum(np.floor((X64[:, 0] - x0) * scale), lim).astype(np.int64)
-    qy = np.minimum(np.floor((X64[:, 1] - y0) * scale), lim).astype(np.int64)
-    code = np.zeros(len(X64), dtype=np.int64)
+    lim = float((1 << LEVELS) - 1)
+    qx = np.minimum(np.floor((X64[:, 0] - x0) * scale), lim).astype(np.uint64)
+    qy = np.minimum(np.floor((X64[:, 1] - y0) * scale), lim).astype(np.uint64)
+    code = np.zeros(len(X64), dtype=np.uint64)
+    one = np.uint64(1)
     for b in range(LEVELS):        # bit b of each axis -> digit LEVELS-1-b of the code
-        code |= ((qy >> b) & 1) << (2 * b + 1)
-        code |= ((qx >> b) & 1) << (2 * b)
+        code |= ((qy >> np.uint64(b)) & one) << np.uint64(2 * b + 1)
+        code |= ((qx >> np.uint64(b)) & one) << np.uint64(2 * b)
     return code, side
 
 
@@ -78,7 +81,7 @@ def build(X) -> tuple:
         node = Node(level, s, e - s, float(pts[s:e, 0].mean()), float(pts[s:e, 1].mean()), [])
         if e - s > 1 and level < LEVELS:
             shift = 2 * (LEVELS - level - 1)
-            digits = (sc[s:e] >> shift) & 3
+            digits = (sc[s:e] >> np.uint64(shift)) & np.uint64(3)
             for d in range(4):
                 idx = np.nonzero(digits == d)[0]
                 if idx.size:

@@ -4,16 +4,20 @@
 // the tree nor the opening test; the readings are the project's:
 //
 //  * Per graph, the bounding square (side = the larger extent, in FP64) is
-//    cut into 2^16 cells per axis; a point's cell is floor((x - x_min) *
-//    2^16 / side) in FP64. Its code interleaves the cell bits, y above x, so
-//    the 2-bit digit of level l is the l-th quadrant choice from the root.
-//    Points are sorted by (graph, code, id) with two stable radix sorts.
+//    cut into 2^32 cells per axis; a point's cell is floor((x - x_min) *
+//    2^32 / side) in FP64. Its 64-bit code interleaves the cell bits, y above
+//    x, so the 2-bit digit of level l is the l-th quadrant choice from the
+//    root. 32 levels keep the leaves small when a few far points stretch the
+//    square (the bulk of the layout then covers a tiny corner of it; with 16
+//    levels whole clusters shared a leaf and were summed pair by pair).
+//    Points are sorted by (graph, code, id) with stable radix sorts: the low
+//    code word, the high code word, then the graph.
 //  * The tree is the linear quadtree of the sorted codes: a node per
 //    non-empty prefix of l digits whose parent holds two or more points;
-//    leaves hold one point or sit at level 16. Sorted position p starts the
+//    leaves hold one point or sit at level 32. Sorted position p starts the
 //    nodes of levels lmin(p)..lmax(p): lmin is one past the digits p shares
 //    with p - 1 (0 at the graph's first point), lmax is one past the digits
-//    it shares with p + 1 (at most 16, at least lmin). Numbering nodes by
+//    it shares with p + 1 (at most 32, at least lmin). Numbering nodes by
 //    (start, level) is a depth-first order, so a node's first child is the
 //    next node and the node after its subtree is the first node starting at
 //    its end: the traversal needs no stack.
@@ -58,7 +62,7 @@ struct QuadWs {
   float4* part = nullptr;    // [num_chunks] bounding-box partials
   unsigned *key = nullptr, *val = nullptr, *kt = nullptr, *vt = nullptr;  // [n] sort
   int *rhist = nullptr, *rtsum = nullptr;
-  unsigned* code = nullptr;  // [n] codes in sorted order
+  unsigned long long* code = nullptr;  // [n] codes in sorted order
   float2* xs = nullptr;      // [n] X in sorted order
   double *px = nullptr, *py = nullptr;  // [n + 1] sorted X in FP64, then exclusive prefix sums
   double* dtsum = nullptr;
@@ -70,8 +74,8 @@ struct QuadWs {
 
 namespace {
 
-constexpr int kQtLevels = 16;
-constexpr double kQtCells = 65536.0;
+constexpr int kQtLevels = 32;
+constexpr double kQtCells = 4294967296.0;
 
 __device__ __forceinline__ unsigned qt_coord(float x, double x0, double scale) {
 #pragma clang fp contract(off)
@@ -79,21 +83,24 @@ __device__ __forceinline__ unsigned qt_coord(float x, double x0, double scale) {
   return u >= 0.0 ? (u < kQtCells - 1.0 ? (unsigned)floor(u) : (unsigned)(kQtCells - 1.0)) : 0u;
 }
 
-__device__ __forceinline__ unsigned qt_spread(unsigned v) {  // bit b -> bit 2b
-  v &= 0xFFFFu;
-  v = (v | (v << 8)) & 0x00FF00FFu;
-  v = (v | (v << 4)) & 0x0F0F0F0Fu;
-  v = (v | (v << 2)) & 0x33333333u;
-  v = (v | (v << 1)) & 0x55555555u;
+__device__ __forceinline__ unsigned long long qt_spread(unsigned u) {  // bit b -> bit 2b
+  unsigned long long v = u;
+  v = (v | (v << 16)) & 0x0000FFFF0000FFFFull;
+  v = (v | (v << 8)) & 0x00FF00FF00FF00FFull;
+  v = (v | (v << 4)) & 0x0F0F0F0F0F0F0F0Full;
+  v = (v | (v << 2)) & 0x3333333333333333ull;
+  v = (v | (v << 1)) & 0x5555555555555555ull;
   return v;
 }
 
-__device__ __forceinline__ unsigned qt_code(float2 x, const QtParam& p) {
+__device__ __forceinline__ unsigned long long qt_code(float2 x, const QtParam& p) {
   return (qt_spread(qt_coord(x.y, p.y0, p.scale)) << 1) | qt_spread(qt_coord(x.x, p.x0, p.scale));
 }
 
 // digits shared by two different codes
-__device__ __forceinline__ int qt_cpl(unsigned a, unsigned b) { return __clz(a ^ b) >> 1; }
+__device__ __forceinline__ int qt_cpl(unsigned long long a, unsigned long long b) {
+  return __clzll(a ^ b) >> 1;
+}
 
 struct QtDev {
   const float2* X;
@@ -181,10 +188,19 @@ __global__ __launch_bounds__(256) void k_qt_plan(QtDev a, const GraphInfo* gi) {
   }
 }
 
+// sort keys, first pass: the low code word of each vertex
 __global__ __launch_bounds__(256) void k_qt_codes(QtDev a) {
   for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += gridDim.x * blockDim.x) {
-    a.w.key[v] = qt_code(a.X[v], a.w.gp[qt_graph(a, v)]);
+    a.w.key[v] = (unsigned)qt_code(a.X[v], a.w.gp[qt_graph(a, v)]);
     a.w.val[v] = (unsigned)v;
+  }
+}
+
+// second pass: the high code word of the vertex at each position
+__global__ __launch_bounds__(256) void k_qt_high_keys(QtDev a) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < a.n; p += gridDim.x * blockDim.x) {
+    const int v = (int)a.w.val[p];
+    a.w.key[p] = (unsigned)(qt_code(a.X[v], a.w.gp[qt_graph(a, v)]) >> 32);
   }
 }
 
@@ -207,16 +223,16 @@ __global__ __launch_bounds__(256) void k_qt_sorted(QtDev a) {
 }
 
 __device__ __forceinline__ void qt_levels(const QtDev& a, int p, int gs, int ge, int& lmin, int& lmax) {
-  const unsigned c = a.w.code[p];
+  const unsigned long long c = a.w.code[p];
   if (p == gs) {
     lmin = 0;
   } else {
-    const unsigned cp = a.w.code[p - 1];
+    const unsigned long long cp = a.w.code[p - 1];
     lmin = cp == c ? -1 : qt_cpl(cp, c) + 1;
   }
   int nxt = -1;
   if (p + 1 < ge) {
-    const unsigned cn = a.w.code[p + 1];
+    const unsigned long long cn = a.w.code[p + 1];
     nxt = cn == c ? kQtLevels : qt_cpl(c, cn);
   }
   lmax = min(kQtLevels, max(lmin, nxt + 1));
@@ -231,8 +247,8 @@ __global__ __launch_bounds__(256) void k_qt_count(QtDev a) {
   }
 }
 
-// The nodes starting at position p: end of each prefix run by binary search
-// over the sorted codes, skip = first node at or after that end.
+// The nodes starting at position p: end of each prefix run by a galloping
+// search over the sorted codes, skip = first node at or after that end.
 __global__ __launch_bounds__(256) void k_qt_nodes(QtDev a) {
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < a.n; p += gridDim.x * blockDim.x) {
     const int g = qt_graph(a, p);
@@ -240,7 +256,7 @@ __global__ __launch_bounds__(256) void k_qt_nodes(QtDev a) {
     int lmin, lmax;
     qt_levels(a, p, gs, ge, lmin, lmax);
     if (lmin < 0) continue;
-    const unsigned c = a.w.code[p];
+    const unsigned long long c = a.w.code[p];
     const int b0 = a.w.base[p];
     const double sx = a.w.px[p], sy = a.w.py[p];
     int lo_hint = p + 1;
@@ -250,8 +266,16 @@ __global__ __launch_bounds__(256) void k_qt_nodes(QtDev a) {
         e = ge;
       } else {
         const int sh = 2 * (kQtLevels - l);
-        const unsigned last = sh >= 32 ? 0xFFFFFFFFu : (c | ((1u << sh) - 1u));
-        int lo = lo_hint, hi = ge;  // first q in [lo, ge) with code[q] > last
+        const unsigned long long last = sh >= 64 ? ~0ull : (c | ((1ull << sh) - 1ull));
+        // first q >= lo_hint with code[q] > last (ge if none): gallop from
+        // lo_hint (most nodes are small), then bisect the last stride
+        int lo = lo_hint, hi = lo_hint, stride = 1;
+        while (hi < ge && a.w.code[hi] <= last) {
+          lo = hi + 1;
+          hi = lo + stride;
+          stride <<= 1;
+        }
+        hi = min(hi, ge);
         while (lo < hi) {
           const int m = (lo + hi) >> 1;
           if (a.w.code[m] > last) hi = m; else lo = m + 1;
@@ -387,6 +411,9 @@ int qt_alloc(T** p, size_t count, const char* what) {
 
 int ensure_quadtree(Problem& P) {
   if (P.qt) return TSNET_OK;
+  // each sorted position starts at most kQtLevels + 1 nodes; node indices are int
+  if ((int64_t)(kQtLevels + 1) * P.n + 1 > INT_MAX)
+    return fail(TSNET_EINVAL, "quadtree terms need n <= " + std::to_string((INT_MAX - 1) / (kQtLevels + 1)));
   QuadWs* w = new (std::nothrow) QuadWs;
   if (!w) return fail(TSNET_ENOMEM, "host allocation failed");
   P.qt = w;
@@ -451,6 +478,9 @@ int run_quadtree(Problem& P, const float2* X, double theta, float eps, int terms
   QT_LAUNCH(hipLaunchKernelGGL(k_qt_plan, dim3(P.G), dim3(256), 0, s, a, P.ginfo));
   QT_LAUNCH(hipLaunchKernelGGL(k_qt_codes, dim3(vb), dim3(256), 0, s, a));
   hipError_t e = radix_sort(a.w.key, a.w.val, a.w.kt, a.w.vt, n, 32, a.w.rhist, a.w.rtsum, s);
+  if (e != hipSuccess) return fail(TSNET_EHIP, std::string("quadtree sort: ") + hipGetErrorString(e));
+  QT_LAUNCH(hipLaunchKernelGGL(k_qt_high_keys, dim3(vb), dim3(256), 0, s, a));
+  e = radix_sort(a.w.key, a.w.val, a.w.kt, a.w.vt, n, 32, a.w.rhist, a.w.rtsum, s);
   if (e != hipSuccess) return fail(TSNET_EHIP, std::string("quadtree sort: ") + hipGetErrorString(e));
   if (P.G > 1) {
     QT_LAUNCH(hipLaunchKernelGGL(k_qt_graph_keys, dim3(vb), dim3(256), 0, s, a));

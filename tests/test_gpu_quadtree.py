@@ -9,8 +9,8 @@ where it is tied to rounding). With theta = 1e-4 no inner node is a summary
 and the sums are the exact all-pairs sums. The gradient assembles those terms
 with the exact sparse attraction; FIt-tsNET keeps the interpolated repulsion
 bit for bit. Layouts: normal, clustered, rounded (many equal codes), a line,
-coincident points, a batch with a one-vertex graph, and BA n = 1e6 on sampled
-vertices.
+coincident points, a bulk stretched by four far points (leaves below level
+16), a batch with a one-vertex graph, and BA n = 1e6 on sampled vertices.
 """
 import numpy as np
 import pytest
@@ -63,6 +63,8 @@ def _layouts(n, seed):
         "rounded": np.round(rng.normal(size=(n, 2)) * 3) / 3,
         "line": np.stack([np.linspace(-20, 20, n), np.zeros(n)], 1),
         "coincident": np.zeros((n, 2)),
+        # four points 1e4 away: the bulk covers about 1e-4 of the square's side
+        "stretched": np.vstack([[[1e4, 0], [-1e4, 0], [0, 1e4], [0, -1e4]], rng.normal(size=(n - 4, 2))]),
     }
 
 

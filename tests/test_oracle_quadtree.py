@@ -4,8 +4,9 @@
   one: the sums equal the exact all-pairs sums of ``gradient.pair_sums`` and a
   direct sum of ln(eps + r^2).
 * Tree invariants: children partition their parent's range in code order,
-  counts add up, leaves hold one point or sit at level 16, centres of mass
-  are means.
+  counts add up, leaves hold one point or sit at the deepest level (32),
+  centres of mass are means; a layout whose bulk covers a tiny corner of the
+  square (a few far points) still gets a leaf per distinct point.
 * A single point facing a far cluster sees the cluster as one summary at its
   centre of mass (closed form).
 * The error against the exact sums shrinks with theta; coincident points;
@@ -60,8 +61,31 @@ def test_tree_invariants():
             assert nd.count == 1 or nd.level == quadtree.LEVELS
     leaves = [nd for nd in nodes if not nd.children]
     assert sum(nd.count for nd in leaves) == len(X)
-    # the two coincident points share a leaf at level 16
+    # the two coincident points share a leaf at the deepest level
     assert any(nd.count == 2 and nd.level == quadtree.LEVELS for nd in leaves)
+
+
+def test_stretched_square_keeps_points_apart():
+    # 2000 points of spread 1 and four points 1e4 away: the bulk covers about
+    # 1e-4 of the square's side, finer than 2^-16 of it, so the leaves lie
+    # below level 16; every leaf still holds one point, except the one pair of
+    # coincident points
+    rng = np.random.default_rng(5)
+    X = rng.normal(size=(2000, 2)).astype(np.float32)
+    X[:4] = np.array([[1e4, 0], [-1e4, 0], [0, 1e4], [0, -1e4]], np.float32)
+    X[10] = X[11]
+    root, order, codes, side = quadtree.build(X)
+    leaves = [nd for nd in _walk(root, []) if not nd.children]
+    assert sum(nd.count for nd in leaves) == len(X)
+    shared = [nd for nd in leaves if nd.count > 1]
+    assert len(shared) == 1 and shared[0].count == 2 and shared[0].level == quadtree.LEVELS
+    assert max(nd.level for nd in leaves if nd.count == 1) > 16
+    # theta near 0: the exact all-pairs sums, also at this depth
+    zi, frep, fent, _ = quadtree.sums(X, theta=1e-6, eps=0.05)
+    ez, er, ee = gradient.pair_sums(X.astype(np.float64), 0.05)
+    assert np.allclose(zi, ez, rtol=1e-12, atol=0)
+    assert np.allclose(frep, er, rtol=1e-9, atol=1e-15)
+    assert np.allclose(fent, ee, rtol=1e-9, atol=1e-15)
 
 
 def test_far_cluster_is_one_summary():
