@@ -172,6 +172,38 @@ def test_batch_of_graphs(api, ctx):
         assert rel_l2(got["G"][a0:a1], ex.G[a0:a1]) <= 1e-3
 
 
+def test_batch_of_twelve_graphs(api, ctx):
+    # 8 or more graphs: each graph's FFT stages get 32 blocks, so the column
+    # stage packs several columns per block (6 at M = 384), fewer than the
+    # buffer holds; every graph against the oracle's interpolated sums
+    parts = []
+    for i in range(12):
+        if i % 3 == 0:
+            parts.append(graphs.grid(6 + i, 9))
+        elif i % 3 == 1:
+            parts.append(graphs.random_recursive_tree(150 + 37 * i, 20 + i))
+        else:
+            parts.append(graphs.sbm([60 + 5 * i, 90], 0.08, 0.01, 30 + i))
+    b = graphs.concat_graphs(parts)
+    P = affinities.build_P(b.indptr, b.indices, 10.0, seed=2, graph_offsets=b.graph_offsets)
+    prob = _upload(api, ctx, P, b.graph_offsets)
+    n = b.indptr.shape[0] - 1
+    X = graphs.initial_layout(n, 8, std=1.5)
+    say(f"[grad parity] batch G=12 n={n}")
+    got = _terms(api, prob, X)
+    X64 = X.astype(np.float64)
+    ex = gradient.grad_terms(X64, P, CostParams(), b.graph_offsets)
+    gi = prob.grid_info()
+    for gidx in range(12):
+        a0, a1 = int(b.graph_offsets[gidx]), int(b.graph_offsets[gidx + 1])
+        it = interp.interp_terms(X64[a0:a1], 0.05)
+        assert int(gi["n_intervals"][gidx]) == it.grid.n_int
+        assert rel_l2(got["F_rep"][a0:a1], it.F_rep) <= 2e-5, gidx
+        assert rel_l2(got["F_ent"][a0:a1], it.F_ent) <= 2e-5, gidx
+        assert abs(got["Z"][gidx] - ex.Z[gidx]) <= 1e-4 * ex.Z[gidx]
+        assert rel_l2(got["G"][a0:a1], ex.G[a0:a1]) <= 1e-3
+
+
 def test_tiny_graphs(api, ctx):
     # n = 1: no pairs, G = (lambda_c / n) X; n = 2 and 3 in one batch with it
     parts = [graphs.csr_from_edges(1, np.zeros(0, np.int64), np.zeros(0, np.int64)),
