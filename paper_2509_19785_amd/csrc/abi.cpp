@@ -212,7 +212,13 @@ static int init_problem(Ctx& c, Problem& P, int n, const int32_t* goff_host, int
   P.num_chunks = (int)cg.size();
   const int nc = P.num_chunks;
   const size_t tiles = ((size_t)n + kBinTileH - 1) / kBinTileH;
-  const size_t ranges = ((size_t)n + kSpreadRange - 1) / kSpreadRange;
+  // sorted points per wave of the spread: kSpreadRange, halved (down to 64)
+  // while the problem has fewer than 256 ranges, so a small problem's spread
+  // still runs on many waves
+  int sr = kSpreadRange;
+  while (sr > 64 && ((size_t)n + sr - 1) / sr < 256) sr >>= 1;
+  P.spread_range = sr;
+  const size_t ranges = ((size_t)n + sr - 1) / sr;
   if ((rc = dmalloc(&P.ginfo, G, "ginfo")) || (rc = dmalloc(&P.goff_d, G + 1, "goff")) ||
       (rc = dmalloc(&P.chunk_graph, nc, "chunks")) || (rc = dmalloc(&P.chunk_start, nc, "chunks")) ||
       (rc = dmalloc(&P.chunk_end, nc, "chunks")) || (rc = dmalloc(&P.desc, G, "desc")) ||

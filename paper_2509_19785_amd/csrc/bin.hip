@@ -314,7 +314,8 @@ __device__ __forceinline__ void emit(const int* __restrict__ box_off, const BoxA
   }
 }
 
-// Phase 1: one wave per range of kRange sorted points. The range splits into
+// Phase 1: one wave per range of `range` sorted points (a power of two, 64 to
+// kRange, chosen per problem). The range splits into
 // segments of equal box id (start positions collected in LDS). A lane sums a
 // short segment by itself; a long one is summed by the whole wave (lanes
 // stride over its points, then a DPP reduction). Every sum runs in a fixed
@@ -322,16 +323,16 @@ __device__ __forceinline__ void emit(const int* __restrict__ box_off, const BoxA
 __global__ __launch_bounds__(kRangeWaves * kWave) void k_spread_ranges(
     const float2* __restrict__ Xs, const int* __restrict__ skeys, int n,
     const int* __restrict__ box_off, const GridDesc* __restrict__ desc, int G, float* charges,
-    size_t stride, int* head_box, int* tail_box, float* head_val, float* tail_val) {
+    size_t stride, int* head_box, int* tail_box, float* head_val, float* tail_val, int range) {
   __shared__ int seg_all[kRangeWaves][kRange + 1];
   int* seg = seg_all[wave_id()];
   const int lane = lane_id();
   const u64 below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
-  const int nranges = (n + kRange - 1) / kRange;
+  const int nranges = (n + range - 1) / range;
   const int nw = gridDim.x * kRangeWaves;
   for (int r = blockIdx.x * kRangeWaves + wave_id(); r < nranges; r += nw) {
-    const int p0 = r * kRange;
-    const int p1 = p0 + kRange < n ? p0 + kRange : n;
+    const int p0 = r * range;
+    const int p1 = p0 + range < n ? p0 + range : n;
     // the range's keys, all loads in flight together; the key before a
     // point comes from the neighbouring lane
     constexpr int kSteps = kRange / kWave;
@@ -411,9 +412,9 @@ __device__ __forceinline__ void spread_dense_box(int b, const int* __restrict__ 
                                                  float* charges, size_t stride,
                                                  const int* __restrict__ head_box,
                                                  const float* __restrict__ head_val,
-                                                 const float* __restrict__ tail_val) {
+                                                 const float* __restrict__ tail_val, int range) {
   const int lane = lane_id();
-  const int r0 = box_off[b] / kRange, r1 = (box_off[b + 1] - 1) / kRange;
+  const int r0 = box_off[b] / range, r1 = (box_off[b + 1] - 1) / range;
   double acc[kVals];
 #pragma unroll
   for (int q = 0; q < kVals; ++q) acc[q] = 0.0;
@@ -435,7 +436,7 @@ __global__ __launch_bounds__(256) void k_spread_boxes(
     const int* __restrict__ box_off, const int* __restrict__ btotal,
     const GridDesc* __restrict__ desc, int G, float* charges, size_t stride,
     const int* __restrict__ head_box, const float* __restrict__ head_val,
-    const float* __restrict__ tail_val) {
+    const float* __restrict__ tail_val, int range) {
   const int B = *btotal;
   const int lane = lane_id();
   const int nwaves = gridDim.x * (blockDim.x / kWave);
@@ -447,8 +448,8 @@ __global__ __launch_bounds__(256) void k_spread_boxes(
       bs = box_off[b];
       be = box_off[b + 1];
       if (be > bs) {
-        r0 = bs / kRange;
-        r1 = (be - 1) / kRange;
+        r0 = bs / range;
+        r1 = (be - 1) / range;
       }
     }
     const bool mine = b < B && be > bs && r0 != r1;  // holds points, not written whole by phase 1
@@ -474,30 +475,31 @@ __global__ __launch_bounds__(256) void k_spread_boxes(
     bool dense = false;
     if (bl < B) {
       const int bs = box_off[bl], be = box_off[bl + 1];
-      dense = be > bs && (be - 1) / kRange - bs / kRange >= kDenseRanges;
+      dense = be > bs && (be - 1) / range - bs / range >= kDenseRanges;
     }
     u64 todo = __ballot(dense);
     while (todo) {
       const int src_lane = __ffsll((long long)todo) - 1;
       todo &= todo - 1;
       const int b = base + src_lane * nwaves;
-      spread_dense_box(b, box_off, desc, G, charges, stride, head_box, head_val, tail_val);
+      spread_dense_box(b, box_off, desc, G, charges, stride, head_box, head_val, tail_val, range);
     }
   }
 }
 
 hipError_t launch_spread(Problem& P, const float2* X, hipStream_t s) {
   (void)X;
-  const int nranges = (P.n + kRange - 1) / kRange;
+  const int nranges = (P.n + P.spread_range - 1) / P.spread_range;
   int blocks = (nranges + kRangeWaves - 1) / kRangeWaves;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_spread_ranges, dim3(blocks), dim3(kRangeWaves * kWave), 0, s, P.xs, P.skeys,
                      P.n, P.box_off, P.desc, P.G, P.charges, P.stride_charges, P.head_box,
-                     P.tail_box, P.head_val, P.tail_val);
+                     P.tail_box, P.head_val, P.tail_val, P.spread_range);
   int bblocks = (P.G * P.cap * P.cap + 255) / 256;
   if (bblocks > 8192) bblocks = 8192;
   hipLaunchKernelGGL(k_spread_boxes, dim3(bblocks), dim3(256), 0, s, P.box_off, P.btotal, P.desc,
-                     P.G, P.charges, P.stride_charges, P.head_box, P.head_val, P.tail_val);
+                     P.G, P.charges, P.stride_charges, P.head_box, P.head_val, P.tail_val,
+                     P.spread_range);
   return hipGetLastError();
 }
 

@@ -18,7 +18,7 @@ constexpr int kMaxNg = kNodes * kMaxIntervals;
 constexpr int kMaxM = 2 * kMaxNg;         // FFT length per axis (3 * 2^b)
 constexpr int kPotCh = 8;                 // potential channels per node (4 planes of pairs)
 constexpr int kCostTerms = 4;             // chunk sums of the cost reduction
-constexpr int kSpreadRange = 1024;        // sorted points per wave in the spread
+constexpr int kSpreadRange = 1024;        // sorted points per wave in the spread (at most)
 constexpr int kChunk = 2048;              // vertices per chunk of per-vertex kernels
 constexpr int kMaxK = 1024;               // neighbours per vertex in tsnet_build_P
 constexpr double kSpanFloor = 1e-4;       // smallest grid span (degenerate layouts)
@@ -145,6 +145,7 @@ struct Problem {
   float2* ospec = nullptr;            // per graph [8][ng][M/2+1] the same, transposed
   float* pot = nullptr;               // per graph 4 planes (channel pairs) of ng^2 float2
   size_t stride_charges = 0, stride_qspec = 0, stride_kspec = 0, stride_ospec = 0, stride_pot = 0;
+  int spread_range = kSpreadRange;    // sorted points per wave of the spread (64 .. kSpreadRange)
   int* head_box = nullptr;            // [spread ranges] box of the leading partial, -1 if none
   int* tail_box = nullptr;            // [spread ranges] box of the trailing partial, -1 if none
   float* head_val = nullptr;          // [spread ranges][27]
