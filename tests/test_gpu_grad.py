@@ -204,6 +204,27 @@ def test_batch_of_twelve_graphs(api, ctx):
         assert rel_l2(got["G"][a0:a1], ex.G[a0:a1]) <= 1e-3
 
 
+@pytest.mark.parametrize("n", [40000, 100000, 200000])
+def test_mid_size_interpolated_terms(api, ctx, n):
+    # sizes whose spread ranges are 128, 256 and 512 sorted points (smaller
+    # problems take 64, from 261,121 vertices on 1024); 30% of the points in a
+    # tight cluster, so dense boxes span many ranges: every vertex's
+    # interpolated sums against the oracle's
+    rowptr, col, val = graphs.random_affinity(n, 4.0, 50)
+    prob = api.Problem.from_host(ctx, rowptr, col, val.astype(np.float32))
+    rng = np.random.default_rng(n)
+    X = (rng.normal(size=(n, 2)) * np.where(rng.random((n, 1)) < 0.3, 0.2, 3.0)).astype(np.float32)
+    prm = api.Params(max_intervals=128)
+    got = _terms(api, prob, X, prm)
+    it = interp.interp_terms(X.astype(np.float64), prm.eps_r, prm.interval_width, prm.min_intervals,
+                             prm.max_intervals)
+    errs = {k: rel_l2(got[k], getattr(it, k)) for k in ("F_rep", "F_ent", "Z_i")}
+    say(f"[grad parity] n={n}: " + " ".join(f"{k} {v:.2e}" for k, v in errs.items()) +
+        f" n_int {it.grid.n_int}")
+    assert max(errs.values()) <= _interp_tol(X)
+    assert int(prob.grid_info()["n_intervals"][0]) == it.grid.n_int
+
+
 def test_tiny_graphs(api, ctx):
     # n = 1: no pairs, G = (lambda_c / n) X; n = 2 and 3 in one batch with it
     parts = [graphs.csr_from_edges(1, np.zeros(0, np.int64), np.zeros(0, np.int64)),
