@@ -71,6 +71,20 @@ typedef struct tsnet_P_s*   tsnet_P;     /* one problem: graph batch, P, workspa
  *  interval_width: target box side h of the interpolation grid; the box count
  *    per axis is ceil(span / h) clamped to [min_intervals, max_intervals] and
  *    rounded up to a power of two (the paper leaves I and P open, Sec. 2.3).
+ *    span is the larger side of the region the grid covers: the bounding box
+ *    of the graph's layout, or its core when far points are set apart.
+ *  far_trim: t of the far-point rule (Sec. 2.3 leaves the covered region
+ *    open), 0 to switch it off, at most 1024, default 64. Per graph with
+ *    t' = min(far_trim, n / 64) >= 1: each axis is cut into 2048 equal bins
+ *    over the bounding box (bin = floor((v - v_min) * 2048 / width) in FP64,
+ *    the last bin closed); lo / hi are the bins of the (t'+1)-th smallest /
+ *    largest coordinate. When the region of the bins [lo, hi] on both axes
+ *    has a larger side of at most half the bounding box's, the grid covers
+ *    that region and the points outside it (at most 4 t') are far points:
+ *    between a far point and a core point the kernel is interpolated in the
+ *    core point's argument only (the far point adds its charges at the nodes
+ *    before the gather; its own sums run over the node charges), far points
+ *    meet each other exactly. Otherwise the grid covers the bounding box.
  *  min_intervals >= 1, max_intervals a power of two in [min_intervals, 512].
  *  The evaluation workspace is sized for max_intervals boxes per axis in
  *  every graph of the problem (about 600 MB per graph at 512, 9.5 MB at 64),
@@ -112,6 +126,8 @@ typedef struct {
   int32_t repulsion;
   int32_t entropy;
   double  theta;
+  int32_t far_trim;
+  int32_t reserved;
 } tsnet_params;
 
 /*
@@ -379,9 +395,10 @@ int tsnet_grad_direct_f64(tsnet_ctx ctx, tsnet_P P, const double* X, const tsnet
 /*
  * Grid of the most recent tsnet_grad / tsnet_cost on P, per graph (host
  * arrays [num_graphs], any may be NULL): intervals per axis, box side,
- * lower-left corner. Synchronous.
+ * lower-left corner, number of far points set apart (far_trim). Synchronous.
  */
-int tsnet_grid_info(tsnet_P P, int32_t* n_intervals, float* box_side, float* x0, float* y0);
+int tsnet_grid_info(tsnet_P P, int32_t* n_intervals, float* box_side, float* x0, float* y0,
+                    int32_t* far_points);
 
 /* Synchronous: OR of the TSNET_STATUS_* bits raised since the last call; clears them. */
 int tsnet_status(tsnet_ctx ctx, uint32_t* flags_host);

@@ -45,6 +45,7 @@ class tsnet_params(ctypes.Structure):
         ("max_intervals", ctypes.c_int32), ("nodes_per_interval", ctypes.c_int32),
         ("attract_layout", ctypes.c_int32), ("repulsion", ctypes.c_int32),
         ("entropy", ctypes.c_int32), ("theta", ctypes.c_double),
+        ("far_trim", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -114,7 +115,7 @@ _SIGS = {
     "tsnet_cost": (_i32, [_vp, _vp, _vp, _P(tsnet_params), _vp, _vp]),
     "tsnet_grad_direct_f64": (_i32, [_vp, _vp, _vp, _P(tsnet_params), _vp, _vp, _vp, _i32, _vp,
                                      _vp]),
-    "tsnet_grid_info": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "tsnet_grid_info": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "tsnet_status": (_i32, [_vp, _P(ctypes.c_uint32)]),
     "tsnet_set_timing": (_i32, [_vp, ctypes.c_uint32]),
     "tsnet_stage_count": (_i32, []),

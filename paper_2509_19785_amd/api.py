@@ -31,6 +31,7 @@ class Params:
     repulsion: int = 0        # 0 interpolation, 1 quadtree (Barnes-Hut)
     entropy: int = 0          # 0 interpolation, 1 quadtree (Eq. 7)
     theta: float = 0.5        # quadtree opening threshold, (0, 0.7]
+    far_trim: int = 64        # t of the far-point rule of the grid (0: the grid covers the bounding box)
 
     @classmethod
     def variant(cls, name: str, **kw) -> "Params":
@@ -44,6 +45,7 @@ class Params:
         p = _lib.tsnet_params()
         for f in fields(self):
             setattr(p, f.name, getattr(self, f.name))
+        p.reserved = 0
         return p
 
 
@@ -224,9 +226,10 @@ class Problem:
         h = np.zeros(G, np.float32)
         x0 = np.zeros(G, np.float32)
         y0 = np.zeros(G, np.float32)
+        far = np.zeros(G, np.int32)
         check(lib.tsnet_grid_info(self.handle, ni.ctypes.data, h.ctypes.data, x0.ctypes.data,
-                                  y0.ctypes.data))
-        return {"n_intervals": ni, "box_side": h, "x0": x0, "y0": y0}
+                                  y0.ctypes.data, far.ctypes.data))
+        return {"n_intervals": ni, "box_side": h, "x0": x0, "y0": y0, "far_points": far}
 
     # ------------------------------------------------------------ evaluation
     def grad(self, X: torch.Tensor, params: Params = Params(), G=None, Z=None, stream=None):

@@ -33,7 +33,7 @@ int fail(int code, const std::string& msg) {
 static const char* kStageNames[ST_COUNT] = {"bbox_plan", "bin_sort", "spread", "fft_conv",
                                              "gather", "z_reduce", "attract_assemble", "step",
                                              "cost", "direct_f64", "build_P", "pmds",
-                                             "np", "stress", "quadtree"};
+                                             "np", "stress", "quadtree", "far_points"};
 
 template <typename T>
 static int dmalloc(T** p, size_t count, const char* what) {
@@ -104,6 +104,7 @@ static int collect_times(Ctx& c) {
 // ---------------------------------------------------------------- problems
 static void free_grid(Problem& P) {
   dfree(P.box_off);
+  dfree(P.trim_hist);
   dfree(P.charges);
   dfree(P.qspec);
   dfree(P.qspec_t);
@@ -160,6 +161,8 @@ static void free_problem(Problem& P) {
   dfree(P.rep_ent);
   dfree(P.zi);
   dfree(P.lnv);
+  dfree(P.slot_z);
+  dfree(P.slot_ln);
   dfree(P.zpart);
   dfree(P.zg);
   dfree(P.cost_part);
@@ -234,7 +237,8 @@ static int init_problem(Ctx& c, Problem& P, int n, const int32_t* goff_host, int
       (rc = dmalloc(&P.tail_val, ranges * 27, "ranges")) ||
       (rc = dmalloc(&P.perm, n, "perm")) || (rc = dmalloc(&P.rep_ent, n, "rep_ent")) ||
       (rc = dmalloc(&P.zi, n, "zi")) ||
-      (rc = dmalloc(&P.lnv, n, "lnv")) || (rc = dmalloc(&P.zpart, nc, "zpart")) ||
+      (rc = dmalloc(&P.lnv, n, "lnv")) || (rc = dmalloc(&P.slot_z, n, "slot_z")) ||
+      (rc = dmalloc(&P.slot_ln, n, "slot_ln")) || (rc = dmalloc(&P.zpart, nc, "zpart")) ||
       (rc = dmalloc(&P.zg, G, "zg")) || (rc = dmalloc(&P.cost_part, (size_t)nc * kCostTerms, "cost")))
     return rc;
   TSNET_HIP(hipMemcpy(P.ginfo, P.ginfo_h.data(), sizeof(GraphInfo) * G, hipMemcpyHostToDevice));
@@ -258,10 +262,12 @@ static int ensure_grid(Problem& P, int cap) {
   P.stride_kspec = 4 * Mh * Mh;
   P.stride_ospec = 8 * ng * Mh;
   P.stride_pot = ng * ng * kPotCh;
-  const size_t boxes = (size_t)P.G * cap * cap;
+  // every graph: cap^2 core boxes at most, then its far box
+  const size_t boxes = (size_t)P.G * ((size_t)cap * cap + 1);
   if (boxes >= (size_t)1 << 30) return fail(TSNET_EINVAL, "too many interpolation boxes in batch");
   int rc;
   if ((rc = dmalloc(&P.box_off, boxes + 1, "box_off")) ||
+      (rc = dmalloc(&P.trim_hist, (size_t)P.G * 2 * kTrimBins, "trim_hist")) ||
       (rc = dmalloc(&P.charges, P.stride_charges * P.G, "charges")) ||
       (rc = dmalloc(&P.qspec, P.stride_qspec * P.G, "qspec")) ||
       (rc = dmalloc(&P.qspec_t, P.stride_qspec * P.G, "qspec")) ||
@@ -273,6 +279,7 @@ static int ensure_grid(Problem& P, int cap) {
     free_grid(P);
     return rc;
   }
+  TSNET_HIP(hipMemset(P.trim_hist, 0, sizeof(int) * (size_t)P.G * 2 * kTrimBins));
   P.cap = cap;
   return TSNET_OK;
 }
@@ -297,6 +304,8 @@ static int check_params(const tsnet_params* p) {
   if (mx < 1 || mx > kMaxIntervals || (mx & (mx - 1)))
     return fail(TSNET_EINVAL, "max_intervals must be a power of two in [1, 512]");
   if (mn < 1 || mn > mx) return fail(TSNET_EINVAL, "min_intervals must be in [1, max_intervals]");
+  if (p->far_trim < 0 || p->far_trim > kMaxFarTrim)
+    return fail(TSNET_EINVAL, "far_trim must be in [0, 1024]");
   if (!(p->interval_width > 0) || !std::isfinite(p->interval_width))
     return fail(TSNET_EINVAL, "interval_width must be positive and finite");
   if (!(p->eps_r > 0) || !std::isfinite(p->eps_r)) return fail(TSNET_EINVAL, "eps_r must be > 0");
@@ -335,10 +344,15 @@ static int run_interp(Problem& P, const float2* X, const tsnet_params& prm, int 
   Ctx& c = *P.ctx;
   int rc = ensure_grid(P, prm.max_intervals);
   if (rc) return rc;
-  PlanParams pp{prm.interval_width, prm.min_intervals, prm.max_intervals};
+  PlanParams pp{prm.interval_width, prm.min_intervals, prm.max_intervals, prm.far_trim};
+  // far points need a graph of kTrimMinPoints vertices or more
+  bool may_trim = false;
+  for (const GraphInfo& g : P.ginfo_h) may_trim |= g.n >= kTrimMinPoints;
+  may_trim = may_trim && prm.far_trim > 0;
   {
     StageScope t(c, ST_BBOX, s);
     TSNET_LAUNCH(launch_bbox_plan(P, X, pp, s));
+    TSNET_LAUNCH(launch_trim_plan(P, X, pp, may_trim, s));
   }
   {
     StageScope t(c, ST_BIN, s);
@@ -351,6 +365,10 @@ static int run_interp(Problem& P, const float2* X, const tsnet_params& prm, int 
   {
     StageScope t(c, ST_FFT, s);
     TSNET_LAUNCH(launch_fft_conv(P, (float)prm.eps_r, with_ln, s));
+  }
+  if (may_trim) {
+    StageScope t(c, ST_FAR, s);
+    TSNET_LAUNCH(launch_far(P, prm.far_trim, (float)prm.eps_r, with_ln, s));
   }
   {
     StageScope t(c, ST_GATHER, s);
@@ -431,6 +449,7 @@ void tsnet_default_params(tsnet_params* p) {
   p->repulsion = TSNET_TERMS_INTERP;
   p->entropy = TSNET_TERMS_INTERP;
   p->theta = 0.5;
+  p->far_trim = 64;
 }
 
 void tsnet_default_step_params(tsnet_step_params* p) {
@@ -808,10 +827,11 @@ int tsnet_grad_direct_f64(tsnet_ctx ctx, tsnet_P Pp, const double* X, const tsne
   return TSNET_OK;
 }
 
-int tsnet_grid_info(tsnet_P Pp, int32_t* n_intervals, float* box_side, float* x0, float* y0) {
+int tsnet_grid_info(tsnet_P Pp, int32_t* n_intervals, float* box_side, float* x0, float* y0,
+                    int32_t* far_points) {
   if (!Pp) return fail(TSNET_EINVAL, "P is NULL");
   Problem& P = Pp->p;
-  if (!P.desc) return fail(TSNET_EINVAL, "no grid yet");
+  if (!P.desc || !P.box_off) return fail(TSNET_EINVAL, "no grid yet");
   TSNET_HIP(hipSetDevice(P.ctx->device));
   TSNET_HIP(hipDeviceSynchronize());
   std::vector<GridDesc> d(P.G);
@@ -821,6 +841,12 @@ int tsnet_grid_info(tsnet_P Pp, int32_t* n_intervals, float* box_side, float* x0
     if (box_side) box_side[g] = d[g].h;
     if (x0) x0[g] = d[g].x0;
     if (y0) y0[g] = d[g].y0;
+    if (far_points) {
+      int fo[2] = {0, 0};
+      if (d[g].trimmed)
+        TSNET_HIP(hipMemcpy(fo, P.box_off + far_key(d[g]), sizeof(int) * 2, hipMemcpyDeviceToHost));
+      far_points[g] = fo[1] - fo[0];
+    }
   }
   return TSNET_OK;
 }

@@ -29,7 +29,19 @@ constexpr int kBinRounds = kBinTile / 256;  // points per thread of a tile
 constexpr int kDigitBits = kBinDigitBits;
 constexpr int kDigits = 1 << kDigitBits;   // buckets per pass
 
+// Bin of a coordinate under the far-point rule (the grid plan's function).
+__device__ __forceinline__ int trim_bin_of(float v, float vmin, double s) {
+  const double f = floor(((double)v - (double)vmin) * s);
+  return f >= 0.0 ? (f < (double)(kTrimBins - 1) ? (int)f : kTrimBins - 1) : 0;
+}
+
+// Global box id of a point: its core box, or its graph's far box when the
+// plan set far points apart and the point's bins leave the core bins.
 __device__ __forceinline__ int box_key(const GridDesc& d, float x, float y) {
+  if (d.trimmed) {
+    const int bx = trim_bin_of(x, d.bmin_x, d.s_x), by = trim_bin_of(y, d.bmin_y, d.s_y);
+    if (bx < d.lo_x || bx > d.hi_x || by < d.lo_y || by > d.hi_y) return far_key(d);
+  }
   int bx, by;
   float s, t;
   locate(d, x, y, bx, by, s, t);
@@ -176,7 +188,7 @@ hipError_t launch_bin(Problem& P, const float2* X, hipStream_t s) {
   const int n = P.n;
   const int tiles = (n + kBinTile - 1) / kBinTile;
   int bits = 1;
-  while (((int64_t)1 << bits) < (int64_t)P.G * P.cap * P.cap) ++bits;
+  while (((int64_t)1 << bits) < (int64_t)P.G * ((int64_t)P.cap * P.cap + 1)) ++bits;
   const int passes = (bits + kDigitBits - 1) / kDigitBits;
   // pass p reads (kin, vin) and writes the final pair on the last pass, else
   // alternates between (keys_tmp, perm_tmp) and (keys, perm_tmp2); keys is
@@ -208,7 +220,7 @@ hipError_t launch_bin(Problem& P, const float2* X, hipStream_t s) {
     kin = kout;
     vin = vout;
   }
-  int bb = (P.G * P.cap * P.cap + 1 + 255) / 256;
+  int bb = (int)(((int64_t)P.G * ((int64_t)P.cap * P.cap + 1) + 1 + 255) / 256);
   if (bb > 4096) bb = 4096;
   if (bb < 1024) bb = 1024;  // enough threads for the grid clearing
   hipLaunchKernelGGL(k_box_bounds, dim3(bb), dim3(256), 0, s, P.skeys, n, P.btotal, P.box_off,
@@ -248,6 +260,7 @@ __device__ __forceinline__ int graph_of_box(const GridDesc* __restrict__ desc, i
 
 struct BoxAt {
   int g, bx, by;
+  bool far;  // the graph's far box: its points are not spread
   GridDesc d;
 };
 
@@ -256,9 +269,15 @@ __device__ __forceinline__ BoxAt box_at(const GridDesc* __restrict__ desc, int G
   b.g = G == 1 ? 0 : graph_of_box(desc, G, key);
   b.d = desc[b.g];
   const int local = key - b.d.box_base;
+  b.far = local == b.d.n_int * b.d.n_int;
   b.by = local / b.d.n_int;
   b.bx = local - b.by * b.d.n_int;
   return b;
+}
+
+__device__ __forceinline__ bool is_far_key(const GridDesc* __restrict__ desc, int G, int key) {
+  const GridDesc& d = desc[G == 1 ? 0 : graph_of_box(desc, G, key)];
+  return key == far_key(d);
 }
 
 // Adds the 27 node contributions of point x of box (bx, by), times w0, to acc
@@ -358,8 +377,8 @@ __global__ __launch_bounds__(kRangeWaves * kWave) void k_spread_ranges(
       const int k0 = skeys[p0], kl = skeys[p1 - 1];
       const bool whole0 = box_off[k0] == p0 && box_off[k0 + 1] == seg[1];
       const bool wholel = box_off[kl] == seg[nseg - 1] && box_off[kl + 1] == p1;
-      head_box[r] = whole0 ? -1 : k0;
-      tail_box[r] = (nseg > 1 && !wholel) ? kl : -1;
+      head_box[r] = (whole0 || is_far_key(desc, G, k0)) ? -1 : k0;
+      tail_box[r] = (nseg > 1 && !wholel && !is_far_key(desc, G, kl)) ? kl : -1;
     }
     for (int s0 = 0; s0 < nseg; s0 += kWave) {
       const int s = s0 + lane;
@@ -368,11 +387,13 @@ __global__ __launch_bounds__(kRangeWaves * kWave) void k_spread_ranges(
       if (mine && b - a < kLongSeg) {
         const int key = skeys[a];
         const BoxAt bx = box_at(desc, G, key);
-        float acc[kVals];
+        if (!bx.far) {  // far points are not spread
+          float acc[kVals];
 #pragma unroll
-        for (int q = 0; q < kVals; ++q) acc[q] = 0.f;
-        add_points(Xs, bx, a, b, 1, acc);
-        emit(box_off, bx, key, a, b, s, r, charges, stride, head_val, tail_val, acc);
+          for (int q = 0; q < kVals; ++q) acc[q] = 0.f;
+          add_points(Xs, bx, a, b, 1, acc);
+          emit(box_off, bx, key, a, b, s, r, charges, stride, head_val, tail_val, acc);
+        }
       }
       u64 todo = __ballot(mine && b - a >= kLongSeg);
       while (todo) {
@@ -381,6 +402,7 @@ __global__ __launch_bounds__(kRangeWaves * kWave) void k_spread_ranges(
         const int la = __shfl(a, src, kWave), lb = __shfl(b, src, kWave);
         const int key = skeys[la];
         const BoxAt bx = box_at(desc, G, key);
+        if (bx.far) continue;  // uniform over the wave: far points are not spread
         float acc[kVals];
 #pragma unroll
         for (int q = 0; q < kVals; ++q) acc[q] = 0.f;
@@ -452,7 +474,8 @@ __global__ __launch_bounds__(256) void k_spread_boxes(
         r1 = (be - 1) / range;
       }
     }
-    const bool mine = b < B && be > bs && r0 != r1;  // holds points, not written whole by phase 1
+    // holds points, not written whole by phase 1, not a far box
+    const bool mine = b < B && be > bs && r0 != r1 && !is_far_key(desc, G, b);
     if (mine && r1 - r0 < kDenseRanges) {
       double acc[kVals];
 #pragma unroll
@@ -475,7 +498,7 @@ __global__ __launch_bounds__(256) void k_spread_boxes(
     bool dense = false;
     if (bl < B) {
       const int bs = box_off[bl], be = box_off[bl + 1];
-      dense = be > bs && (be - 1) / range - bs / range >= kDenseRanges;
+      dense = be > bs && (be - 1) / range - bs / range >= kDenseRanges && !is_far_key(desc, G, bl);
     }
     u64 todo = __ballot(dense);
     while (todo) {
@@ -495,7 +518,7 @@ hipError_t launch_spread(Problem& P, const float2* X, hipStream_t s) {
   hipLaunchKernelGGL(k_spread_ranges, dim3(blocks), dim3(kRangeWaves * kWave), 0, s, P.xs, P.skeys,
                      P.n, P.box_off, P.desc, P.G, P.charges, P.stride_charges, P.head_box,
                      P.tail_box, P.head_val, P.tail_val, P.spread_range);
-  int bblocks = (P.G * P.cap * P.cap + 255) / 256;
+  int bblocks = (int)(((int64_t)P.G * ((int64_t)P.cap * P.cap + 1) + 255) / 256);
   if (bblocks > 8192) bblocks = 8192;
   hipLaunchKernelGGL(k_spread_boxes, dim3(bblocks), dim3(256), 0, s, P.box_off, P.btotal, P.desc,
                      P.G, P.charges, P.stride_charges, P.head_box, P.head_val, P.tail_val,

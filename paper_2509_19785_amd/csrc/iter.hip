@@ -13,22 +13,20 @@
 namespace tsnet {
 
 // ---------------------------------------------------------------------------
-// Bounding box per chunk, then (last block to finish) the grid of every graph.
-// Grid rule (Sec. 2.3 leaves I and P open): span = larger side of the
-// bounding box, n_int = ceil(span / h_target) clamped to [min, max] and
-// rounded up to a power of two, box side h = span / n_int, grid centred on the
-// bounding box. The decisions are taken in FP64.
+// Bounding box per chunk; the last block to finish reduces the boxes of every
+// graph and starts its descriptor: the box, the bin scales of the far-point
+// rule and whether that rule can apply (t = min(far_trim, n / 64) >= 1 and a
+// positive width). The grid itself is planned by k_trim_plan.
 // One block of kChunkThreads per chunk (a few vertices per thread); the bounds
-// of every chunk go to part[chunk] and the last block to finish plans the
-// grids. One counter update per chunk: many more blocks would queue on it.
+// of every chunk go to part[chunk]. One counter update per chunk: many more
+// blocks would queue on it.
 constexpr int kChunkThreads = 1024;
 constexpr int kPartBatch = 8;  // chunk partials a lane of the final reduction loads at once
 
 __global__ __launch_bounds__(kChunkThreads) void k_bbox_plan(
     const float2* __restrict__ X, const int* __restrict__ chunk_start,
     const int* __restrict__ chunk_end, int nblocks, float4* part, unsigned* counter,
-    const GraphInfo* __restrict__ gi, int G, PlanParams pp, GridDesc* desc, int* btotal,
-    unsigned* status) {
+    const GraphInfo* __restrict__ gi, int G, PlanParams pp, GridDesc* desc) {
   __shared__ float red[kChunkThreads / kWave][4];
   __shared__ int bad_s;
   __shared__ int last_s;
@@ -103,12 +101,145 @@ __global__ __launch_bounds__(kChunkThreads) void k_bbox_plan(
     f = wave_max(f);
     nonfinite = __any(nonfinite);
     if (lane_id() != 0) continue;
-    double da = a, db = b, de = e, df = f;
-    if (!(db >= da)) {  // no finite point at all
-      da = db = de = df = 0.0;
+    if (!(b >= a)) {  // no finite point at all
+      a = b = e = f = 0.f;
     }
-    int flags = nonfinite ? TSNET_STATUS_NONFINITE : 0;
-    double span = fmax(db - da, df - de);
+    GridDesc d = {};
+    d.bmin_x = a;
+    d.bmax_x = b;
+    d.bmin_y = e;
+    d.bmax_y = f;
+    d.flags = nonfinite ? TSNET_STATUS_NONFINITE : 0;
+    const double wx = (double)b - (double)a, wy = (double)f - (double)e;
+    d.s_x = wx > 0.0 ? (double)kTrimBins / wx : 0.0;
+    d.s_y = wy > 0.0 ? (double)kTrimBins / wy : 0.0;
+    const int t = min(pp.far_trim, gi[g].n / kTrimMinPoints);
+    d.trim_t = t;
+    d.trimmed = (t >= 1 && fmax(wx, wy) > 0.0 && !nonfinite) ? 1 : 0;
+    desc[g] = d;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *counter = 0u;
+}
+
+hipError_t launch_bbox_plan(Problem& P, const float2* X, const PlanParams& pp, hipStream_t s) {
+  hipLaunchKernelGGL(k_bbox_plan, dim3(P.num_chunks), dim3(kChunkThreads), 0, s, X, P.chunk_start,
+                     P.chunk_end, P.num_chunks, P.bbox_part, P.counters + 0, P.ginfo, P.G, pp,
+                     P.desc);
+  return hipGetLastError();
+}
+
+// Bin of coordinate v among kTrimBins equal bins from v_min (s = kTrimBins /
+// width), in FP64: floor((v - v_min) s), the last bin closed. A product of a
+// difference, so no contraction changes it.
+__device__ __forceinline__ int trim_bin(float v, float vmin, double s) {
+  const double f = floor(((double)v - (double)vmin) * s);
+  return f >= 0.0 ? (f < (double)(kTrimBins - 1) ? (int)f : kTrimBins - 1) : 0;
+}
+
+// Per chunk of a graph the far-point rule may apply to: bin counts of both
+// axes in LDS, added to the graph's counts (integer atomics, so the counts do
+// not depend on the order).
+constexpr int kTrimThreads = 1024;
+
+__global__ __launch_bounds__(kTrimThreads) void k_trim_hist(
+    const float2* __restrict__ X, const int* __restrict__ chunk_graph,
+    const int* __restrict__ chunk_start, const int* __restrict__ chunk_end,
+    const GridDesc* __restrict__ desc, int* hist) {
+  __shared__ int hx[kTrimBins], hy[kTrimBins];
+  const int c = blockIdx.x;
+  const int g = chunk_graph[c];
+  const GridDesc d = desc[g];
+  if (!d.trimmed) return;
+  for (int b = threadIdx.x; b < kTrimBins; b += kTrimThreads) hx[b] = hy[b] = 0;
+  __syncthreads();
+  for (int i = chunk_start[c] + threadIdx.x; i < chunk_end[c]; i += kTrimThreads) {
+    const float2 p = X[i];
+    atomicAdd(&hx[trim_bin(p.x, d.bmin_x, d.s_x)], 1);
+    atomicAdd(&hy[trim_bin(p.y, d.bmin_y, d.s_y)], 1);
+  }
+  __syncthreads();
+  int* h = hist + (size_t)g * 2 * kTrimBins;
+  for (int b = threadIdx.x; b < kTrimBins; b += kTrimThreads) {
+    if (hx[b]) atomicAdd(&h[b], hx[b]);
+    if (hy[b]) atomicAdd(&h[kTrimBins + b], hy[b]);
+  }
+}
+
+// Grid plan, one block per graph (Sec. 2.3 leaves the interval count, the
+// node placement and the covered region open). Where the far-point rule may
+// apply: lo = bin of the (t+1)-th smallest coordinate, hi = bin of the
+// (t+1)-th largest, per axis; when the core bins' region is at most half the
+// bounding box's larger side, the grid covers that region and the points
+// outside it are far. Otherwise the grid covers the bounding box. Then
+// span = larger side (floor kSpanFloor), n_int = ceil(span / h_target)
+// clamped to [min, max] and rounded up to a power of two, h = span / n_int,
+// grid centred on the region. Decisions in FP64 with every operation rounded
+// on its own (no contraction), so the far points and the grid are those of
+// the same rule evaluated anywhere else in IEEE FP64. The counts are cleared
+// for the next call. The last block to finish numbers the boxes of the batch.
+constexpr int kPlanThreads = 256;
+constexpr int kPlanBins = kTrimBins / kPlanThreads;  // consecutive bins per thread
+
+__global__ __launch_bounds__(kPlanThreads) void k_trim_plan(
+    GridDesc* desc, int G, int* hist, PlanParams pp, unsigned* counter, int* btotal,
+    unsigned* status) {
+  __shared__ int sh[kPlanThreads / kWave + 1];
+  __shared__ int bounds[4];  // lo_x, hi_x, lo_y, hi_y
+  __shared__ int last_s;
+  const int g = blockIdx.x;
+  GridDesc d = desc[g];
+  if (d.trimmed) {  // uniform over the block
+    int* h = hist + (size_t)g * 2 * kTrimBins;
+    const int t = d.trim_t;
+    for (int axis = 0; axis < 2; ++axis) {
+      int* ha = h + axis * kTrimBins;
+      int v[kPlanBins];
+      int local = 0;
+#pragma unroll
+      for (int k = 0; k < kPlanBins; ++k) {
+        v[k] = ha[threadIdx.x * kPlanBins + k];
+        local += v[k];
+      }
+#pragma unroll
+      for (int k = 0; k < kPlanBins; ++k) ha[threadIdx.x * kPlanBins + k] = 0;
+      int total;
+      int cum = block_excl_scan(local, sh, &total);
+      const int want_lo = t + 1, want_hi = total - t;  // first bins reaching these counts
+#pragma unroll
+      for (int k = 0; k < kPlanBins; ++k) {
+        const int before = cum;
+        cum += v[k];
+        if (before < want_lo && cum >= want_lo) bounds[2 * axis] = threadIdx.x * kPlanBins + k;
+        if (before < want_hi && cum >= want_hi) bounds[2 * axis + 1] = threadIdx.x * kPlanBins + k;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double xlo = d.bmin_x, xhi = d.bmax_x, ylo = d.bmin_y, yhi = d.bmax_y;
+    int trim = 0;
+    if (d.trimmed) {
+      const double wx = __dsub_rn((double)d.bmax_x, (double)d.bmin_x);
+      const double wy = __dsub_rn((double)d.bmax_y, (double)d.bmin_y);
+      const double qx = wx / kTrimBins, qy = wy / kTrimBins;  // exact: a power of two
+      d.lo_x = bounds[0];
+      d.hi_x = bounds[1];
+      d.lo_y = bounds[2];
+      d.hi_y = bounds[3];
+      const double cw = __dmul_rn((double)(d.hi_x - d.lo_x + 1), qx);
+      const double ch = __dmul_rn((double)(d.hi_y - d.lo_y + 1), qy);
+      if (2.0 * fmax(cw, ch) <= fmax(wx, wy)) {
+        trim = 1;
+        xlo = __dadd_rn((double)d.bmin_x, __dmul_rn((double)d.lo_x, qx));
+        xhi = __dadd_rn((double)d.bmin_x, __dmul_rn((double)(d.hi_x + 1), qx));
+        ylo = __dadd_rn((double)d.bmin_y, __dmul_rn((double)d.lo_y, qy));
+        yhi = __dadd_rn((double)d.bmin_y, __dmul_rn((double)(d.hi_y + 1), qy));
+      }
+    }
+    d.trimmed = trim;
+    int flags = d.flags;
+    double span = fmax(__dsub_rn(xhi, xlo), __dsub_rn(yhi, ylo));
     if (!(span >= kSpanFloor)) span = kSpanFloor;
     const double q = span / pp.h_target;
     int nint;
@@ -123,41 +254,46 @@ __global__ __launch_bounds__(kChunkThreads) void k_bbox_plan(
     while (p2 < nint) p2 <<= 1;
     nint = p2 < pp.max_int ? p2 : pp.max_int;
     const double h = span / nint;
-    const double cx = 0.5 * (da + db), cy = 0.5 * (de + df);
-    GridDesc d;
-    d.x0 = (float)(cx - 0.5 * nint * h);
-    d.y0 = (float)(cy - 0.5 * nint * h);
+    const double cx = __dmul_rn(0.5, __dadd_rn(xlo, xhi)), cy = __dmul_rn(0.5, __dadd_rn(ylo, yhi));
+    const double half = __dmul_rn(__dmul_rn(0.5, (double)nint), h);
+    d.x0 = (float)__dsub_rn(cx, half);
+    d.y0 = (float)__dsub_rn(cy, half);
     d.h = (float)h;
     d.inv_h = (float)(1.0 / h);
     d.cx = (float)cx;
     d.cy = (float)cy;
-    d.half = (float)(0.5 * nint * h);
+    d.half = (float)half;
     d.spacing = (float)(h / kNodes);
     d.n_int = nint;
     d.ng = kNodes * nint;
     d.M = 2 * kNodes * nint;
     d.box_base = 0;
     d.flags = flags;
-    d.pad0 = d.pad1 = d.pad2 = 0;
     desc[g] = d;
     if (flags) atomicOr(status, (unsigned)flags);
+    __threadfence();
+    last_s = (atomicAdd(counter, 1u) == (unsigned)(G - 1));
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    for (int g = 0; g < G; ++g) {
-      desc[g].box_base = acc;
-      acc += desc[g].n_int * desc[g].n_int;
-    }
-    *btotal = acc;
-    *counter = 0u;
+  if (!last_s || threadIdx.x != 0) return;
+  __threadfence();
+  int acc = 0;  // each graph: n_int^2 core boxes, then its far box
+  for (int gg = 0; gg < G; ++gg) {
+    desc[gg].box_base = acc;
+    const int ni = ld_coherent(&desc[gg].n_int);
+    acc += ni * ni + 1;
   }
+  *btotal = acc;
+  *counter = 0u;
 }
 
-hipError_t launch_bbox_plan(Problem& P, const float2* X, const PlanParams& pp, hipStream_t s) {
-  hipLaunchKernelGGL(k_bbox_plan, dim3(P.num_chunks), dim3(kChunkThreads), 0, s, X, P.chunk_start,
-                     P.chunk_end, P.num_chunks, P.bbox_part, P.counters + 0, P.ginfo, P.G, pp,
-                     P.desc, P.btotal, P.ctx->status);
+hipError_t launch_trim_plan(Problem& P, const float2* X, const PlanParams& pp, bool with_hist,
+                            hipStream_t s) {
+  if (with_hist)
+    hipLaunchKernelGGL(k_trim_hist, dim3(P.num_chunks), dim3(kTrimThreads), 0, s, X, P.chunk_graph,
+                       P.chunk_start, P.chunk_end, P.desc, P.trim_hist);
+  hipLaunchKernelGGL(k_trim_plan, dim3(P.G), dim3(kPlanThreads), 0, s, P.desc, P.G, P.trim_hist, pp,
+                     P.counters + 3, P.btotal, P.ctx->status);
   return hipGetLastError();
 }
 
@@ -168,7 +304,9 @@ hipError_t launch_bbox_plan(Problem& P, const float2* X, const PlanParams& pp, h
 //   F_rep = (x - c) phi[K2,1] - phi[K2,x],  F_ent = (x - c) phi[Ke,1] - phi[Ke,x],
 //   Z_i = phi[K1,1] - 1 (the self term K1(0) = 1),
 // and write them at the vertex of the slot (F_rep and F_ent as one 16-byte
-// record, Z_i only when it is asked for).
+// record, Z_i only when it is asked for). Far points (the last box of their
+// graph) were summed by k_far: their F_rep and F_ent are in place, their Z_i
+// and ln sum come from slot_z and slot_ln.
 // One block of kChunkThreads per chunk. Each block also sums the Z_i of its
 // chunk (compensated FP32, in sorted order) into zpart[chunk]; the last block
 // to finish adds the chunk sums of every graph in FP64 (fixed order, so Z is
@@ -178,8 +316,9 @@ __global__ __launch_bounds__(kChunkThreads) void k_gather(
     const int* __restrict__ chunk_graph, const int* __restrict__ chunk_start,
     const int* __restrict__ chunk_end, const GridDesc* __restrict__ desc,
     const GraphInfo* __restrict__ gi, int G, const float* __restrict__ pot, size_t stride_pot,
-    float4* rep_ent, float* zi, float* lnv, double* zpart, unsigned* counter,
-    int nblocks, double* zg, double* Z_out) {
+    const float* __restrict__ slot_z, const float* __restrict__ slot_ln, float4* rep_ent,
+    float* zi, float* lnv, double* zpart, unsigned* counter, int nblocks, double* zg,
+    double* Z_out) {
   constexpr int NW = kChunkThreads / kWave;
   __shared__ float sh_hi[NW], sh_lo[NW];
   __shared__ int last_s;
@@ -192,6 +331,13 @@ __global__ __launch_bounds__(kChunkThreads) void k_gather(
   for (int p = chunk_start[c] + threadIdx.x; p < chunk_end[c]; p += kChunkThreads) {
     const float2 x = xs[p];
     const int local = skeys[p] - d.box_base;
+    if (local == d.n_int * d.n_int) {  // a far point: its sums come from k_far
+      const float z = slot_z[p];
+      if (zi) zi[perm[p]] = z;
+      if (lnv) lnv[perm[p]] = slot_ln[p];
+      zs.add(z);
+      continue;
+    }
     const int by = local / d.n_int, bx = local - by * d.n_int;
     const float s = (x.x - d.x0) / d.h - (float)bx;
     const float t = (x.y - d.y0) / d.h - (float)by;
@@ -277,7 +423,7 @@ hipError_t launch_gather(Problem& P, const float2* X, int with_ln, int with_zi, 
   const int nb = P.num_chunks;
   hipLaunchKernelGGL(k_gather, dim3(nb), dim3(kChunkThreads), 0, s, P.xs, P.skeys, P.perm, P.chunk_graph,
                      P.chunk_start, P.chunk_end, P.desc, P.ginfo, P.G, P.pot, P.stride_pot,
-                     P.rep_ent, with_zi ? P.zi : nullptr, with_ln ? P.lnv : nullptr, P.zpart,
+                     P.slot_z, P.slot_ln, P.rep_ent, with_zi ? P.zi : nullptr, with_ln ? P.lnv : nullptr, P.zpart,
                      P.counters + 1, nb, P.zg, Z_out);
   return hipGetLastError();
 }

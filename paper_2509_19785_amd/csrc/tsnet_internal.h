@@ -29,16 +29,23 @@ constexpr int kTileMaxRows = 4096;        // rows per row tile of the tiled attr
 constexpr int kTileSlotBits = 12;         // bits of a row slot inside a tile
 constexpr int kTileMinTiles = 256;        // row tiles (one workgroup each) at least
 constexpr int kTileAutoMinN = 262144;     // automatic layout: tiled from this many vertices
+constexpr int kTrimBins = 2048;           // bins per axis of the far-point rule
+constexpr int kTrimMinPoints = 64;        // points per far point allowed (t <= n / 64)
+constexpr int kMaxFarTrim = 1024;         // largest far_trim accepted
 
 // Output channels of the convolution (charge index in comments):
 //  0 K2*1, 1 K2*x, 2 K2*y, 3 K1*1, 4 Ke*1, 5 Ke*x, 6 Ke*y, 7 Kln*1
 enum { CH_K2_1 = 0, CH_K2_X, CH_K2_Y, CH_K1_1, CH_KE_1, CH_KE_X, CH_KE_Y, CH_KLN_1 };
 
 // Per-graph interpolation grid, rewritten on the device every evaluation.
+// The grid covers the bounding box, or the core region when far points are
+// set apart (trimmed = 1): a point is far when its bin on either axis lies
+// outside [lo, hi], bin = min(floor((v - v_min) * s), kTrimBins - 1) in FP64.
+// Box ids of the graph: n_int^2 core boxes from box_base, then its far box.
 struct GridDesc {
   float x0, y0;      // lower-left corner of the box grid
   float h, inv_h;    // box side and its inverse
-  float cx, cy;      // charge centre (bounding-box centre)
+  float cx, cy;      // charge centre (centre of the covered region)
   float half;        // half the grid side: charges x, y are stored divided by it
   float spacing;     // node spacing h / 3
   int n_int;         // boxes per axis
@@ -46,8 +53,16 @@ struct GridDesc {
   int M;             // FFT length per axis (2 ng)
   int box_base;      // first global box id of this graph
   int flags;         // TSNET_STATUS_* bits raised by this graph
-  int pad0, pad1, pad2;
+  int trimmed;       // 1: far points set apart (bounding-box kernel: 1 = may be)
+  int trim_t;        // t = min(far_trim, n / kTrimMinPoints)
+  int lo_x, hi_x, lo_y, hi_y;  // core bins per axis
+  float bmin_x, bmin_y;        // bounding box of the graph's points
+  float bmax_x, bmax_y;
+  int pad0;
+  double s_x, s_y;   // kTrimBins / width per axis (0 for a zero width)
 };
+
+__host__ __device__ inline int far_key(const GridDesc& d) { return d.box_base + d.n_int * d.n_int; }
 
 // Static per-graph data (device copy made once per problem).
 struct GraphInfo {
@@ -64,12 +79,13 @@ struct GraphInfo {
 struct PlanParams {
   double h_target;
   int min_int, max_int;
+  int far_trim;      // t of the far-point rule (0: the grid covers the bounding box)
 };
 
 // Stage ids for optional per-stage timing.
 enum Stage {
   ST_BBOX = 0, ST_BIN, ST_SPREAD, ST_FFT, ST_GATHER, ST_ZRED, ST_ATTR, ST_STEP, ST_COST,
-  ST_DIRECT, ST_BUILD, ST_PMDS, ST_NP, ST_STRESS, ST_QUADTREE, ST_COUNT
+  ST_DIRECT, ST_BUILD, ST_PMDS, ST_NP, ST_STRESS, ST_QUADTREE, ST_FAR, ST_COUNT
 };
 
 // ---------------------------------------------------------------- contexts
@@ -135,7 +151,10 @@ struct Problem {
   float2* xs = nullptr;               // [n] X in sorted order
   int* bin_hist = nullptr;            // [256 tiles + 1] digit counts, then offsets
   int* bin_tsum = nullptr;            // scan scratch
-  int* box_off = nullptr;             // [G cap^2 + 1] first sorted slot of every box
+  int* box_off = nullptr;             // [G (cap^2 + 1) + 1] first sorted slot of every box
+  int* trim_hist = nullptr;           // [G][2][kTrimBins] bin counts (kept at zero between calls)
+  float* slot_z = nullptr;            // [n] Z_i of far points, by sorted slot
+  float* slot_ln = nullptr;           // [n] interpolated ln sums of far points, by sorted slot
   float* charges = nullptr;           // per graph 3 ng^2
   float2* qspec = nullptr;            // per graph [3][ng][M/2+1] row spectra of the charges
   float2* qspec_t = nullptr;          // per graph [3][M/2+1][ng] the same, transposed
@@ -176,6 +195,12 @@ int fail(int code, const std::string& msg);
 
 // per-evaluation path (iter.hip, bin.hip, attract.hip)
 hipError_t launch_bbox_plan(Problem& P, const float2* X, const PlanParams& pp, hipStream_t s);
+// far-point rule: bin counts (only when some graph may set points apart), then the grid plan
+hipError_t launch_trim_plan(Problem& P, const float2* X, const PlanParams& pp, bool with_hist,
+                            hipStream_t s);
+// far points: their own sums from the node charges and each other, and their
+// charges added to the node potentials (between the FFT and the gather)
+hipError_t launch_far(Problem& P, int far_trim, float eps, int with_ln, hipStream_t s);
 hipError_t launch_bin(Problem& P, const float2* X, hipStream_t s);
 hipError_t launch_spread(Problem& P, const float2* X, hipStream_t s);
 // gather also reduces Z per graph into zg (and Z_out when not NULL)

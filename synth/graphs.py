@@ -266,6 +266,23 @@ def initial_layout(n: int, seed: int, std: float = 0.01) -> np.ndarray:
     return rng.normal(0.0, std, size=(n, 2)).astype(np.float32)
 
 
+def bulk_with_far_points(n: int, seed: int, n_far: int = 100, std: float = 0.18,
+                         r_min: float = 1.0, r_max: float = 60.0) -> np.ndarray:
+    """A dense bulk N(0, std^2 I) with ``n_far`` of its points moved far out: at
+    radii log-uniform in [r_min, r_max] and uniform directions. The shape of
+    the layouts a descent from a small random start passes through at
+    n = 1e6 (a bulk about a unit wide, a few dozen to a hundred points out to
+    tens of units setting the bounding box). float32 [n, 2]."""
+    rng = np.random.default_rng(seed)
+    X = rng.normal(0.0, std, size=(n, 2))
+    idx = rng.choice(n, size=min(n_far, n), replace=False)
+    r = np.exp(rng.uniform(np.log(r_min), np.log(r_max), size=idx.shape[0]))
+    a = rng.uniform(0.0, 2.0 * np.pi, size=idx.shape[0])
+    X[idx, 0] = r * np.cos(a)
+    X[idx, 1] = r * np.sin(a)
+    return X.astype(np.float32)
+
+
 def random_affinity(n: int, mean_len: float, seed: int, hub_rows: int = 0, hub_len: int = 0,
                     empty_frac: float = 0.0):
     """A seeded sparse nonnegative n x n matrix in CSR form for layout-independent

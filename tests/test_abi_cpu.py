@@ -31,10 +31,11 @@ def test_defaults():
     _lib.tsnet_default_params(ctypes.byref(p))
     assert (p.lambda_kl, p.lambda_c, p.lambda_r, p.eps_r) == (1.0, 1.2, 0.01, 0.05)
     assert (p.interval_width, p.min_intervals, p.max_intervals, p.nodes_per_interval) == (0.25, 50, 512, 3)
-    assert (p.repulsion, p.entropy, p.theta) == (0, 0, 0.5)
+    assert (p.repulsion, p.entropy, p.theta, p.far_trim) == (0, 0, 0.5, 64)
     # the Python mirror of the struct has the C layout (size and defaults)
     from paper_2509_19785_amd import api
-    assert ctypes.sizeof(_lib.tsnet_params) == 72
+    assert ctypes.sizeof(_lib.tsnet_params) == 80
+    assert api.Params().far_trim == p.far_trim
     q = api.Params.variant("BH-tsNET", theta=0.3).to_c()
     assert (q.repulsion, q.entropy, q.theta) == (1, 1, 0.3)
     s = _lib.tsnet_step_params()
@@ -49,11 +50,12 @@ def test_null_arguments_are_rejected():
     assert b"NULL" in _lib.lib.tsnet_last_error()
     assert _lib.lib.tsnet_grad(None, None, None, None, None, None, None) == _lib.TSNET_EINVAL
     assert _lib.lib.tsnet_P_free(None) == 0 and _lib.lib.tsnet_ctx_destroy(None) == 0
-    assert _lib.lib.tsnet_stage_count() == 15
+    assert _lib.lib.tsnet_stage_count() == 16
     assert _lib.lib.tsnet_stage_name(6) == b"attract_assemble"
     assert _lib.lib.tsnet_stage_name(11) == b"pmds"
     assert _lib.lib.tsnet_stage_name(12) == b"np" and _lib.lib.tsnet_stage_name(13) == b"stress"
     assert _lib.lib.tsnet_stage_name(14) == b"quadtree"
+    assert _lib.lib.tsnet_stage_name(15) == b"far_points"
 
 
 def test_pmds_arguments_checked_on_the_host():

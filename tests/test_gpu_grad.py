@@ -4,7 +4,9 @@ Every expected value comes from the FP64 oracle on the same seeded inputs;
 P is built by the oracle and handed to the library with tsnet_P_from_host.
 Tolerances: kernel arithmetic against the FP64 interpolation oracle (same
 scheme) 2e-5; the total gradient against the exact O(n^2) oracle 1e-3
-relative L2 (term-normalised where the gradient itself has converged to ~0).
+relative L2. Only at a converged layout, where the gradient itself is ~0 and
+its relative error says nothing, the error is measured against the size of
+its terms instead (both numbers are printed for every case).
 """
 import numpy as np
 import pytest
@@ -63,7 +65,7 @@ def _interp_tol(X32):
 
 
 def _check_against_oracles(api, prob, P, X32, prm, tol_interp=None, tol_total=1e-3, label="",
-                           tol_terms=None, tol_Z=1e-4):
+                           tol_terms=None, tol_Z=1e-4, converged=False):
     say(f"[grad parity] {label} n={X32.shape[0]}")
     tol_interp = tol_interp or _interp_tol(X32)
     tol_terms = tol_terms or tol_total
@@ -71,7 +73,8 @@ def _check_against_oracles(api, prob, P, X32, prm, tol_interp=None, tol_total=1e
     X = X32.astype(np.float64)
     cp = CostParams(prm.lambda_kl, prm.lambda_c, prm.lambda_r, prm.eps_r)
     ex = gradient.grad_terms(X, P, cp)
-    it = interp.interp_terms(X, prm.eps_r, prm.interval_width, prm.min_intervals, prm.max_intervals)
+    it = interp.interp_terms(X, prm.eps_r, prm.interval_width, prm.min_intervals, prm.max_intervals,
+                             far_trim=prm.far_trim)
     fa = gradient.attraction_all(X, P.rowptr, P.col, P32(P).val)
     e_attr = rel_l2(got["F_attr"], fa)
     e_rep_i = rel_l2(got["F_rep"], it.F_rep)
@@ -87,15 +90,19 @@ def _check_against_oracles(api, prob, P, X32, prm, tol_interp=None, tol_total=1e
     e_G_terms = np.linalg.norm(got["G"] - ex.G) / scale
     say(f"   attr {e_attr:.2e} rep(interp) {e_rep_i:.2e} ent(interp) {e_ent_i:.2e} Zi(interp) {e_z_i:.2e}"
         f" rep {e_rep:.2e} ent {e_ent:.2e} Z {e_Z:.2e} G {e_G:.2e} G/terms {e_G_terms:.2e}"
-        f" n_int {it.grid.n_int}")
+        f" n_int {it.grid.n_int} far {int(it.far.sum())}")
     assert e_attr <= 1e-6
     assert e_rep_i <= tol_interp and e_ent_i <= tol_interp and e_z_i <= tol_interp
     assert e_rep <= tol_terms and e_ent <= tol_terms and e_Z <= tol_Z
-    assert min(e_G, e_G_terms) <= tol_total
-    # the grid the GPU used is the oracle's grid
+    if converged:
+        assert e_G_terms <= 1e-5
+    else:
+        assert e_G <= tol_total
+    # the grid the GPU used is the oracle's grid, with the same far points
     gi = prob.grid_info()
     assert int(gi["n_intervals"][0]) == it.grid.n_int
     assert abs(float(gi["box_side"][0]) - it.grid.h) <= 1e-6 * it.grid.h
+    assert int(gi["far_points"][0]) == int(it.far.sum())
     return got, ex
 
 
@@ -139,7 +146,9 @@ def test_converged_layout(api, ctx, grid_problem):
         G = gradient.grad_terms(X, P).G
         X, upd, gains = ostep.step(X, upd, gains, G, t)
     prob = _upload(api, ctx, P)
-    _check_against_oracles(api, prob, P, X.astype(np.float32), api.Params(), label="grid32 t=120")
+    # the gradient has converged (|G| << |4 F_attr|): measured against its terms
+    _check_against_oracles(api, prob, P, X.astype(np.float32), api.Params(), label="grid32 t=120",
+                           converged=True)
 
 
 def test_sbm_ragged(api, ctx):
@@ -150,6 +159,56 @@ def test_sbm_ragged(api, ctx):
     _check_against_oracles(api, prob, P, X, api.Params(min_intervals=8), label="sbm 3033")
 
 
+@pytest.mark.parametrize("n_far,std,seed", [(40, 0.15, 1), (100, 0.3, 2), (8, 0.05, 3)])
+def test_far_points_sbm(api, ctx, n_far, std, seed):
+    # a dense bulk with far points setting the bounding box: the grid covers
+    # the bulk, the far points meet it through the nodes
+    g = graphs.sbm([700, 900, 1433], 0.012, 4e-4, 11)
+    P = affinities.build_P(g.indptr, g.indices, 15.0, seed=3)
+    prob = _upload(api, ctx, P)
+    X = graphs.bulk_with_far_points(g.n, seed, n_far=n_far, std=std)
+    _, ex = _check_against_oracles(api, prob, P, X, api.Params(), label=f"sbm 3033 far={n_far}")
+    assert prob.grid_info()["far_points"][0] >= n_far
+    # with the rule off the grid covers the bounding box (and the oracle agrees)
+    _check_against_oracles(api, prob, P, X, api.Params(far_trim=0), tol_terms=5e-2, tol_Z=1e-3,
+                           tol_total=5e-2, label=f"sbm 3033 far={n_far} rule off")
+    assert prob.grid_info()["far_points"][0] == 0
+
+
+def test_far_points_cost(api, ctx, grid_problem):
+    # the ln(eps + r^2) channel of the cost with far points (their own ln
+    # sums and their ln kernel at the nodes)
+    g, P = grid_problem
+    prob = _upload(api, ctx, P)
+    X = graphs.bulk_with_far_points(g.n, 4, n_far=12, std=0.2)
+    got = prob.cost(torch.tensor(X, device="cuda")).cpu().numpy()[0]
+    assert prob.grid_info()["far_points"][0] >= 12
+    ex = gradient.cost_terms(X.astype(np.float64), P, CostParams())
+    say(f"[cost parity] far points: gpu {got} oracle {ex.kl[0]} {ex.cmp[0]} {ex.ent[0]}")
+    assert abs(got[0] - ex.kl[0]) <= 1e-5 * abs(ex.kl[0])
+    assert abs(got[2] - ex.ent[0]) <= 1e-4 * abs(ex.ent[0])
+    assert abs(got[3] - ex.total[0]) <= 1e-5 * abs(ex.total[0])
+
+
+def test_nonfinite_layout_raises_status(api, ctx, grid_problem):
+    # NaN or Inf in X: the grid set-up raises TSNET_STATUS_NONFINITE through
+    # the C ABI (the call itself is asynchronous and returns TSNET_OK)
+    from paper_2509_19785_amd import _lib
+    g, P = grid_problem
+    prob = _upload(api, ctx, P)
+    for bad in (np.nan, np.inf):
+        X = graphs.initial_layout(g.n, 1, std=1.0)
+        X[17, 1] = bad
+        ctx.status()
+        prob.grad(torch.tensor(X, device="cuda"))
+        st = ctx.status()
+        say(f"[status] X[17] = {bad}: status {st:#x}")
+        assert st & _lib.TSNET_STATUS_NONFINITE
+    X = graphs.initial_layout(g.n, 1, std=1.0)
+    prob.grad(torch.tensor(X, device="cuda"))
+    assert not ctx.status() & _lib.TSNET_STATUS_NONFINITE
+
+
 def test_batch_of_graphs(api, ctx):
     parts = [graphs.grid(16, 20), graphs.sbm([250, 260], 0.05, 0.004, 2), graphs.random_recursive_tree(777, 9)]
     b = graphs.concat_graphs(parts)
@@ -157,6 +216,9 @@ def test_batch_of_graphs(api, ctx):
     prob = _upload(api, ctx, P, b.graph_offsets)
     n = b.indptr.shape[0] - 1
     X = graphs.initial_layout(n, 3, std=1.5)
+    # the second graph: a dense bulk with far points (the others have none)
+    a1, a2 = int(b.graph_offsets[1]), int(b.graph_offsets[2])
+    X[a1:a2] = graphs.bulk_with_far_points(a2 - a1, 6, n_far=9, std=0.2)
     say(f"[grad parity] batch G=3 n={n}")
     got = _terms(api, prob, X)
     X64 = X.astype(np.float64)
@@ -166,8 +228,11 @@ def test_batch_of_graphs(api, ctx):
         a0, a1 = int(b.graph_offsets[gidx]), int(b.graph_offsets[gidx + 1])
         it = interp.interp_terms(X64[a0:a1], 0.05)
         assert int(gi["n_intervals"][gidx]) == it.grid.n_int
+        assert int(gi["far_points"][gidx]) == int(it.far.sum())
+        assert (it.far.sum() > 0) == (gidx == 1)
         assert rel_l2(got["F_rep"][a0:a1], it.F_rep) <= 2e-5
         assert rel_l2(got["F_ent"][a0:a1], it.F_ent) <= 2e-5
+        assert rel_l2(got["Z_i"][a0:a1], it.Z_i) <= 2e-5
         assert abs(got["Z"][gidx] - ex.Z[gidx]) <= 1e-4 * ex.Z[gidx]
         assert rel_l2(got["G"][a0:a1], ex.G[a0:a1]) <= 1e-3
 

@@ -28,7 +28,7 @@ import numpy as np
 import pytest
 
 from helpers import P32, rel_l2, say
-from oracle import affinities, gradient, perplexity
+from oracle import affinities, gradient, interp, perplexity
 from oracle.gradient import CostParams
 from synth import graphs
 
@@ -156,6 +156,72 @@ def test_ba1m_repulsion_sampled(api, ba1m, std):
         f" Z_i {e_zi:.2e}; Z {t['Z'][0]:.6e} sum Z_i {z_sum:.6e}")
     assert e_rep <= 1e-3 and e_ent <= 1e-3 and e_zi <= 1e-3
     assert abs(t["Z"][0] - z_sum) <= 1e-5 * z_sum
+
+
+def test_ba1m_bulk_with_far_points(api, ba1m):
+    """The layout class of the benchmark descent: a dense bulk about a unit wide
+    and ~100 far points out to tens of units that set the bounding box. Against
+    the oracle: the far points and the grid; every vertex's interpolated sums
+    (FP64 interpolation oracle); F_rep, F_ent, Z_i of 256 sampled vertices and
+    the gradient of 16 of them against exact sums, each term within 1e-3."""
+    g, prob = ba1m
+    X32 = graphs.bulk_with_far_points(g.n, 3, n_far=100)
+    X64 = X32.astype(np.float64)
+    prm = api.Params()
+    t = _terms(prob, torch.tensor(X32, device="cuda"), prm)
+    gi = prob.grid_info()
+    it = interp.interp_terms(X64, prm.eps_r, prm.interval_width, prm.min_intervals, prm.max_intervals)
+    say(f"[workload] BA 1e6 bulk + far points: n_int {int(gi['n_intervals'][0])} (oracle "
+        f"{it.grid.n_int}), far {int(gi['far_points'][0])} (oracle {int(it.far.sum())})")
+    assert int(gi["n_intervals"][0]) == it.grid.n_int
+    assert int(gi["far_points"][0]) == int(it.far.sum()) >= 100
+    e_i = {k: rel_l2(t[k], getattr(it, k)) for k in ("F_rep", "F_ent", "Z_i")}
+    say("   against the FP64 interpolation: " + " ".join(f"{k} {v:.2e}" for k, v in e_i.items()))
+    assert max(e_i.values()) <= 2e-5
+    # exact pair sums of sampled vertices: every far point and 156 others
+    rng = np.random.default_rng(6)
+    far_ids = np.nonzero(it.far)[0]
+    rows = np.concatenate([far_ids, rng.choice(np.nonzero(~it.far)[0], 256 - far_ids.size, replace=False)])
+    zi, frep, fent = gradient.pair_sums(X64, 0.05, rows=rows)
+    e_rep = rel_l2(t["F_rep"][rows], frep)
+    e_ent = rel_l2(t["F_ent"][rows], fent)
+    e_zi = rel_l2(t["Z_i"][rows], zi)
+    # the oracle's interpolated Z_i of the same rows, to vouch for its Z below
+    e_zi_oracle = rel_l2(it.Z_i[rows], zi)
+    say(f"   against exact sums of {rows.size} vertices: rep {e_rep:.2e} ent {e_ent:.2e} Z_i {e_zi:.2e}"
+        f" (oracle interpolation Z_i {e_zi_oracle:.2e})")
+    assert e_rep <= 1e-3 and e_ent <= 1e-3 and e_zi <= 1e-3
+    assert e_zi_oracle <= 1e-6
+    assert abs(t["Z"][0] - it.Z) <= 1e-5 * it.Z
+    # the gradient of 16 sampled rows whose P entries the oracle derives from
+    # its own conditional rows (each entry (p_j|i + p_i|j) / 2n)
+    got = prob.export()
+    n = g.n
+    Grows = rows[::16]
+    ptr, nbr, dist, p, beta, status = affinities.conditional_rows(g.indptr, g.indices, 40.0, seed=3,
+                                                                  rows=Grows)
+    fa = np.zeros((Grows.size, 2))
+    for r, i in enumerate(Grows):
+        cols = got["col"][got["rowptr"][i]:got["rowptr"][i + 1]].astype(np.int64)
+        sel = nbr[ptr[r]:ptr[r + 1]].astype(np.int64)
+        assert np.isin(sel, cols).all(), i
+        cp, cn, _, cpv, _, _ = affinities.conditional_rows(g.indptr, g.indices, 40.0, seed=3, rows=cols)
+        vals = np.zeros(cols.size)
+        for q, j in enumerate(cols):
+            back = cn[cp[q]:cp[q + 1]]
+            hit = np.nonzero(back == i)[0]
+            fwd = np.nonzero(sel == j)[0]
+            assert hit.size or fwd.size, (i, j)     # every stored entry is a selection
+            vals[q] = ((p[ptr[r] + fwd[0]] if fwd.size else 0.0) +
+                       (cpv[cp[q] + hit[0]] if hit.size else 0.0)) / (2.0 * n)
+        d = X64[i] - X64[cols]
+        w = 1.0 / (1.0 + (d ** 2).sum(1))
+        fa[r] = ((vals * w)[:, None] * d).sum(0)
+    k = np.arange(0, rows.size, 16)  # positions of Grows in rows
+    Gx = 4.0 * (fa - frep[k] / it.Z) + 1.2 / n * X64[Grows] - 0.01 / n ** 2 * fent[k]
+    e_G = rel_l2(t["G"][Grows], Gx)
+    say(f"   gradient of {Grows.size} rows: rel L2 {e_G:.2e}")
+    assert e_G <= 1e-3
 
 
 # --------------------------------------------------------------------- random 1e6
