@@ -61,6 +61,38 @@ def _cpu_worker(rows):
     return time.perf_counter() - t0
 
 
+def host_cpu():
+    """Model name and core counts of the host CPU (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    if model is None:
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"model": model, "cpus_visible": os.cpu_count(), "cpus_usable": usable}
+
+
+# worker processes of the oracle timings: every usable core, at most the host's
+# share per GPU of the machines this runs on (16)
+HOST_SHARE = 16
+
+
 def cpu_baseline(X: np.ndarray, budget_s: float = 12.0):
     """The FP64 oracle's exact O(n^2) pair sums on a bounded row sample, all worker
     processes in parallel; extrapolated to one full iteration (n(n-1) pairs)."""
@@ -69,7 +101,8 @@ def cpu_baseline(X: np.ndarray, budget_s: float = 12.0):
     global _CPU_X
     _CPU_X = X.astype(np.float64)
     n = X.shape[0]
-    cores = max(1, min(16, os.cpu_count() or 1))
+    host = host_cpu()
+    cores = max(1, min(HOST_SHARE, host["cpus_usable"]))
     t0 = time.perf_counter()
     gradient.pair_sums(_CPU_X, 0.05, rows=np.arange(4))
     per_row = (time.perf_counter() - t0) / 4
@@ -89,6 +122,7 @@ def cpu_baseline(X: np.ndarray, budget_s: float = 12.0):
         "value": 1.0 / iter_s,
         "unit": "iters/s",
         "cores": cores,
+        "cpu": host,
         "kind": "oracle",
         "sample": (f"exact FP64 pair sums (Z_i, F_rep, F_ent) of {sample.shape[0]} random rows of "
                    f"the n={n} layout in {cores} processes, {wall:.1f} s wall; one iteration "
@@ -219,6 +253,147 @@ def metrics_cpu_baseline(g, X, np_sample: int = 16, stress_sample: int = 2, sour
                       f"{stress_sample} sources (scipy BFS, one core) extrapolated to {sources}"}
 
 
+# --------------------------------------------------------------------------- descent legs
+def descent_leg(api, ctx, prob, X0d, iters, prm, sp, block=100, direct_rows=4096, seed=0):
+    """`iters` steps of (gradient + step) from X0d between two device
+    synchronisations, HIP events every `block` steps; then the status word of
+    the timed steps, the grid of every step (an untimed replay: reading it
+    synchronises), and the FP32 gradient at the final layout against the FP64
+    direct kernel on sampled rows (per graph for a batch)."""
+    import torch
+    n, Gn = prob.n, prob.num_graphs
+    X = X0d.clone()
+    upd, gains = torch.zeros_like(X), torch.ones_like(X)
+    G = torch.empty_like(X)
+    Z = torch.empty(Gn, dtype=torch.float64, device=X.device)
+    stream = torch.cuda.current_stream()
+    prob.grad(X, prm, G=G, Z=Z, stream=stream)   # the first evaluation sizes the workspace
+    torch.cuda.synchronize()
+    ctx.status()
+    nb = iters // block
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(nb + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs[0].record(stream)
+    for it in range(iters):
+        prob.grad(X, prm, G=G, Z=Z, stream=stream)
+        prob.step(X, upd, gains, G, it, sp, stream=stream)
+        if (it + 1) % block == 0:
+            evs[(it + 1) // block].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    status = ctx.status()
+    rates = [block / (evs[k].elapsed_time(evs[k + 1]) * 1e-3) for k in range(nb)]
+    # accuracy at the final layout, against the FP64 direct kernel on sampled rows;
+    # per graph the relative L2 error of G and, since G of a converged layout is
+    # a small difference of large terms, the error against the size of its terms
+    rng = np.random.default_rng(seed)
+    rows = np.sort(rng.choice(n, min(direct_rows, n), replace=False)).astype(np.int32)
+    prob.grad(X, prm, G=G, Z=Z)
+    Gd, Zd, Td = prob.grad_direct_f64(X.double(), prm, rows=rows, with_terms=True)
+    torch.cuda.synchronize()
+    rt = torch.as_tensor(rows, device=X.device).long()
+    Gs, Xs = G[rt].double(), X[rt].double()
+    goff = np.asarray(prob_offsets(prob))
+    gid = np.searchsorted(goff, rows, side="right") - 1
+    rel, rel_terms, conv = [], [], []
+    for g in np.unique(gid):
+        m = torch.as_tensor(gid == g, device=X.device)
+        ng = float(goff[g + 1] - goff[g])
+        size = (float(torch.linalg.norm(4 * prm.lambda_kl * Td[m, 0:2])) +
+                float(torch.linalg.norm(4 * prm.lambda_kl * Td[m, 2:4] / Zd[g])) +
+                float(torch.linalg.norm(prm.lambda_c / ng * Xs[m])) +
+                float(torch.linalg.norm(prm.lambda_r / ng ** 2 * Td[m, 4:6])))
+        den = float(torch.linalg.norm(Gd[m]))
+        dif = float(torch.linalg.norm(Gs[m] - Gd[m]))
+        if size > 0:
+            rel_terms.append(dif / size)
+            conv.append(den / size)
+        if den > 0 and den >= 1e-3 * size:
+            rel.append(dif / den)
+    acc = {"rows": int(rows.size), "graphs": len(rel_terms),
+           "rel_l2_max": max(rel) if rel else None,
+           "rel_l2_median": float(np.median(rel)) if rel else None,
+           "graphs_not_converged": len(rel),
+           "term_normalised_max": max(rel_terms),
+           "G_over_terms_min": min(conv),
+           "note": "rel_l2 over graphs with |G| >= 1e-3 of the sum of its terms' norms; "
+                   "term_normalised = |dG| / sum of the terms' norms, every graph"}
+    z_err = float(torch.max(torch.abs(Z - Zd) / Zd).item()) if Gn else 0.0
+    # the grid along the run (untimed replay from the same start)
+    Xr = X0d.clone()
+    upd.zero_()
+    gains.fill_(1.0)
+    ni_max, far_tot, ni_hist = [], [], {}
+    for it in range(iters):
+        prob.grad(Xr, prm, G=G, Z=Z, stream=stream)
+        prob.step(Xr, upd, gains, G, it, sp, stream=stream)
+        gi = prob.grid_info()
+        ni_max.append(int(gi["n_intervals"].max()))
+        far_tot.append(int(gi["far_points"].sum()))
+        for v in gi["n_intervals"].tolist():
+            ni_hist[v] = ni_hist.get(v, 0) + 1
+    return {
+        "iters": iters, "iters_per_s": iters / wall, "ms_per_step": wall / iters * 1e3,
+        "ns_per_vertex_iter": wall / iters / n * 1e9,
+        f"iters_per_s_per_{block}": rates,
+        "status_after_timed_steps": status,
+        "grid_capped_in_timed_steps": bool(status & 0x2),
+        "n_intervals_max": max(ni_max), "n_intervals_end": ni_max[-1],
+        "n_intervals_graph_steps": {str(k): v for k, v in sorted(ni_hist.items())},
+        "far_points_range": [min(far_tot), max(far_tot)],
+        "accuracy_vs_direct_f64": acc,
+        "Z_rel_vs_direct_max": z_err,
+    }
+
+
+def prob_offsets(prob):
+    return prob.graph_offsets if getattr(prob, "graph_offsets", None) is not None else [0, prob.n]
+
+
+def workload_legs(api, ctx, which, iters):
+    """Rates of the other configurations: SBM n = 2e4 and RGG n = 1e5 (one graph
+    each), the mixed batch of 256 graphs (one launch per stage for all of
+    them), each from N(0, 1e-4) with P built on the GPU."""
+    import torch
+    from synth import graphs
+    dev = torch.device("cuda", 0)
+    prm, sp = api.Params(), api.StepParams()
+    out = {}
+    specs = {
+        "sbm20k": ("SBM 20 blocks of 1000, p_in 0.01, p_out 5e-5, seed 1; perplexity 40", graphs.workload_sbm20k, 1),
+        "rgg100k": ("RGG n = 1e5, mean degree 8, seed 2; perplexity 40", graphs.workload_rgg100k, 2),
+        "mixed256": ("256 SBM / grid / tree graphs, n ~ U{500..50000}, seed 4; perplexity 40",
+                     graphs.workload_mixed256, 4),
+    }
+    for key in which:
+        desc, make, seed = specs[key]
+        t0 = time.perf_counter()
+        g = make()
+        goff = getattr(g, "graph_offsets", None)
+        n = g.indptr.shape[0] - 1
+        log(f"{key}: n={n} graph made in {time.perf_counter() - t0:.1f} s")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prob = api.Problem.build(ctx, g.indptr, g.indices, 40.0, seed=seed,
+                                 graph_offsets=None if goff is None else goff.astype(np.int64))
+        torch.cuda.synchronize()
+        build_ms = (time.perf_counter() - t0) * 1e3
+        prob.graph_offsets = None if goff is None else goff.astype(np.int64)
+        X0d = torch.tensor(graphs.initial_layout(n, seed), device=dev)
+        r = descent_leg(api, ctx, prob, X0d, iters, prm, sp, seed=seed)
+        r.update({"workload": desc, "n": n, "graphs": prob.num_graphs, "nnz_P": prob.nnz,
+                  "build_P_ms": build_ms})
+        log(f"{key}: {r['iters_per_s']:.1f} iters/s over {iters} steps, status {r['status_after_timed_steps']:#x}, "
+            f"n_int max {r['n_intervals_max']}, far points {r['far_points_range']}, "
+            f"G vs direct: {r['accuracy_vs_direct_f64']}")
+        out[key] = r
+        prob.free()
+        del prob, X0d
+        torch.cuda.empty_cache()
+    return out
+
+
 # --------------------------------------------------------------------------- per-kernel table
 FIXED_GRID_STDS = (6.0, 12.0)   # layouts N(0, std^2): 256 and 512 intervals at n = 1e6
 FIXED_GRID_EVALS = 20
@@ -327,6 +502,12 @@ def main():
                     help="timed runs from the initial layout (plain launches); value is their mean")
     ap.add_argument("--last", type=int, default=100,
                     help="the rate of the last LAST steps of every run is reported beside the whole-run rate")
+    ap.add_argument("--long-steps", type=int, default=1000,
+                    help="steps of the long run of the benchmark problem from the initial layout (0: skip)")
+    ap.add_argument("--legs", default="sbm20k,rgg100k,mixed256",
+                    help="comma-separated rate legs of the other configurations ('' to skip)")
+    ap.add_argument("--leg-iters", type=int, default=0,
+                    help="steps of every rate leg (0: 1000 for sbm20k and mixed256, 500 for rgg100k)")
     ap.add_argument("--graph-steps", type=int, default=0,
                     help="iterations per captured HIP graph in the timed region (0: plain launches; "
                          "graph replays measured slower than plain launches on ROCm 7, and event "
@@ -462,12 +643,14 @@ def main():
         wall = time.perf_counter() - t0
         st = ctx.stage_times()  # the events in the graphs hold their last replay
         ctx.set_timing(None)
+        status_timed = ctx.status()
         del g_early, g_late
         run_rates, last_rates = [args.steps / wall], []
     else:
         # every run starts from the initial layout: warmup steps untimed, then
         # exactly --steps steps between two device synchronisations
         run_rates, last_rates, attr_ms, attr_calls = [], [], 0.0, 0
+        status_timed = 0
         for r in range(max(1, args.runs)):
             if r > 0:
                 restart()
@@ -486,6 +669,7 @@ def main():
             ev_end.record(stream)
             torch.cuda.synchronize()
             w = time.perf_counter() - t0
+            status_timed |= ctx.status()  # raised during the warm-up and timed steps of this run
             a_ms, a_calls = ctx.stage_times()["attract_assemble"]
             ctx.set_timing(None)
             attr_ms += a_ms
@@ -499,7 +683,7 @@ def main():
     iters_per_s = args.steps / wall
     attr_ms, attr_calls = st["attract_assemble"]
     attr_avg_s = attr_ms / max(attr_calls, 1) * 1e-3
-    n, nnz = prob.n, prob.nnz
+    n, nnz, prob_k = prob.n, prob.nnz, prob.k
     attr_bytes = 8 * nnz + 8 * (n + 1) + 8 * n + 16 * n + 8 * n
     achieved = attr_bytes / attr_avg_s / 1e9
     log(f"timed ({'graphs of ' + str(K) if graphs_used else 'plain launches'}): {ms_per_step:.4f} ms/step, "
@@ -521,14 +705,15 @@ def main():
 
     # grid of every iteration of one run (replayed untimed: reading it synchronises)
     restart()
-    grid_ni, grid_span = [], []
+    grid_ni, grid_span, grid_far = [], [], []
     for it in range(args.warmup + args.steps):
         one(it)
         g_i = prob.grid_info()
         grid_ni.append(int(g_i["n_intervals"][0]))
         grid_span.append(float(g_i["n_intervals"][0]) * float(g_i["box_side"][0]))
-    log("grid per iteration (it span n_int M): " + "; ".join(
-        f"{i} {grid_span[i]:.2f} {grid_ni[i]} {6 * grid_ni[i]}" for i in range(len(grid_ni))))
+        grid_far.append(int(g_i["far_points"][0]))
+    log("grid per iteration (it span n_int M far): " + "; ".join(
+        f"{i} {grid_span[i]:.2f} {grid_ni[i]} {6 * grid_ni[i]} {grid_far[i]}" for i in range(len(grid_ni))))
     # quality metrics of the layout the run ended with (not part of the timed steps):
     # neighbourhood preservation of every vertex, stress over sampled sources
     met = None
@@ -677,8 +862,28 @@ def main():
             "L-tsNET vs FIt-tsNET": iters_per_s / variants["FIt-tsNET"]["iters_per_s"],
             "FIt-tsNET vs BH-tsNET": variants["FIt-tsNET"]["iters_per_s"] / variants["BH-tsNET"]["iters_per_s"]}
 
+    long_run = None
+    if args.long_steps > 0:
+        long_run = descent_leg(api, ctx, prob, X0d, args.long_steps, prm, sp, seed=3)
+        long_run["workload"] = "the benchmark problem, one run of --long-steps steps from the initial layout"
+        log(f"long run: {long_run['iters_per_s']:.1f} iters/s over {args.long_steps} steps "
+            f"(per 100: {', '.join(f'{v:.0f}' for v in long_run['iters_per_s_per_100'])}), status "
+            f"{long_run['status_after_timed_steps']:#x}, n_int max {long_run['n_intervals_max']}, far points "
+            f"{long_run['far_points_range']}, G vs direct {long_run['accuracy_vs_direct_f64']}")
+
     small = small_n_leg(api, ctx, args.small_iters, cpu=not args.no_cpu_baseline) \
         if args.small_iters > 0 else None
+
+    legs = None
+    which = [w for w in args.legs.split(",") if w]
+    if which:
+        prob.free()
+        del prob
+        torch.cuda.empty_cache()
+        legs = {}
+        for w in which:
+            iters = args.leg_iters or (500 if w == "rgg100k" else 1000)
+            legs.update(workload_legs(api, ctx, [w], iters))
 
     out = {
         "metric": METRIC,
@@ -696,7 +901,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "barabasi_albert_n1e6_m4_seed3",
-            "n": n, "edges": int(g.m), "perplexity": 40.0, "k": prob.k, "nnz_P": nnz,
+            "n": n, "edges": int(g.m), "perplexity": 40.0, "k": prob_k, "nnz_P": nnz,
             "init": "N(0,1e-4) seed 0", "interval_width": prm.interval_width,
             "min_intervals": prm.min_intervals, "max_intervals": prm.max_intervals,
             "n_intervals_end": int(gi["n_intervals"][0]), "span_end": span,
@@ -729,6 +934,11 @@ def main():
             "fft_length_M": "6 * n_intervals",
             "span_min": float(min(grid_span[args.warmup:])),
             "span_max": float(max(grid_span[args.warmup:])),
+            "span_is": "side of the region the grid covers (the core when far points are set apart)",
+            "far_points_min": int(min(grid_far[args.warmup:])),
+            "far_points_max": int(max(grid_far[args.warmup:])),
+            "status_after_timed_steps": status_timed,
+            "grid_capped_in_timed_steps": bool(status_timed & 0x2),
         },
         "build_P_ms": build_ms,
         "pmds": pm,
@@ -736,7 +946,9 @@ def main():
         "stages_ms": stages,
         "direct_f64": direct,
         "variants": variants,
+        "long_run": long_run,
         "small_n": small,
+        "workloads": legs,
     }
     print(json.dumps(out), flush=True)
 

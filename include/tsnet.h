@@ -380,7 +380,10 @@ int tsnet_cost(tsnet_ctx ctx, tsnet_P P, const float* X, const tsnet_params* prm
 
 /*
  * Exact all-pairs FP64 gradient (the O(n^2) tsNET evaluation over the same
- * sparse P), the comparison baseline. X, G [n][2] double.
+ * sparse P), the comparison baseline: Eq. (6) for the KL part with the
+ * normaliser Z of Sec. 2.1 summed over every pair, the entropy part of
+ * Eq. (8) pair by pair and the compression derivative, assembled as in
+ * tsnet_grad. X, G [n][2] double.
  *  rows: NULL for every vertex, else device int32 [nrows] vertex ids; G is
  *    then [nrows][2] and only those rows are evaluated (Z is still summed over
  *    all pairs of each graph).

@@ -1,7 +1,9 @@
 // Binning of points by interpolation box and the spread to the nodes.
 //
-// Binning: stable LSD radix sort (9-bit digits: two passes cover the 2^18
-// boxes of a 512 x 512 grid) of the global box id of every point. Tiles of 2048 points rank their digits in LDS with wave ballots, so
+// Binning: stable LSD radix sort (10-bit digits: two passes cover the
+// 2^18 + 1 boxes of a 512 x 512 grid and its far box) of the global box id
+// of every point. Tiles of 2048 points rank their digits in LDS with wave
+// ballots, so
 // no global atomics are needed and the order is deterministic (by box, then
 // by vertex id). Pass 0 computes the keys from X; the last pass also gathers
 // X into sorted order. box_off[b] is the first sorted slot of box b.

@@ -23,7 +23,7 @@ constexpr int kChunk = 2048;              // vertices per chunk of per-vertex ke
 constexpr int kMaxK = 1024;               // neighbours per vertex in tsnet_build_P
 constexpr double kSpanFloor = 1e-4;       // smallest grid span (degenerate layouts)
 constexpr int kBinTileH = 2048;           // points per tile of the binning radix sort
-constexpr int kBinDigitBits = 9;          // digit width of the binning radix sort
+constexpr int kBinDigitBits = 10;         // digit width of the binning radix sort
 constexpr int kRadixTile = 2048;          // elements per block tile of the LSD radix sort
 constexpr int kTileMaxRows = 4096;        // rows per row tile of the tiled attraction
 constexpr int kTileSlotBits = 12;         // bits of a row slot inside a tile

@@ -249,37 +249,101 @@ def test_random1m_tiled_attraction(api, ctx):
 
 
 # --------------------------------------------------------------------- mixed batch
-def test_mixed256_sampled_graphs(api, ctx):
+def _oracle_interp(args):
+    """The oracle's interpolated sums of one graph (runs in a worker process)."""
+    from oracle import interp as oi
+    X64, eps = args
+    it = oi.interp_terms(X64, eps)
+    return it.F_rep, it.F_ent, it.Z_i, it.grid.n_int, int(it.far.sum())
+
+
+def _oracle_graph_exact(args):
+    """One graph of the batch: its P from the oracle's conditional rows (global
+    ids, as the batch was built), then the exact gradient terms of sampled rows
+    and the exact Z (runs in a worker process)."""
+    from oracle import affinities as oa, gradient as og
+    indptr, indices, a, e, X64, rows = args
+    ng = e - a
+    ptr, nbr, dist, p, beta, status = oa.conditional_rows(indptr, indices, 40.0, seed=4,
+                                                          rows=np.arange(a, e))
+    rp, cl, vl = oa.symmetrize(ng, ptr, nbr.astype(np.int64) - a, p, status,
+                               np.array([0, ng], dtype=np.int64))
+    zi, frep, fent = og.pair_sums(X64, 0.05, rows=rows)
+    fa = og.attraction(X64, rp, cl, vl.astype(np.float32).astype(np.float64), rows=rows)
+    Z = og.normaliser(X64)
+    return rp, cl, vl, zi, frep, fent, fa, Z
+
+
+def _pool(k):
+    import multiprocessing as mp
+    import os
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return mp.get_context("spawn").Pool(max(1, min(k, 16, usable)))
+
+
+def test_mixed256_all_graphs(api, ctx):
+    """The 256-graph batch at the default settings, one launch per stage for all
+    graphs, on layouts of both classes (a dense bulk with far points in the
+    even graphs, N(0, 2^2) in the odd ones): every graph's F_rep, F_ent and Z_i
+    against the FP64 interpolation oracle, its grid and far points the
+    oracle's; the gradient of the 5 largest graphs against the exact oracle on
+    256 sampled rows each, with P from the oracle's conditional rows."""
     b = graphs.workload_mixed256()
     off = b.graph_offsets.astype(np.int64)
     sizes = np.diff(off)
-    say(f"[workload] mixed batch: {b.num_graphs} graphs, n={int(off[-1])}")
+    n = int(off[-1])
+    say(f"[workload] mixed batch: {b.num_graphs} graphs, n={n}")
     prob = api.Problem.build(ctx, b.indptr, b.indices, 40.0, seed=4, graph_offsets=off)
     got = prob.export()
-    X32 = graphs.initial_layout(int(off[-1]), 4, std=2.0)
-    prm = api.Params(max_intervals=128)
+    X32 = np.empty((n, 2), np.float32)
+    for g in range(b.num_graphs):
+        a, e = int(off[g]), int(off[g + 1])
+        X32[a:e] = (graphs.bulk_with_far_points(e - a, 40 + g, n_far=max(4, (e - a) // 500), r_min=5.0)
+                    if g % 2 == 0 else graphs.initial_layout(e - a, 40 + g, std=2.0))
+    prm = api.Params()
     t = _terms(prob, torch.tensor(X32, device="cuda"), prm)
-    order = np.argsort(sizes, kind="stable")
-    pick = list(order[:4]) + list(np.random.default_rng(4).choice(order[4:40], 2, replace=False))
-    for gid in pick:
-        a, e = int(off[gid]), int(off[gid + 1])
+    gi = prob.grid_info()
+    X64 = X32.astype(np.float64)
+    with _pool(16) as pool:
+        res = pool.map(_oracle_interp, [(X64[off[g]:off[g + 1]], 0.05) for g in range(b.num_graphs)])
+    worst = 0.0
+    for g, (frep, fent, zi, nint, nfar) in enumerate(res):
+        a, e = int(off[g]), int(off[g + 1])
+        assert int(gi["n_intervals"][g]) == nint, g
+        assert int(gi["far_points"][g]) == nfar, g
+        assert (nfar > 0) == (g % 2 == 0), g
+        err = max(rel_l2(t["F_rep"][a:e], frep), rel_l2(t["F_ent"][a:e], fent), rel_l2(t["Z_i"][a:e], zi))
+        worst = max(worst, err)
+        assert err <= 2e-5, (g, err)
+        assert abs(t["Z"][g] - zi.sum()) <= 1e-5 * zi.sum(), g
+    say(f"   every graph against the FP64 interpolation: worst term {worst:.2e}; far points "
+        f"{int(gi['far_points'].sum())} in {int((gi['far_points'] > 0).sum())} graphs, "
+        f"intervals {sorted(set(gi['n_intervals'].tolist()))}")
+    big = np.argsort(sizes, kind="stable")[-5:]
+    rng = np.random.default_rng(4)
+    jobs = []
+    for g in big:
+        a, e = int(off[g]), int(off[g + 1])
+        jobs.append((b.indptr, b.indices, a, e, X64[a:e], np.sort(rng.choice(e - a, 256, replace=False))))
+    with _pool(5) as pool:
+        ex = pool.map(_oracle_graph_exact, jobs)
+    for g, job, (rp, cl, vl, zi, frep, fent, fa, Z) in zip(big, jobs, ex):
+        a, e, rows = job[2], job[3], job[5]
         ng = e - a
-        ptr, nbr, dist, p, beta, status = affinities.conditional_rows(b.indptr, b.indices, 40.0, seed=4,
-                                                                      rows=np.arange(a, e))
-        rp, cl, vl = affinities.symmetrize(ng, ptr, nbr.astype(np.int64) - a, p, status,
-                                           np.array([0, ng], dtype=np.int64))
+        # P of the graph: support bit-exact, values within 4 ulp
         grp = got["rowptr"][a:e + 1] - got["rowptr"][a]
-        gcl = got["col"][got["rowptr"][a]:got["rowptr"][e]] - a
-        gvl = got["val"][got["rowptr"][a]:got["rowptr"][e]]
-        assert np.array_equal(grp, rp) and np.array_equal(gcl, cl), gid
-        assert _ulps(gvl, vl).max() <= 4, gid
-
-        class _P:
-            pass
-        Pg = _P()
-        Pg.rowptr, Pg.col, Pg.val = rp, cl, vl
-        ex = gradient.grad_terms(X32[a:e].astype(np.float64), Pg, CostParams())
-        eg = rel_l2(t["G"][a:e], ex.G)
-        say(f"   graph {gid} ({b.kinds[gid]}, n={ng}): gradient rel L2 {eg:.2e}")
-        assert eg <= 1e-3
-        assert abs(t["Z"][gid] - ex.Z[0]) <= 1e-4 * ex.Z[0]
+        assert np.array_equal(grp, rp)
+        assert np.array_equal(got["col"][got["rowptr"][a]:got["rowptr"][e]] - a, cl)
+        assert _ulps(got["val"][got["rowptr"][a]:got["rowptr"][e]], vl).max() <= 4
+        Xg = X64[a:e]
+        Gx = 4.0 * (fa - frep / Z) + 1.2 / ng * Xg[rows] - 0.01 / ng ** 2 * fent
+        eg = rel_l2(t["G"][a + rows], Gx)
+        e_terms = max(rel_l2(t["F_rep"][a + rows], frep), rel_l2(t["F_ent"][a + rows], fent),
+                      rel_l2(t["Z_i"][a + rows], zi))
+        say(f"   graph {g} ({b.kinds[g]}, n={ng}, far {int(gi['far_points'][g])}): gradient rel L2 {eg:.2e}, "
+            f"terms {e_terms:.2e}, Z {abs(t['Z'][g] - Z) / Z:.2e}")
+        assert eg <= 1e-3 and e_terms <= 1e-3
+        assert abs(t["Z"][g] - Z) <= 1e-4 * Z
