@@ -396,6 +396,27 @@ int tsnet_grad_direct_f64(tsnet_ctx ctx, tsnet_P P, const double* X, const tsnet
                           double* terms, void* stream);
 
 /*
+ * tsnet_grad_direct_f64 for callers that cannot allocate device memory: code
+ * being captured into a HIP graph, tight serving loops, harnesses that forbid
+ * allocation. Same arguments, results and kernels (bit-identical output);
+ * the per-row pair sums go to a file-scope device array of 2^21 doubles
+ * (16 MiB) that every GPU the library runs on holds until the process ends,
+ * instead of a buffer the problem allocates on first use. It calls no
+ * allocating routine and records no stage timing.
+ *  Limit: 5 * (n + nrows) <= 2^21 with rows, 5 * n <= 2^21 without (n at
+ *    most 419,430 for every row); larger calls fail with TSNET_EINVAL before
+ *    anything is enqueued.
+ *  All calls on one GPU share that GPU's array, which keeps the last call's
+ *  contents: calls that overlap on one GPU (other streams, other threads,
+ *  other contexts) race and must be ordered by the caller. Nothing in the
+ *  array needs to start at zero (every value is written before it is read
+ *  within a call).
+ */
+int tsnet_grad_direct_f64_static(tsnet_ctx ctx, tsnet_P P, const double* X,
+                                 const tsnet_params* prm, double* G, double* Z_out,
+                                 const int32_t* rows, int32_t nrows, double* terms, void* stream);
+
+/*
  * Grid of the most recent tsnet_grad / tsnet_cost on P, per graph (host
  * arrays [num_graphs], any may be NULL): intervals per axis, box side,
  * lower-left corner, number of far points set apart (far_trim). Synchronous.

@@ -34,6 +34,7 @@ EXPORTS = (
     "tsnet_grid_info", "tsnet_status", "tsnet_set_timing", "tsnet_stage_count",
     "tsnet_stage_name", "tsnet_stage_times", "tsnet_last_error",
     "tsnet_default_pmds_params", "tsnet_pmds", "tsnet_np", "tsnet_stress", "tsnet_run",
+    "tsnet_grad_direct_f64_static",
 )
 
 
@@ -114,6 +115,8 @@ _SIGS = {
     "tsnet_step": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _P(tsnet_step_params), _i32, _vp]),
     "tsnet_cost": (_i32, [_vp, _vp, _vp, _P(tsnet_params), _vp, _vp]),
     "tsnet_grad_direct_f64": (_i32, [_vp, _vp, _vp, _P(tsnet_params), _vp, _vp, _vp, _i32, _vp,
+                                     _vp]),
+    "tsnet_grad_direct_f64_static": (_i32, [_vp, _vp, _vp, _P(tsnet_params), _vp, _vp, _vp, _i32, _vp,
                                      _vp]),
     "tsnet_grid_info": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "tsnet_status": (_i32, [_vp, _P(ctypes.c_uint32)]),

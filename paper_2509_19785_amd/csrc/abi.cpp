@@ -494,6 +494,13 @@ int tsnet_ctx_create(tsnet_ctx* out, int device) {
     delete c;
     return fail(TSNET_EHIP, std::string("context set-up: ") + hipGetErrorString(e));
   }
+  // the allocation-free direct call's scratch on this device (device current)
+  if ((rc = static_scratch(device, &c->c.static_scratch))) {
+    dfree(c->c.twiddle);
+    dfree(c->c.status);
+    delete c;
+    return rc;
+  }
   *out = c;
   return TSNET_OK;
 }
@@ -823,7 +830,30 @@ int tsnet_grad_direct_f64(tsnet_ctx ctx, tsnet_P Pp, const double* X, const tsne
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   StageScope t(ctx->c, ST_DIRECT, s);
   TSNET_LAUNCH(launch_direct(P, reinterpret_cast<const double2*>(X), *prm,
-                             reinterpret_cast<double2*>(G), Z_out, rows, nrows, terms, s));
+                             reinterpret_cast<double2*>(G), Z_out, rows, nrows, terms,
+                             P.direct_part, s));
+  return TSNET_OK;
+}
+
+int tsnet_grad_direct_f64_static(tsnet_ctx ctx, tsnet_P Pp, const double* X,
+                                 const tsnet_params* prm, double* G, double* Z_out,
+                                 const int32_t* rows, int32_t nrows, double* terms, void* stream) {
+  int rc = check_call(ctx, Pp);
+  if (rc) return rc;
+  if (!prm || !std::isfinite(prm->eps_r) || !(prm->eps_r > 0))
+    return fail(TSNET_EINVAL, "bad params");
+  if (!X || !G) return fail(TSNET_EINVAL, "X and G must not be NULL");
+  Problem& P = Pp->p;
+  if (!rows) nrows = P.n;
+  if (nrows < 1) return fail(TSNET_EINVAL, "nrows must be >= 1");
+  const size_t need = ((size_t)(rows ? nrows : 0) + P.n) * 5;
+  if (need > kStaticScratchDoubles)
+    return fail(TSNET_EINVAL, "5 (n + nrows) exceeds the 2^21 doubles of the static scratch");
+  if (!ctx->c.static_scratch) return fail(TSNET_EHIP, "no static scratch on this device");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  TSNET_LAUNCH(launch_direct(P, reinterpret_cast<const double2*>(X), *prm,
+                             reinterpret_cast<double2*>(G), Z_out, rows, nrows, terms,
+                             ctx->c.static_scratch, s));
   return TSNET_OK;
 }
 

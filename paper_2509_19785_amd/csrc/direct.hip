@@ -9,6 +9,9 @@
 // refined by two Newton steps from the hardware estimate.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <string>
+
 #include "dev_util.h"
 #include "tsnet_internal.h"
 
@@ -202,11 +205,11 @@ __global__ __launch_bounds__(256) void k_direct_attr(
 }
 
 hipError_t launch_direct(Problem& P, const double2* X, const tsnet_params& prm, double2* G,
-                         double* Z_out, const int* rows, int nrows, double* terms, hipStream_t s) {
+                         double* Z_out, const int* rows, int nrows, double* terms, double* pairs,
+                         hipStream_t s) {
   const int per_block = 256 * kDirRows;
-  // pairs scratch holds [max(n, nrows)][5] doubles; sized by the caller
-  double* pairs = P.direct_part;
-  double* zrows = rows ? P.direct_part + (size_t)nrows * 5 : P.direct_part;
+  // pairs: [nrows][5] row sums, then (with rows) [n][5] for the Z pass; sized by the caller
+  double* zrows = rows ? pairs + (size_t)nrows * 5 : pairs;
   if (rows) {
     hipLaunchKernelGGL(k_direct_pairs, dim3((P.n + per_block - 1) / per_block), dim3(256), 0, s, X,
                        P.n, nullptr, P.n, P.goff_d, P.G, prm.eps_r, 1, zrows);
@@ -223,6 +226,38 @@ hipError_t launch_direct(Problem& P, const double2* X, const tsnet_params& prm, 
   hipLaunchKernelGGL(k_direct_attr, dim3(blocks), dim3(256), 0, s, X, P.n, P.rowptr, P.col, P.val, rows,
                      nrows, P.goff_d, P.G, P.ginfo, P.zg, pairs, dp, G, terms);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free entry point: the per-row pair sums live in a
+// file-scope device array of kStaticScratchDoubles doubles (16 MiB), one copy
+// per GPU for the life of the process. Host code never passes the array's
+// name to a kernel: its device address comes from hipGetSymbolAddress, once
+// per device with that device current, and is kept per device.
+__device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+int static_scratch(int device, double** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(TSNET_EINVAL, "device id out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = 0;
+    TSNET_HIP(hipGetDevice(&cur));
+    TSNET_HIP(hipSetDevice(device));
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    (void)hipSetDevice(cur);
+    if (e != hipSuccess || !ptr)
+      return fail(TSNET_EHIP, std::string("static scratch address: ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[device];
+  return TSNET_OK;
 }
 
 }  // namespace tsnet

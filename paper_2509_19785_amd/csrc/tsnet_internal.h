@@ -32,6 +32,7 @@ constexpr int kTileAutoMinN = 262144;     // automatic layout: tiled from this m
 constexpr int kTrimBins = 2048;           // bins per axis of the far-point rule
 constexpr int kTrimMinPoints = 64;        // points per far point allowed (t <= n / 64)
 constexpr int kMaxFarTrim = 1024;         // largest far_trim accepted
+constexpr size_t kStaticScratchDoubles = (size_t)1 << 21;  // scratch of the allocation-free direct call
 
 // Output channels of the convolution (charge index in comments):
 //  0 K2*1, 1 K2*x, 2 K2*y, 3 K1*1, 4 Ke*1, 5 Ke*x, 6 Ke*y, 7 Kln*1
@@ -92,6 +93,7 @@ enum Stage {
 struct Ctx {
   int device = 0;
   float2* twiddle = nullptr;          // e^{-2 pi i m / kMaxM}, m < kMaxM
+  double* static_scratch = nullptr;   // this device's scratch array of the allocation-free call
   unsigned* status = nullptr;         // device status word
   int lds_per_block = 65536;
   uint32_t timing = 0;                // bit s: time stage s
@@ -233,9 +235,14 @@ hipError_t radix_sort(unsigned* keys, unsigned* vals, unsigned* kt, unsigned* vt
 // FFT convolution (fft.hip)
 hipError_t launch_fft_conv(Problem& P, float eps, int with_ln, hipStream_t s);
 
-// direct FP64 baseline (direct.hip)
+// direct FP64 baseline (direct.hip); the pair sums go to `pairs`, which holds
+// (n + nrows) * 5 doubles with rows, n * 5 without
 hipError_t launch_direct(Problem& P, const double2* X, const tsnet_params& prm, double2* G,
-                         double* Z_out, const int* rows, int nrows, double* terms, hipStream_t s);
+                         double* Z_out, const int* rows, int nrows, double* terms, double* pairs,
+                         hipStream_t s);
+// device address of the allocation-free direct call's scratch array on `device`
+// (looked up once per device; synchronous)
+int static_scratch(int device, double** out);
 
 // Pivot MDS starting layout (pmds.hip). goff: host graph offsets [G+1].
 // Synchronous; X [n][2] on the device, pivots_out [G][pivots] device or NULL,
