@@ -28,8 +28,9 @@
 
 namespace tsnet {
 
-constexpr int kFarThreads = 256;
-constexpr int kFarBatch = 256;  // far points staged in LDS at a time (node role)
+constexpr int kFarThreads = 512;
+constexpr int kFarBatch = 512;  // far points staged in LDS at a time (node role)
+constexpr int kFarNodes = 4;    // nodes a thread loads ahead per step (far-point role)
 constexpr int kFarSums = 14;    // 8 node channels + 6 far-far direct sums
 
 struct FarArgs {
@@ -71,23 +72,37 @@ __global__ __launch_bounds__(kFarThreads) void k_far(FarArgs A) {
       float acc[kFarSums];
 #pragma unroll
       for (int k = 0; k < kFarSums; ++k) acc[k] = 0.f;
-      for (int a = tid; a < nodes; a += kFarThreads) {
-        const int ay = a / ng, ax = a - ay * ng;
-        const float dx = xo.x - (d.x0 + ((float)ax + 0.5f) * d.spacing);
-        const float dy = xo.y - (d.y0 + ((float)ay + 0.5f) * d.spacing);
-        const float r2 = dx * dx + dy * dy;
-        const float k1 = 1.0f / (1.0f + r2);
-        const float k2 = k1 * k1;
-        const float ke = 1.0f / (A.eps + r2);
-        const float w1 = w[a], wx = w[nodes + a], wy = w[2 * nodes + a];
-        acc[0] += k2 * w1;
-        acc[1] += k2 * wx;
-        acc[2] += k2 * wy;
-        acc[3] += k1 * w1;
-        acc[4] += ke * w1;
-        acc[5] += ke * wx;
-        acc[6] += ke * wy;
-        if (A.with_ln) acc[7] += logf(A.eps + r2) * w1;
+      // kFarNodes nodes per step, all their charges loaded before any is used
+      for (int a0 = tid; a0 < nodes; a0 += kFarNodes * kFarThreads) {
+        float w1[kFarNodes], wx[kFarNodes], wy[kFarNodes];
+#pragma unroll
+        for (int u = 0; u < kFarNodes; ++u) {
+          const int a = min(a0 + u * kFarThreads, nodes - 1);
+          w1[u] = w[a];
+          wx[u] = w[nodes + a];
+          wy[u] = w[2 * nodes + a];
+        }
+#pragma unroll
+        for (int u = 0; u < kFarNodes; ++u) {
+          const int a = a0 + u * kFarThreads;
+          if (a < nodes) {
+            const int ay = a / ng, ax = a - ay * ng;
+            const float dx = xo.x - (d.x0 + ((float)ax + 0.5f) * d.spacing);
+            const float dy = xo.y - (d.y0 + ((float)ay + 0.5f) * d.spacing);
+            const float r2 = dx * dx + dy * dy;
+            const float k1 = 1.0f / (1.0f + r2);
+            const float k2 = k1 * k1;
+            const float ke = 1.0f / (A.eps + r2);
+            acc[0] += k2 * w1[u];
+            acc[1] += k2 * wx[u];
+            acc[2] += k2 * wy[u];
+            acc[3] += k1 * w1[u];
+            acc[4] += ke * w1[u];
+            acc[5] += ke * wx[u];
+            acc[6] += ke * wy[u];
+            if (A.with_ln) acc[7] += logf(A.eps + r2) * w1[u];
+          }
+        }
       }
       for (int q = fs + tid; q < fe; q += kFarThreads) {
         if (q == p) continue;
