@@ -383,7 +383,7 @@ def workload_legs(api, ctx, which, iters):
         X0d = torch.tensor(graphs.initial_layout(n, seed), device=dev)
         r = descent_leg(api, ctx, prob, X0d, iters, prm, sp, seed=seed)
         r.update({"workload": desc, "n": n, "graphs": prob.num_graphs, "nnz_P": prob.nnz,
-                  "build_P_ms": build_ms})
+                  "build_P_ms": build_ms, "grid_workspace_bytes": prob.workspace_bytes()})
         log(f"{key}: {r['iters_per_s']:.1f} iters/s over {iters} steps, status {r['status_after_timed_steps']:#x}, "
             f"n_int max {r['n_intervals_max']}, far points {r['far_points_range']}, "
             f"G vs direct: {r['accuracy_vs_direct_f64']}")

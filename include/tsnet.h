@@ -60,6 +60,8 @@ extern "C" {
 #define TSNET_STATUS_ROW_LOW     0x4u  /* some row could not reach u from below      */
 #define TSNET_STATUS_ROW_HIGH    0x8u  /* some row could not reach u from above      */
 #define TSNET_STATUS_ROW_EMPTY   0x10u /* some vertex has no neighbour               */
+#define TSNET_STATUS_WORKSPACE   0x20u /* a batch's grids were planned down to fit the
+                                          evaluation workspace (with GRID_CAPPED)     */
 
 typedef struct tsnet_ctx_s* tsnet_ctx;   /* per-device state: twiddles, status, timers */
 typedef struct tsnet_P_s*   tsnet_P;     /* one problem: graph batch, P, workspace      */
@@ -86,9 +88,14 @@ typedef struct tsnet_P_s*   tsnet_P;     /* one problem: graph batch, P, workspa
  *    before the gather; its own sums run over the node charges), far points
  *    meet each other exactly. Otherwise the grid covers the bounding box.
  *  min_intervals >= 1, max_intervals a power of two in [min_intervals, 512].
- *  The evaluation workspace is sized for max_intervals boxes per axis in
- *  every graph of the problem (about 600 MB per graph at 512, 9.5 MB at 64),
- *  so batches of many graphs should lower it.
+ *  Evaluation workspace: a single graph holds grid buffers for a
+ *  max_intervals grid (about 600 MB at 512, 9.5 MB at 64). A batch's grid
+ *  buffers are pools with every graph at its own offset, sized by the first
+ *  evaluation (which waits once for its grid plan) at four times what its
+ *  grids need, at most max_intervals grids in every graph; when a later plan
+ *  needs more, the evaluation that finds the pools short halves its largest
+ *  grids until they fit (TSNET_STATUS_WORKSPACE and GRID_CAPPED) and the
+ *  pools grow before the next evaluation (except under stream capture).
  *  nodes_per_interval: interpolation points per box and axis; must be 3.
  *  attract_layout: TSNET_ATTRACT_*. The tiled layout is a second copy of P
  *    (8 bytes per nonzero) made on the first evaluation that needs it, or in
@@ -423,6 +430,15 @@ int tsnet_grad_direct_f64_static(tsnet_ctx ctx, tsnet_P P, const double* X,
  */
 int tsnet_grid_info(tsnet_P P, int32_t* n_intervals, float* box_side, float* x0, float* y0,
                     int32_t* far_points);
+
+/*
+ * Device bytes of P's grid workspace (host-side bookkeeping, no GPU call):
+ * the grid buffers (charges, spectra, products, potentials), the box offsets
+ * and the far-point bin counts. A single graph holds grid buffers for a
+ * max_intervals grid; a batch holds pools sized from its plans (four times
+ * the first evaluation's needs, at most max_intervals grids in every graph).
+ */
+int tsnet_workspace_bytes(tsnet_P P, size_t* bytes_host);
 
 /* Synchronous: OR of the TSNET_STATUS_* bits raised since the last call; clears them. */
 int tsnet_status(tsnet_ctx ctx, uint32_t* flags_host);

@@ -25,6 +25,7 @@ TSNET_STATUS_GRID_CAPPED = 0x2
 TSNET_STATUS_ROW_LOW = 0x4
 TSNET_STATUS_ROW_HIGH = 0x8
 TSNET_STATUS_ROW_EMPTY = 0x10
+TSNET_STATUS_WORKSPACE = 0x20
 
 # every entry point declared in include/tsnet.h
 EXPORTS = (
@@ -34,7 +35,7 @@ EXPORTS = (
     "tsnet_grid_info", "tsnet_status", "tsnet_set_timing", "tsnet_stage_count",
     "tsnet_stage_name", "tsnet_stage_times", "tsnet_last_error",
     "tsnet_default_pmds_params", "tsnet_pmds", "tsnet_np", "tsnet_stress", "tsnet_run",
-    "tsnet_grad_direct_f64_static",
+    "tsnet_grad_direct_f64_static", "tsnet_workspace_bytes",
 )
 
 
@@ -119,6 +120,7 @@ _SIGS = {
     "tsnet_grad_direct_f64_static": (_i32, [_vp, _vp, _vp, _P(tsnet_params), _vp, _vp, _vp, _i32, _vp,
                                      _vp]),
     "tsnet_grid_info": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "tsnet_workspace_bytes": (_i32, [_vp, _P(ctypes.c_size_t)]),
     "tsnet_status": (_i32, [_vp, _P(ctypes.c_uint32)]),
     "tsnet_set_timing": (_i32, [_vp, ctypes.c_uint32]),
     "tsnet_stage_count": (_i32, []),

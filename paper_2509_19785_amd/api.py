@@ -231,6 +231,11 @@ class Problem:
                                   y0.ctypes.data, far.ctypes.data))
         return {"n_intervals": ni, "box_side": h, "x0": x0, "y0": y0, "far_points": far}
 
+    def workspace_bytes(self) -> int:
+        v = ctypes.c_size_t()
+        check(lib.tsnet_workspace_bytes(self.handle, ctypes.byref(v)))
+        return v.value
+
     # ------------------------------------------------------------ evaluation
     def grad(self, X: torch.Tensor, params: Params = Params(), G=None, Z=None, stream=None):
         n = self.n

@@ -102,9 +102,7 @@ static int collect_times(Ctx& c) {
 }
 
 // ---------------------------------------------------------------- problems
-static void free_grid(Problem& P) {
-  dfree(P.box_off);
-  dfree(P.trim_hist);
+static void free_pools(Problem& P) {
   dfree(P.charges);
   dfree(P.qspec);
   dfree(P.qspec_t);
@@ -113,6 +111,34 @@ static void free_grid(Problem& P) {
   dfree(P.ospec);
   dfree(P.ospec_t);
   dfree(P.pot);
+  for (int k = 0; k < POOL_KINDS; ++k) P.pool_cap[k] = 0;
+}
+
+// Pools of the grid buffers with `cap[k]` elements of each kind.
+static int alloc_pools(Problem& P, const size_t* cap) {
+  int rc;
+  if ((rc = dmalloc(&P.charges, cap[POOL_C], "charges")) ||
+      (rc = dmalloc(&P.qspec, cap[POOL_Q], "qspec")) ||
+      (rc = dmalloc(&P.qspec_t, cap[POOL_Q], "qspec")) ||
+      (rc = dmalloc(&P.kspec, cap[POOL_K], "kspec")) ||
+      (rc = dmalloc(&P.kspec_t, cap[POOL_K], "kspec")) ||
+      (rc = dmalloc(&P.ospec, cap[POOL_O], "ospec")) ||
+      (rc = dmalloc(&P.ospec_t, cap[POOL_O], "ospec")) ||
+      (rc = dmalloc(&P.pot, cap[POOL_P], "pot"))) {
+    free_pools(P);
+    return rc;
+  }
+  for (int k = 0; k < POOL_KINDS; ++k) P.pool_cap[k] = cap[k];
+  return TSNET_OK;
+}
+
+static void free_grid(Problem& P) {
+  dfree(P.box_off);
+  dfree(P.trim_hist);
+  free_pools(P);
+  if (P.need_host) (void)hipHostFree(P.need_host);
+  P.need_host = nullptr;
+  P.need_dev = nullptr;
   P.cap = 0;
 }
 
@@ -251,33 +277,42 @@ static int init_problem(Ctx& c, Problem& P, int n, const int32_t* goff_host, int
   return TSNET_OK;
 }
 
-// Grid buffers sized for `cap` boxes per axis in every graph.
+// Box offsets and far-point counts sized for `cap` boxes per axis in every
+// graph; the grid buffers of a single graph sized for a cap x cap grid. A
+// batch's grid buffers are pools sized from its plans (ensure_pools).
 static int ensure_grid(Problem& P, int cap) {
   if (P.cap >= cap) return TSNET_OK;
   TSNET_HIP(hipDeviceSynchronize());
   free_grid(P);
-  const size_t ng = (size_t)kNodes * cap, M = 2 * ng, Mh = M / 2 + 1;
-  P.stride_charges = 3 * ng * ng;
-  P.stride_qspec = 3 * ng * Mh;
-  P.stride_kspec = 4 * Mh * Mh;
-  P.stride_ospec = 8 * ng * Mh;
-  P.stride_pot = ng * ng * kPotCh;
   // every graph: cap^2 core boxes at most, then its far box
   const size_t boxes = (size_t)P.G * ((size_t)cap * cap + 1);
   if (boxes >= (size_t)1 << 30) return fail(TSNET_EINVAL, "too many interpolation boxes in batch");
   int rc;
   if ((rc = dmalloc(&P.box_off, boxes + 1, "box_off")) ||
-      (rc = dmalloc(&P.trim_hist, (size_t)P.G * 2 * kTrimBins, "trim_hist")) ||
-      (rc = dmalloc(&P.charges, P.stride_charges * P.G, "charges")) ||
-      (rc = dmalloc(&P.qspec, P.stride_qspec * P.G, "qspec")) ||
-      (rc = dmalloc(&P.qspec_t, P.stride_qspec * P.G, "qspec")) ||
-      (rc = dmalloc(&P.kspec, P.stride_kspec * P.G, "kspec")) ||
-      (rc = dmalloc(&P.kspec_t, P.stride_kspec * P.G, "kspec")) ||
-      (rc = dmalloc(&P.ospec, P.stride_ospec * P.G, "ospec")) ||
-      (rc = dmalloc(&P.ospec_t, P.stride_ospec * P.G, "ospec")) ||
-      (rc = dmalloc(&P.pot, P.stride_pot * P.G, "pot"))) {
+      (rc = dmalloc(&P.trim_hist, (size_t)P.G * 2 * kTrimBins, "trim_hist"))) {
     free_grid(P);
     return rc;
+  }
+  void* h = nullptr;
+  if (hipHostMalloc(&h, sizeof(size_t) * POOL_KINDS, hipHostMallocMapped) != hipSuccess || !h) {
+    free_grid(P);
+    return fail(TSNET_ENOMEM, "pinned host allocation failed (pool needs)");
+  }
+  P.need_host = static_cast<size_t*>(h);
+  std::memset(P.need_host, 0, sizeof(size_t) * POOL_KINDS);
+  void* hd = nullptr;
+  if (hipHostGetDevicePointer(&hd, h, 0) != hipSuccess || !hd) {
+    free_grid(P);
+    return fail(TSNET_EHIP, "no device address for the pool needs");
+  }
+  P.need_dev = static_cast<size_t*>(hd);
+  if (P.G == 1) {  // one graph: its pools hold the largest grid it may plan
+    size_t c[POOL_KINDS];
+    for (int k = 0; k < POOL_KINDS; ++k) c[k] = pool_elems(k, cap);
+    if ((rc = alloc_pools(P, c))) {
+      free_grid(P);
+      return rc;
+    }
   }
   TSNET_HIP(hipMemset(P.trim_hist, 0, sizeof(int) * (size_t)P.G * 2 * kTrimBins));
   P.cap = cap;
@@ -338,17 +373,68 @@ static int check_call(tsnet_ctx ctx, tsnet_P P) {
     if (e_ != hipSuccess) return fail(TSNET_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// Pools of a batch's grid buffers. The first evaluation plans the grids of its
+// layout once without a limit, waits for the plan and sizes every pool at
+// four times what it needs (at most the size of max_intervals grids in every
+// graph). Later evaluations read the needs the last finished plan left in
+// mapped host memory (no wait) and grow the pools first when they fell
+// short; the plan of an evaluation that finds them short halves its largest
+// grids until they fit and raises TSNET_STATUS_WORKSPACE. Under stream
+// capture nothing is waited for or allocated.
+static int ensure_pools(Problem& P, const float2* X, const PlanParams& pp, bool may_trim,
+                        hipStream_t s) {
+  const bool have = P.pool_cap[0] > 0;
+  bool grow = !have;
+  if (have) {
+    const volatile size_t* nh = P.need_host;
+    for (int k = 0; k < POOL_KINDS; ++k) grow |= nh[k] > P.pool_cap[k];
+  }
+  if (!grow) return TSNET_OK;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  TSNET_HIP(hipStreamIsCapturing(s, &cs));
+  if (cs != hipStreamCaptureStatusNone) {
+    if (!have)
+      return fail(TSNET_EINVAL, "the first evaluation of a batch sizes its workspace and "
+                                "cannot run under stream capture");
+    return TSNET_OK;  // the plan fits the grids into the pools and flags it
+  }
+  if (!have) {
+    PlanParams p0 = pp;
+    for (int k = 0; k < POOL_KINDS; ++k) p0.cap[k] = SIZE_MAX;
+    TSNET_LAUNCH(launch_bbox_plan(P, X, p0, s));
+    TSNET_LAUNCH(launch_trim_plan(P, X, p0, may_trim, s));
+  }
+  TSNET_HIP(hipStreamSynchronize(s));
+  size_t cap[POOL_KINDS];
+  for (int k = 0; k < POOL_KINDS; ++k) {
+    const size_t full = pool_elems(k, P.cap) * (size_t)P.G;
+    const size_t want = 4 * P.need_host[k];
+    cap[k] = want < full ? want : full;
+    if (cap[k] < P.need_host[k]) cap[k] = P.need_host[k];
+  }
+  TSNET_HIP(hipDeviceSynchronize());
+  free_pools(P);
+  return alloc_pools(P, cap);
+}
+
 // The interpolation pipeline shared by grad and cost: grid, sort, spread, FFT, gather.
 static int run_interp(Problem& P, const float2* X, const tsnet_params& prm, int with_ln,
                       int with_zi, double* Z_out, hipStream_t s) {
   Ctx& c = *P.ctx;
   int rc = ensure_grid(P, prm.max_intervals);
   if (rc) return rc;
-  PlanParams pp{prm.interval_width, prm.min_intervals, prm.max_intervals, prm.far_trim};
+  PlanParams pp{};
+  pp.h_target = prm.interval_width;
+  pp.min_int = prm.min_intervals;
+  pp.max_int = prm.max_intervals;
+  pp.far_trim = prm.far_trim;
+  pp.need = P.need_dev;
   // far points need a graph of kTrimMinPoints vertices or more
   bool may_trim = false;
   for (const GraphInfo& g : P.ginfo_h) may_trim |= g.n >= kTrimMinPoints;
   may_trim = may_trim && prm.far_trim > 0;
+  if (P.G > 1 && (rc = ensure_pools(P, X, pp, may_trim, s))) return rc;
+  for (int k = 0; k < POOL_KINDS; ++k) pp.cap[k] = P.pool_cap[k];
   {
     StageScope t(c, ST_BBOX, s);
     TSNET_LAUNCH(launch_bbox_plan(P, X, pp, s));
@@ -878,6 +964,21 @@ int tsnet_grid_info(tsnet_P Pp, int32_t* n_intervals, float* box_side, float* x0
       far_points[g] = fo[1] - fo[0];
     }
   }
+  return TSNET_OK;
+}
+
+int tsnet_workspace_bytes(tsnet_P Pp, size_t* bytes_host) {
+  if (!Pp || !bytes_host) return fail(TSNET_EINVAL, "NULL argument");
+  const Problem& P = Pp->p;
+  const size_t per[POOL_KINDS] = {sizeof(float), 2 * sizeof(float2), 2 * sizeof(float),
+                                  2 * sizeof(float2), sizeof(float)};  // q, k, o: two arrays each
+  size_t b = 0;
+  for (int k = 0; k < POOL_KINDS; ++k) b += P.pool_cap[k] * per[k];
+  if (P.cap > 0) {
+    b += sizeof(int) * ((size_t)P.G * ((size_t)P.cap * P.cap + 1) + 1);  // box offsets
+    b += sizeof(int) * (size_t)P.G * 2 * kTrimBins;                     // far-point bin counts
+  }
+  *bytes_host = b;
   return TSNET_OK;
 }
 

@@ -164,7 +164,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const int* __restrict__ kin
 __global__ __launch_bounds__(256) void k_box_bounds(const int* __restrict__ skeys, int n,
                                                     const int* __restrict__ btotal, int* box_off,
                                                     const GridDesc* __restrict__ desc, int G,
-                                                    float* charges, size_t stride) {
+                                                    float* charges) {
   const int B = *btotal;
   const int t0 = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
   for (int b = t0; b <= B; b += nt) {
@@ -177,9 +177,8 @@ __global__ __launch_bounds__(256) void k_box_bounds(const int* __restrict__ skey
   }
   for (int g = 0; g < G; ++g) {
     const size_t len = (size_t)3 * desc[g].ng * desc[g].ng;  // floats of the graph's 3 grids
-    float* base = charges + (size_t)g * stride;
-    // stride is a multiple of 4 floats whenever the grid cap is 2 or more
-    const size_t len4 = (stride % 4 == 0) ? len / 4 : 0;
+    float* base = charges + desc[g].off_c;  // 256-byte aligned
+    const size_t len4 = len / 4;
     float4* b4 = reinterpret_cast<float4*>(base);
     for (size_t k = t0; k < len4; k += nt) b4[k] = make_float4(0.f, 0.f, 0.f, 0.f);
     for (size_t k = 4 * len4 + t0; k < len; k += nt) base[k] = 0.f;
@@ -226,7 +225,7 @@ hipError_t launch_bin(Problem& P, const float2* X, hipStream_t s) {
   if (bb > 4096) bb = 4096;
   if (bb < 1024) bb = 1024;  // enough threads for the grid clearing
   hipLaunchKernelGGL(k_box_bounds, dim3(bb), dim3(256), 0, s, P.skeys, n, P.btotal, P.box_off,
-                     P.desc, P.G, P.charges, P.stride_charges);
+                     P.desc, P.G, P.charges);
   return hipGetLastError();
 }
 
@@ -324,10 +323,10 @@ __device__ __forceinline__ void add_points(const float2* __restrict__ Xs, const 
 // the tail partial (a segment that is not a whole box touches an end of the
 // range).
 __device__ __forceinline__ void emit(const int* __restrict__ box_off, const BoxAt& bx, int key,
-                                     int a, int b, int s, int r, float* charges, size_t stride,
+                                     int a, int b, int s, int r, float* charges,
                                      float* head_val, float* tail_val, const float (&v)[kVals]) {
   if (box_off[key] == a && box_off[key + 1] == b) {
-    node_store(charges + (size_t)bx.g * stride, bx.d.ng, bx.bx, bx.by, v);
+    node_store(charges + bx.d.off_c, bx.d.ng, bx.bx, bx.by, v);
   } else {
     float* dst = (s == 0 ? head_val : tail_val) + (size_t)r * kVals;
 #pragma unroll
@@ -344,7 +343,7 @@ __device__ __forceinline__ void emit(const int* __restrict__ box_off, const BoxA
 __global__ __launch_bounds__(kRangeWaves * kWave) void k_spread_ranges(
     const float2* __restrict__ Xs, const int* __restrict__ skeys, int n,
     const int* __restrict__ box_off, const GridDesc* __restrict__ desc, int G, float* charges,
-    size_t stride, int* head_box, int* tail_box, float* head_val, float* tail_val, int range) {
+    int* head_box, int* tail_box, float* head_val, float* tail_val, int range) {
   __shared__ int seg_all[kRangeWaves][kRange + 1];
   int* seg = seg_all[wave_id()];
   const int lane = lane_id();
@@ -394,7 +393,7 @@ __global__ __launch_bounds__(kRangeWaves * kWave) void k_spread_ranges(
 #pragma unroll
           for (int q = 0; q < kVals; ++q) acc[q] = 0.f;
           add_points(Xs, bx, a, b, 1, acc);
-          emit(box_off, bx, key, a, b, s, r, charges, stride, head_val, tail_val, acc);
+          emit(box_off, bx, key, a, b, s, r, charges, head_val, tail_val, acc);
         }
       }
       u64 todo = __ballot(mine && b - a >= kLongSeg);
@@ -412,7 +411,7 @@ __global__ __launch_bounds__(kRangeWaves * kWave) void k_spread_ranges(
 #pragma unroll
         for (int q = 0; q < kVals; ++q) acc[q] = wave_sum_to_last(acc[q]);
         if (lane == kWave - 1)
-          emit(box_off, bx, key, la, lb, s0 + src, r, charges, stride, head_val, tail_val, acc);
+          emit(box_off, bx, key, la, lb, s0 + src, r, charges, head_val, tail_val, acc);
       }
     }
   }
@@ -433,7 +432,7 @@ __device__ __forceinline__ const float* partial_of(int r, int b, const int* head
 // sums in FP64 in range order, joined by a DPP reduction in a fixed order).
 __device__ __forceinline__ void spread_dense_box(int b, const int* __restrict__ box_off,
                                                  const GridDesc* __restrict__ desc, int G,
-                                                 float* charges, size_t stride,
+                                                 float* charges,
                                                  const int* __restrict__ head_box,
                                                  const float* __restrict__ head_val,
                                                  const float* __restrict__ tail_val, int range) {
@@ -452,13 +451,13 @@ __device__ __forceinline__ void spread_dense_box(int b, const int* __restrict__ 
   for (int q = 0; q < kVals; ++q) tot[q] = wave_sum_to_last((float)acc[q]);
   if (lane == kWave - 1) {
     const BoxAt bx = box_at(desc, G, b);
-    node_store(charges + (size_t)bx.g * stride, bx.d.ng, bx.bx, bx.by, tot);
+    node_store(charges + bx.d.off_c, bx.d.ng, bx.bx, bx.by, tot);
   }
 }
 
 __global__ __launch_bounds__(256) void k_spread_boxes(
     const int* __restrict__ box_off, const int* __restrict__ btotal,
-    const GridDesc* __restrict__ desc, int G, float* charges, size_t stride,
+    const GridDesc* __restrict__ desc, int G, float* charges,
     const int* __restrict__ head_box, const float* __restrict__ head_val,
     const float* __restrict__ tail_val, int range) {
   const int B = *btotal;
@@ -488,7 +487,7 @@ __global__ __launch_bounds__(256) void k_spread_boxes(
         for (int q = 0; q < kVals; ++q) acc[q] += (double)src[q];
       }
       const BoxAt bx = box_at(desc, G, b);
-      node_store(charges + (size_t)bx.g * stride, bx.d.ng, bx.bx, bx.by, acc);
+      node_store(charges + bx.d.off_c, bx.d.ng, bx.bx, bx.by, acc);
     }
   }
   // dense boxes (clustered points) are dealt to waves round-robin, one wave
@@ -507,7 +506,7 @@ __global__ __launch_bounds__(256) void k_spread_boxes(
       const int src_lane = __ffsll((long long)todo) - 1;
       todo &= todo - 1;
       const int b = base + src_lane * nwaves;
-      spread_dense_box(b, box_off, desc, G, charges, stride, head_box, head_val, tail_val, range);
+      spread_dense_box(b, box_off, desc, G, charges, head_box, head_val, tail_val, range);
     }
   }
 }
@@ -518,12 +517,12 @@ hipError_t launch_spread(Problem& P, const float2* X, hipStream_t s) {
   int blocks = (nranges + kRangeWaves - 1) / kRangeWaves;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_spread_ranges, dim3(blocks), dim3(kRangeWaves * kWave), 0, s, P.xs, P.skeys,
-                     P.n, P.box_off, P.desc, P.G, P.charges, P.stride_charges, P.head_box,
+                     P.n, P.box_off, P.desc, P.G, P.charges, P.head_box,
                      P.tail_box, P.head_val, P.tail_val, P.spread_range);
   int bblocks = (int)(((int64_t)P.G * ((int64_t)P.cap * P.cap + 1) + 255) / 256);
   if (bblocks > 8192) bblocks = 8192;
   hipLaunchKernelGGL(k_spread_boxes, dim3(bblocks), dim3(256), 0, s, P.box_off, P.btotal, P.desc,
-                     P.G, P.charges, P.stride_charges, P.head_box, P.head_val, P.tail_val,
+                     P.G, P.charges, P.head_box, P.head_val, P.tail_val,
                      P.spread_range);
   return hipGetLastError();
 }

@@ -39,9 +39,7 @@ struct FarArgs {
   const float2* xs;
   const int* perm;
   const float* charges;
-  size_t s_charges;
   float* pot;
-  size_t s_pot;
   float4* rep_ent;
   float* slot_z;
   float* slot_ln;
@@ -66,7 +64,7 @@ __global__ __launch_bounds__(kFarThreads) void k_far(FarArgs A) {
   const int tid = threadIdx.x;
   if ((int)blockIdx.x < A.nbx) {
     // ---- far points' own sums
-    const float* w = A.charges + (size_t)g * A.s_charges;  // [3][ng][ng]
+    const float* w = A.charges + d.off_c;  // [3][ng][ng]
     for (int p = fs + blockIdx.x; p < fe; p += A.nbx) {
       const float2 xo = A.xs[p];
       float acc[kFarSums];
@@ -148,7 +146,7 @@ __global__ __launch_bounds__(kFarThreads) void k_far(FarArgs A) {
   }
   // ---- far charges at the nodes
   const int j = blockIdx.x - A.nbx;
-  float2* pl = reinterpret_cast<float2*>(A.pot + (size_t)g * A.s_pot);  // 4 planes of ng^2
+  float2* pl = reinterpret_cast<float2*>(A.pot + d.off_p);  // 4 planes of ng^2
   const int sweep = A.nbx * kFarThreads;
   for (int base = j * kFarThreads; base < nodes; base += sweep) {  // uniform over the block
     const int a = base + tid;
@@ -210,9 +208,7 @@ hipError_t launch_far(Problem& P, int far_trim, float eps, int with_ln, hipStrea
   A.xs = P.xs;
   A.perm = P.perm;
   A.charges = P.charges;
-  A.s_charges = P.stride_charges;
   A.pot = P.pot;
-  A.s_pot = P.stride_pot;
   A.rep_ent = P.rep_ent;
   A.slot_z = P.slot_z;
   A.slot_ln = P.slot_ln;

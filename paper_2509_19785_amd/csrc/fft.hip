@@ -196,19 +196,15 @@ __device__ __forceinline__ int fft_pack(int M, int jobs) {
 struct FftArgs {
   const GridDesc* desc;
   const float2* tw;
+  // pools; every graph's part starts at its GridDesc offsets
   const float* charges;
-  size_t s_charges;
   float2* qr;   // [3][ng][Mh]
   float2* qt;   // [3][Mh][ng]
-  size_t s_q;
   float* kr;    // [4][Mh][Mh]
   float* kt;    // [4][Mh][Mh] transposed
-  size_t s_k;
   float2* ot;   // [8][Mh][ng]
   float2* orr;  // [8][ng][Mh]
-  size_t s_o;
   float* pot;
-  size_t s_pot;
   float eps;
   int with_ln;
 };
@@ -227,9 +223,9 @@ __global__ __launch_bounds__(kFftThreads, 4) void k_fft_rows_fwd(FftArgs A) {
   load_twiddles(twl, A.tw, M);
   const int nseq = 2 * ng + 2 * Mh;
   const int S = fft_pack(M, nseq);  // sequences per block iteration
-  const float* ch = A.charges + (size_t)g * A.s_charges;
-  float2* qs = A.qr + (size_t)g * A.s_q;
-  float* ks = A.kr + (size_t)g * A.s_k;
+  const float* ch = A.charges + d.off_c;
+  float2* qs = A.qr + d.off_q;
+  float* ks = A.kr + d.off_k;
   const float sp = d.spacing;
   for (int s0 = blockIdx.x * S; s0 < nseq; s0 += gridDim.x * S) {
     const int ns = nseq - s0 < S ? nseq - s0 : S;
@@ -351,15 +347,15 @@ __global__ __launch_bounds__(256) void k_fft_transpose(FftArgs A, int which) {
   if (which == 0) {
     const int half = gridDim.x / 2;
     if ((int)blockIdx.x < half) {
-      transpose_tiles<float2>(A.qr + (size_t)g * A.s_q, A.qt + (size_t)g * A.s_q, ng, Mh, 3, tc,
+      transpose_tiles<float2>(A.qr + d.off_q, A.qt + d.off_q, ng, Mh, 3, tc,
                               blockIdx.x, half);
     } else {
       float (*tf)[33] = reinterpret_cast<float (*)[33]>(&tc[0][0]);
-      transpose_tiles<float>(A.kr + (size_t)g * A.s_k, A.kt + (size_t)g * A.s_k, Mh, Mh, 4, tf,
+      transpose_tiles<float>(A.kr + d.off_k, A.kt + d.off_k, Mh, Mh, 4, tf,
                              blockIdx.x - half, gridDim.x - half);
     }
   } else {
-    transpose_tiles<float2>(A.ot + (size_t)g * A.s_o, A.orr + (size_t)g * A.s_o, Mh, ng,
+    transpose_tiles<float2>(A.ot + d.off_o, A.orr + d.off_o, Mh, ng,
                             A.with_ln ? 8 : 7, tc, blockIdx.x, gridDim.x);
   }
 }
@@ -374,9 +370,9 @@ __global__ __launch_bounds__(kFftThreads, 3) void k_fft_cols(FftArgs A) {
   float2* B0 = lds;
   float2* twl = lds + kFftBuf;  // half twiddle table
   load_twiddles(twl, A.tw, M);
-  const float2* qt = A.qt + (size_t)g * A.s_q;
-  const float* kt = A.kt + (size_t)g * A.s_k;
-  float2* ot = A.ot + (size_t)g * A.s_o;
+  const float2* qt = A.qt + d.off_q;
+  const float* kt = A.kt + d.off_k;
+  float2* ot = A.ot + d.off_o;
   const int nout0 = A.with_ln ? 4 : 3;
   for (int c0 = blockIdx.x * S; c0 < Mh; c0 += gridDim.x * S) {
     const int ncc = Mh - c0 < S ? Mh - c0 : S;
@@ -484,8 +480,8 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_inv(FftArgs A) {
   load_twiddles(twl, A.tw, M);
   const int jobs = ng * 4;
   const int S = fft_pack(M, jobs);
-  const float2* orr = A.orr + (size_t)g * A.s_o;
-  float* pg = A.pot + (size_t)g * A.s_pot;
+  const float2* orr = A.orr + d.off_o;
+  float* pg = A.pot + d.off_p;
   const float scale = 1.0f / ((float)M * (float)M);
   for (int j0 = blockIdx.x * S; j0 < jobs; j0 += gridDim.x * S) {
     const int nj = jobs - j0 < S ? jobs - j0 : S;
@@ -537,18 +533,13 @@ hipError_t launch_fft_conv(Problem& P, float eps, int with_ln, hipStream_t s) {
   A.desc = P.desc;
   A.tw = P.ctx->twiddle;
   A.charges = P.charges;
-  A.s_charges = P.stride_charges;
   A.qr = P.qspec;
   A.qt = P.qspec_t;
-  A.s_q = P.stride_qspec;
   A.kr = P.kspec;
   A.kt = P.kspec_t;
-  A.s_k = P.stride_kspec;
   A.ot = P.ospec_t;
   A.orr = P.ospec;
-  A.s_o = P.stride_ospec;
   A.pot = P.pot;
-  A.s_pot = P.stride_pot;
   A.eps = eps;
   A.with_ln = with_ln;
   const int bx = P.G >= 64 ? 4 : (P.G >= 8 ? 32 : 1024);

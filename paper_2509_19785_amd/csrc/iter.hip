@@ -277,10 +277,67 @@ __global__ __launch_bounds__(kPlanThreads) void k_trim_plan(
   __syncthreads();
   if (!last_s || threadIdx.x != 0) return;
   __threadfence();
-  int acc = 0;  // each graph: n_int^2 core boxes, then its far box
+  // the grid buffers every graph needs, before and after fitting them into
+  // the workspace pools: while a pool is short, the largest grid (the
+  // lowest graph id among equals) is halved per axis over the same region
+  size_t need[POOL_KINDS] = {0, 0, 0, 0, 0};
   for (int gg = 0; gg < G; ++gg) {
-    desc[gg].box_base = acc;
     const int ni = ld_coherent(&desc[gg].n_int);
+    for (int k = 0; k < POOL_KINDS; ++k) need[k] += pool_elems(k, ni);
+  }
+  if (pp.need) {
+    for (int k = 0; k < POOL_KINDS; ++k) pp.need[k] = need[k];
+    __threadfence_system();
+  }
+  bool short_pool = false;
+  for (int k = 0; k < POOL_KINDS; ++k) short_pool |= need[k] > pp.cap[k];
+  if (short_pool) {
+    unsigned raised = TSNET_STATUS_WORKSPACE | TSNET_STATUS_GRID_CAPPED;
+    for (;;) {
+      bool fits = true;
+      for (int k = 0; k < POOL_KINDS; ++k) fits &= need[k] <= pp.cap[k];
+      if (fits) break;
+      int big = -1, bn = 1;
+      for (int gg = 0; gg < G; ++gg) {
+        const int ni = ld_coherent(&desc[gg].n_int);
+        if (ni > bn) {
+          bn = ni;
+          big = gg;
+        }
+      }
+      if (big < 0) break;  // every grid is down to one box: nothing left to give
+      GridDesc d2 = desc[big];
+      const double span = (double)d2.h * d2.n_int;
+      const int nn = d2.n_int / 2;
+      for (int k = 0; k < POOL_KINDS; ++k) need[k] += pool_elems(k, nn) - pool_elems(k, d2.n_int);
+      const double h2 = span / nn;
+      const double half2 = 0.5 * nn * h2;
+      d2.x0 = (float)((double)d2.cx - half2);
+      d2.y0 = (float)((double)d2.cy - half2);
+      d2.h = (float)h2;
+      d2.inv_h = (float)(1.0 / h2);
+      d2.half = (float)half2;
+      d2.spacing = (float)(h2 / kNodes);
+      d2.n_int = nn;
+      d2.ng = kNodes * nn;
+      d2.M = 2 * kNodes * nn;
+      d2.flags |= (int)raised;
+      desc[big] = d2;
+      __threadfence();  // the coherent reads of n_int above see the new value
+    }
+    atomicOr(status, raised);
+  }
+  int acc = 0;  // each graph: n_int^2 core boxes, then its far box
+  size_t off[POOL_KINDS] = {0, 0, 0, 0, 0};
+  for (int gg = 0; gg < G; ++gg) {
+    const int ni = ld_coherent(&desc[gg].n_int);
+    desc[gg].box_base = acc;
+    desc[gg].off_c = off[POOL_C];
+    desc[gg].off_q = off[POOL_Q];
+    desc[gg].off_k = off[POOL_K];
+    desc[gg].off_o = off[POOL_O];
+    desc[gg].off_p = off[POOL_P];
+    for (int k = 0; k < POOL_KINDS; ++k) off[k] += pool_elems(k, ni);
     acc += ni * ni + 1;
   }
   *btotal = acc;
@@ -315,7 +372,7 @@ __global__ __launch_bounds__(kChunkThreads) void k_gather(
     const float2* __restrict__ xs, const int* __restrict__ skeys, const int* __restrict__ perm,
     const int* __restrict__ chunk_graph, const int* __restrict__ chunk_start,
     const int* __restrict__ chunk_end, const GridDesc* __restrict__ desc,
-    const GraphInfo* __restrict__ gi, int G, const float* __restrict__ pot, size_t stride_pot,
+    const GraphInfo* __restrict__ gi, int G, const float* __restrict__ pot,
     const float* __restrict__ slot_z, const float* __restrict__ slot_ln, float4* rep_ent,
     float* zi, float* lnv, double* zpart, unsigned* counter, int nblocks, double* zg,
     double* Z_out) {
@@ -325,7 +382,7 @@ __global__ __launch_bounds__(kChunkThreads) void k_gather(
   const int c = blockIdx.x;
   const int g = chunk_graph[c];
   const GridDesc d = desc[g];
-  const float* pg = pot + (size_t)g * stride_pot;
+  const float* pg = pot + d.off_p;
   const bool single = gi[g].n == 1;
   CompSum zs;
   for (int p = chunk_start[c] + threadIdx.x; p < chunk_end[c]; p += kChunkThreads) {
@@ -422,7 +479,7 @@ hipError_t launch_gather(Problem& P, const float2* X, int with_ln, int with_zi, 
   (void)X;
   const int nb = P.num_chunks;
   hipLaunchKernelGGL(k_gather, dim3(nb), dim3(kChunkThreads), 0, s, P.xs, P.skeys, P.perm, P.chunk_graph,
-                     P.chunk_start, P.chunk_end, P.desc, P.ginfo, P.G, P.pot, P.stride_pot,
+                     P.chunk_start, P.chunk_end, P.desc, P.ginfo, P.G, P.pot,
                      P.slot_z, P.slot_ln, P.rep_ent, with_zi ? P.zi : nullptr, with_ln ? P.lnv : nullptr, P.zpart,
                      P.counters + 1, nb, P.zg, Z_out);
   return hipGetLastError();

@@ -61,7 +61,31 @@ struct GridDesc {
   float bmax_x, bmax_y;
   int pad0;
   double s_x, s_y;   // kTrimBins / width per axis (0 for a zero width)
+  // element offsets of the graph's grid buffers in the workspace pools
+  size_t off_c;      // charges (float, 3 ng^2)
+  size_t off_q;      // charge row spectra and their transposes (float2, 3 ng Mh)
+  size_t off_k;      // kernel spectra and their transposes (float, 4 Mh^2)
+  size_t off_o;      // products and their transposes (float2, 8 ng Mh)
+  size_t off_p;      // potentials (float, 8 ng^2)
 };
+
+// Workspace pool kinds, in the order of GridDesc's offsets.
+enum { POOL_C = 0, POOL_Q, POOL_K, POOL_O, POOL_P, POOL_KINDS };
+
+// Elements of each pool kind one graph with n_int boxes per axis needs
+// (rounded up to 64 elements, so every graph's part starts 256-byte aligned).
+__host__ __device__ inline size_t pool_elems(int kind, int n_int) {
+  const size_t ng = 3 * (size_t)n_int, mh = ng + 1;
+  size_t e = 0;
+  switch (kind) {
+    case POOL_C: e = 3 * ng * ng; break;
+    case POOL_Q: e = 3 * ng * mh; break;
+    case POOL_K: e = 4 * mh * mh; break;
+    case POOL_O: e = 8 * ng * mh; break;
+    default: e = 8 * ng * ng; break;
+  }
+  return (e + 63) & ~(size_t)63;
+}
 
 __host__ __device__ inline int far_key(const GridDesc& d) { return d.box_base + d.n_int * d.n_int; }
 
@@ -81,6 +105,9 @@ struct PlanParams {
   double h_target;
   int min_int, max_int;
   int far_trim;      // t of the far-point rule (0: the grid covers the bounding box)
+  int pad;
+  size_t cap[POOL_KINDS];  // pool capacities in elements (SIZE_MAX: no limit)
+  size_t* need;            // mapped host memory: the plan's pool needs, before any capping
 };
 
 // Stage ids for optional per-stage timing.
@@ -157,6 +184,7 @@ struct Problem {
   int* trim_hist = nullptr;           // [G][2][kTrimBins] bin counts (kept at zero between calls)
   float* slot_z = nullptr;            // [n] Z_i of far points, by sorted slot
   float* slot_ln = nullptr;           // [n] interpolated ln sums of far points, by sorted slot
+  // grid buffers: one pool per kind, each graph at its own offset (GridDesc)
   float* charges = nullptr;           // per graph 3 ng^2
   float2* qspec = nullptr;            // per graph [3][ng][M/2+1] row spectra of the charges
   float2* qspec_t = nullptr;          // per graph [3][M/2+1][ng] the same, transposed
@@ -165,7 +193,9 @@ struct Problem {
   float2* ospec_t = nullptr;          // per graph [8][M/2+1][ng] products after the column stage
   float2* ospec = nullptr;            // per graph [8][ng][M/2+1] the same, transposed
   float* pot = nullptr;               // per graph 4 planes (channel pairs) of ng^2 float2
-  size_t stride_charges = 0, stride_qspec = 0, stride_kspec = 0, stride_ospec = 0, stride_pot = 0;
+  size_t pool_cap[POOL_KINDS] = {0, 0, 0, 0, 0};  // capacities in elements (0: not allocated)
+  size_t* need_host = nullptr;        // pinned, mapped: the latest plan's needs [POOL_KINDS]
+  size_t* need_dev = nullptr;         // its device address
   int spread_range = kSpreadRange;    // sorted points per wave of the spread (64 .. kSpreadRange)
   int* head_box = nullptr;            // [spread ranges] box of the leading partial, -1 if none
   int* tail_box = nullptr;            // [spread ranges] box of the trailing partial, -1 if none
@@ -197,6 +227,7 @@ int fail(int code, const std::string& msg);
 
 // per-evaluation path (iter.hip, bin.hip, attract.hip)
 hipError_t launch_bbox_plan(Problem& P, const float2* X, const PlanParams& pp, hipStream_t s);
+// `pp` carries the pool capacities; the plan writes the uncapped needs to pp.need
 // far-point rule: bin counts (only when some graph may set points apart), then the grid plan
 hipError_t launch_trim_plan(Problem& P, const float2* X, const PlanParams& pp, bool with_hist,
                             hipStream_t s);

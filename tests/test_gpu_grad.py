@@ -237,6 +237,42 @@ def test_batch_of_graphs(api, ctx):
         assert rel_l2(got["G"][a0:a1], ex.G[a0:a1]) <= 1e-3
 
 
+def test_batch_workspace_grows(api, ctx):
+    """A batch's grid buffers are pools sized from its first plan (four times
+    its needs). A layout whose grids need more is planned down once, with
+    TSNET_STATUS_WORKSPACE and GRID_CAPPED raised; the pools then grow before
+    the next evaluation, which matches the oracle again."""
+    from paper_2509_19785_amd import _lib
+    parts = [graphs.grid(16, 20), graphs.sbm([250, 260], 0.05, 0.004, 2),
+             graphs.random_recursive_tree(777, 9)]
+    b = graphs.concat_graphs(parts)
+    P = affinities.build_P(b.indptr, b.indices, 10.0, seed=1, graph_offsets=b.graph_offsets)
+    prob = _upload(api, ctx, P, b.graph_offsets)
+    n = b.indptr.shape[0] - 1
+    X1 = graphs.initial_layout(n, 3, std=0.5)
+    ctx.status()
+    _terms(api, prob, X1)                      # 64 intervals per graph: sizes the pools
+    assert not ctx.status() & _lib.TSNET_STATUS_WORKSPACE
+    X2 = X1.copy()
+    a1, a2 = int(b.graph_offsets[1]), int(b.graph_offsets[2])
+    X2[a1:a2] = graphs.initial_layout(a2 - a1, 4, std=12.0)   # needs 512 intervals
+    _terms(api, prob, X2)
+    st = ctx.status()
+    say(f"[workspace] after the larger layout: status {st:#x}, intervals {prob.grid_info()['n_intervals']}")
+    assert st & _lib.TSNET_STATUS_WORKSPACE and st & _lib.TSNET_STATUS_GRID_CAPPED
+    got = _terms(api, prob, X2)                # the pools have grown
+    assert not ctx.status() & (_lib.TSNET_STATUS_WORKSPACE | _lib.TSNET_STATUS_GRID_CAPPED)
+    gi = prob.grid_info()
+    X64 = X2.astype(np.float64)
+    for gidx in range(3):
+        a0, a1_ = int(b.graph_offsets[gidx]), int(b.graph_offsets[gidx + 1])
+        it = interp.interp_terms(X64[a0:a1_], 0.05)
+        assert int(gi["n_intervals"][gidx]) == it.grid.n_int
+        assert rel_l2(got["F_rep"][a0:a1_], it.F_rep) <= _interp_tol(X2[a0:a1_])
+        assert rel_l2(got["F_ent"][a0:a1_], it.F_ent) <= _interp_tol(X2[a0:a1_])
+    assert int(gi["n_intervals"][1]) == 512
+
+
 def test_batch_of_twelve_graphs(api, ctx):
     # 8 or more graphs: each graph's FFT stages get 32 blocks, so the column
     # stage packs several columns per block (6 at M = 384), fewer than the
