@@ -234,6 +234,54 @@ def small_n_leg(api, ctx, iters: int, cpu: bool = True):
     return res
 
 
+def c1_leg(api, ctx, iters: int):
+    """The 32 x 32 grid from N(0, 1e-4) (seed 0), perplexity 40 (k = 120),
+    lambda_c 1.2, lambda_r 0.01, eps 0.05: `iters` iterations with the exact
+    FP64 all-pairs gradient (cast to FP32 for the vertex move), and the same
+    run with the FP32 interpolation gradient; rates and the quality of both
+    final layouts (NP of every vertex, stress over every source)."""
+    import torch
+    from synth import graphs
+    g = graphs.workload_grid32()
+    prob = api.Problem.build(ctx, g.indptr, g.indices, 40.0, seed=0)
+    prm, sp = api.Params(), api.StepParams()
+    X0 = torch.tensor(graphs.initial_layout(g.n, 0), device="cuda")
+    out = {"workload": f"grid 32 x 32, N(0, 1e-4) seed 0, perplexity 40, {iters} iterations, "
+                       "lambda_c 1.2, lambda_r 0.01, eps 0.05"}
+    for name in ("exact FP64 gradient", "FP32 interpolation gradient"):
+        X = X0.clone()
+        U, Ga, G = torch.zeros_like(X), torch.ones_like(X), torch.empty_like(X)
+        exact = name.startswith("exact")
+
+        def one(it):
+            if exact:
+                Gd, _ = prob.grad_direct_f64(X.double(), prm)
+                G.copy_(Gd)
+            else:
+                prob.grad(X, prm, G=G)
+            prob.step(X, U, Ga, G, it, sp)
+        one(0)  # the first evaluation sizes the workspace
+        X.copy_(X0)
+        U.zero_()
+        Ga.fill_(1.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for it in range(iters):
+            one(it)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        q = api.neighbourhood_preservation(ctx, g.indptr, g.indices, X)
+        st = api.stress(ctx, g.indptr, g.indices, X, np.arange(g.n, dtype=np.int32))
+        out[name] = {"iters_per_s": iters / wall, "np": float(q["np"][0]),
+                     "stress": float(st["stress"][0]),
+                     "stress_best_scale": float(st["stress_best_scale"][0]),
+                     "span": float((X.max(0).values - X.min(0).values).max())}
+        log(f"C1 {name}: {iters / wall:.0f} iters/s, NP {out[name]['np']:.4f}, stress "
+            f"{out[name]['stress']:.4f} (best scale {out[name]['stress_best_scale']:.4f})")
+    prob.free()
+    return out
+
+
 def metrics_cpu_baseline(g, X, np_sample: int = 16, stress_sample: int = 2, sources: int = 64):
     """The oracle's metrics on the host: neighbourhood preservation of `np_sample`
     vertices extrapolated to all n, stress of `stress_sample` sources extrapolated
@@ -502,6 +550,9 @@ def main():
                     help="timed runs from the initial layout (plain launches); value is their mean")
     ap.add_argument("--last", type=int, default=100,
                     help="the rate of the last LAST steps of every run is reported beside the whole-run rate")
+    ap.add_argument("--c1-iters", type=int, default=500,
+                    help="iterations of the 32 x 32 grid run from N(0, 1e-4), exact FP64 gradient "
+                         "and FP32 interpolation (0: skip)")
     ap.add_argument("--long-steps", type=int, default=1000,
                     help="steps of the long run of the benchmark problem from the initial layout (0: skip)")
     ap.add_argument("--legs", default="sbm20k,rgg100k,mixed256",
@@ -873,6 +924,7 @@ def main():
 
     small = small_n_leg(api, ctx, args.small_iters, cpu=not args.no_cpu_baseline) \
         if args.small_iters > 0 else None
+    c1 = c1_leg(api, ctx, args.c1_iters) if args.c1_iters > 0 else None
 
     legs = None
     which = [w for w in args.legs.split(",") if w]
@@ -948,6 +1000,7 @@ def main():
         "variants": variants,
         "long_run": long_run,
         "small_n": small,
+        "c1_grid32": c1,
         "workloads": legs,
     }
     print(json.dumps(out), flush=True)

@@ -151,6 +151,7 @@ static void free_problem(Problem& P) {
   free_quadtree(P);
   dfree(P.ginfo);
   dfree(P.goff_d);
+  dfree(P.vgraph);
   dfree(P.chunk_graph);
   dfree(P.chunk_start);
   dfree(P.chunk_end);
@@ -269,6 +270,13 @@ static int init_problem(Ctx& c, Problem& P, int n, const int32_t* goff_host, int
     return rc;
   TSNET_HIP(hipMemcpy(P.ginfo, P.ginfo_h.data(), sizeof(GraphInfo) * G, hipMemcpyHostToDevice));
   TSNET_HIP(hipMemcpy(P.goff_d, P.goff.data(), sizeof(int) * (G + 1), hipMemcpyHostToDevice));
+  if (G > 1) {  // graph of every vertex: one load instead of a search over the offsets
+    std::vector<int> vg(n);
+    for (int g = 0; g < G; ++g)
+      for (int v = P.goff[g]; v < P.goff[g + 1]; ++v) vg[v] = g;
+    if ((rc = dmalloc(&P.vgraph, n, "vgraph"))) return rc;
+    TSNET_HIP(hipMemcpy(P.vgraph, vg.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+  }
   TSNET_HIP(hipMemcpy(P.chunk_graph, cg.data(), sizeof(int) * nc, hipMemcpyHostToDevice));
   TSNET_HIP(hipMemcpy(P.chunk_start, cs.data(), sizeof(int) * nc, hipMemcpyHostToDevice));
   TSNET_HIP(hipMemcpy(P.chunk_end, ce.data(), sizeof(int) * nc, hipMemcpyHostToDevice));

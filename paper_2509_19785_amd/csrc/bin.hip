@@ -52,7 +52,7 @@ __device__ __forceinline__ int box_key(const GridDesc& d, float x, float y) {
 
 // Pass 0: keys of tile `blockIdx.x` and its digit histogram.
 __global__ __launch_bounds__(256) void k_bin_keys(const float2* __restrict__ X, int n,
-                                                  const int* __restrict__ goff, int G,
+                                                  const int* __restrict__ vgraph, int G,
                                                   const GridDesc* __restrict__ desc, int* keys,
                                                   int tiles, int* hist) {
   __shared__ int cnt[kDigits];
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(256) void k_bin_keys(const float2* __restrict__ X, 
   for (int r = 0; r < kBinRounds; ++r) {
     const int i = base + r * 256 + threadIdx.x;
     if (i < n) {
-      const int g = G == 1 ? 0 : graph_of(goff, G, i);
+      const int g = G == 1 ? 0 : vgraph[i];
       const int key = box_key(desc[g], p[r].x, p[r].y);
       keys[i] = key;
       atomicAdd(&cnt[key & (kDigits - 1)], 1);
@@ -175,14 +175,11 @@ __global__ __launch_bounds__(256) void k_box_bounds(const int* __restrict__ skey
     }
     box_off[b] = lo;
   }
-  for (int g = 0; g < G; ++g) {
-    const size_t len = (size_t)3 * desc[g].ng * desc[g].ng;  // floats of the graph's 3 grids
-    float* base = charges + desc[g].off_c;  // 256-byte aligned
-    const size_t len4 = len / 4;
-    float4* b4 = reinterpret_cast<float4*>(base);
-    for (size_t k = t0; k < len4; k += nt) b4[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (size_t k = 4 * len4 + t0; k < len; k += nt) base[k] = 0.f;
-  }
+  // the graphs' charge grids lie back to back in the pool (each part a
+  // multiple of 64 floats): one flat sweep clears all of them
+  const size_t len4 = (desc[G - 1].off_c + pool_elems(POOL_C, desc[G - 1].n_int)) / 4;
+  float4* b4 = reinterpret_cast<float4*>(charges);
+  for (size_t k = t0; k < len4; k += nt) b4[k] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 hipError_t launch_bin(Problem& P, const float2* X, hipStream_t s) {
@@ -196,7 +193,7 @@ hipError_t launch_bin(Problem& P, const float2* X, hipStream_t s) {
   // free once pass 0 has read it.
   int* kin = P.keys;
   int* vin = nullptr;
-  hipLaunchKernelGGL(k_bin_keys, dim3(tiles), dim3(256), 0, s, X, n, P.goff_d, P.G, P.desc, P.keys,
+  hipLaunchKernelGGL(k_bin_keys, dim3(tiles), dim3(256), 0, s, X, n, P.vgraph, P.G, P.desc, P.keys,
                      tiles, P.bin_hist);
   for (int p = 0; p < passes; ++p) {
     const int shift = kDigitBits * p;

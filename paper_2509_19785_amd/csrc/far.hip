@@ -197,11 +197,12 @@ __global__ __launch_bounds__(kFarThreads) void k_far(FarArgs A) {
 }
 
 hipError_t launch_far(Problem& P, int far_trim, float eps, int with_ln, hipStream_t s) {
-  // blocks per graph and role: enough for one far point each at G = 1, fewer
-  // per graph in a batch (most graphs of a batch have no far point)
-  int nbx = 2048 / P.G;
-  nbx = nbx < 1 ? 1 : (nbx > 4 * far_trim ? 4 * far_trim : nbx);
+  // blocks per graph and role: one per far point at G = 1 (4 t at most),
+  // fewer per graph in a batch, at least 16
+  int nbx = 16384 / P.G;
+  if (nbx > 4 * far_trim) nbx = 4 * far_trim;
   if (nbx > 256) nbx = 256;
+  if (nbx < 16) nbx = 16;
   FarArgs A;
   A.desc = P.desc;
   A.box_off = P.box_off;

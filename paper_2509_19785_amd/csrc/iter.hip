@@ -275,73 +275,115 @@ __global__ __launch_bounds__(kPlanThreads) void k_trim_plan(
     last_s = (atomicAdd(counter, 1u) == (unsigned)(G - 1));
   }
   __syncthreads();
-  if (!last_s || threadIdx.x != 0) return;
+  if (!last_s) return;
   __threadfence();
   // the grid buffers every graph needs, before and after fitting them into
-  // the workspace pools: while a pool is short, the largest grid (the
-  // lowest graph id among equals) is halved per axis over the same region
+  // the workspace pools (the whole block: one graph per thread and step)
+  __shared__ unsigned long long red_need[POOL_KINDS][kPlanThreads / kWave];
   size_t need[POOL_KINDS] = {0, 0, 0, 0, 0};
-  for (int gg = 0; gg < G; ++gg) {
+  for (int gg = threadIdx.x; gg < G; gg += kPlanThreads) {
     const int ni = ld_coherent(&desc[gg].n_int);
     for (int k = 0; k < POOL_KINDS; ++k) need[k] += pool_elems(k, ni);
   }
-  if (pp.need) {
-    for (int k = 0; k < POOL_KINDS; ++k) pp.need[k] = need[k];
-    __threadfence_system();
+  for (int k = 0; k < POOL_KINDS; ++k) {
+    const unsigned long long v = wave_sum((unsigned long long)need[k]);
+    if (lane_id() == 0) red_need[k][wave_id()] = v;
   }
-  bool short_pool = false;
-  for (int k = 0; k < POOL_KINDS; ++k) short_pool |= need[k] > pp.cap[k];
-  if (short_pool) {
-    unsigned raised = TSNET_STATUS_WORKSPACE | TSNET_STATUS_GRID_CAPPED;
-    for (;;) {
-      bool fits = true;
-      for (int k = 0; k < POOL_KINDS; ++k) fits &= need[k] <= pp.cap[k];
-      if (fits) break;
-      int big = -1, bn = 1;
-      for (int gg = 0; gg < G; ++gg) {
-        const int ni = ld_coherent(&desc[gg].n_int);
-        if (ni > bn) {
-          bn = ni;
-          big = gg;
-        }
-      }
-      if (big < 0) break;  // every grid is down to one box: nothing left to give
-      GridDesc d2 = desc[big];
-      const double span = (double)d2.h * d2.n_int;
-      const int nn = d2.n_int / 2;
-      for (int k = 0; k < POOL_KINDS; ++k) need[k] += pool_elems(k, nn) - pool_elems(k, d2.n_int);
-      const double h2 = span / nn;
-      const double half2 = 0.5 * nn * h2;
-      d2.x0 = (float)((double)d2.cx - half2);
-      d2.y0 = (float)((double)d2.cy - half2);
-      d2.h = (float)h2;
-      d2.inv_h = (float)(1.0 / h2);
-      d2.half = (float)half2;
-      d2.spacing = (float)(h2 / kNodes);
-      d2.n_int = nn;
-      d2.ng = kNodes * nn;
-      d2.M = 2 * kNodes * nn;
-      d2.flags |= (int)raised;
-      desc[big] = d2;
-      __threadfence();  // the coherent reads of n_int above see the new value
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < POOL_KINDS; ++k) {
+      need[k] = 0;
+      for (int w = 0; w < kPlanThreads / kWave; ++w) need[k] += red_need[k][w];
     }
-    atomicOr(status, raised);
+    if (pp.need) {
+      for (int k = 0; k < POOL_KINDS; ++k) pp.need[k] = need[k];
+      __threadfence_system();
+    }
+    bool short_pool = false;
+    for (int k = 0; k < POOL_KINDS; ++k) short_pool |= need[k] > pp.cap[k];
+    if (short_pool) {
+      // while a pool is short, the largest grid (the lowest graph id among
+      // equals) is halved per axis over the same region
+      const unsigned raised = TSNET_STATUS_WORKSPACE | TSNET_STATUS_GRID_CAPPED;
+      for (;;) {
+        bool fits = true;
+        for (int k = 0; k < POOL_KINDS; ++k) fits &= need[k] <= pp.cap[k];
+        if (fits) break;
+        int big = -1, bn = 1;
+        for (int gg = 0; gg < G; ++gg) {
+          const int ni = ld_coherent(&desc[gg].n_int);
+          if (ni > bn) {
+            bn = ni;
+            big = gg;
+          }
+        }
+        if (big < 0) break;  // every grid is down to one box: nothing left to give
+        GridDesc d2 = desc[big];
+        const double span = (double)d2.h * d2.n_int;
+        const int nn = d2.n_int / 2;
+        for (int k = 0; k < POOL_KINDS; ++k) need[k] += pool_elems(k, nn) - pool_elems(k, d2.n_int);
+        const double h2 = span / nn;
+        const double half2 = 0.5 * nn * h2;
+        d2.x0 = (float)((double)d2.cx - half2);
+        d2.y0 = (float)((double)d2.cy - half2);
+        d2.h = (float)h2;
+        d2.inv_h = (float)(1.0 / h2);
+        d2.half = (float)half2;
+        d2.spacing = (float)(h2 / kNodes);
+        d2.n_int = nn;
+        d2.ng = kNodes * nn;
+        d2.M = 2 * kNodes * nn;
+        d2.flags |= (int)raised;
+        desc[big] = d2;
+        __threadfence();  // the coherent reads of n_int above see the new value
+      }
+      atomicOr(status, raised);
+    }
   }
-  int acc = 0;  // each graph: n_int^2 core boxes, then its far box
-  size_t off[POOL_KINDS] = {0, 0, 0, 0, 0};
-  for (int gg = 0; gg < G; ++gg) {
-    const int ni = ld_coherent(&desc[gg].n_int);
-    desc[gg].box_base = acc;
-    desc[gg].off_c = off[POOL_C];
-    desc[gg].off_q = off[POOL_Q];
-    desc[gg].off_k = off[POOL_K];
-    desc[gg].off_o = off[POOL_O];
-    desc[gg].off_p = off[POOL_P];
-    for (int k = 0; k < POOL_KINDS; ++k) off[k] += pool_elems(k, ni);
-    acc += ni * ni + 1;
+  __syncthreads();
+  // box ids and pool offsets: exclusive prefix sums over the graphs in order,
+  // kPlanThreads graphs per step
+  __shared__ int carry_box;
+  __shared__ unsigned long long carry_off[POOL_KINDS];
+  __shared__ int sh_scan[kPlanThreads / kWave + 1];
+  if (threadIdx.x == 0) {
+    carry_box = 0;
+    for (int k = 0; k < POOL_KINDS; ++k) carry_off[k] = 0;
   }
-  *btotal = acc;
-  *counter = 0u;
+  __syncthreads();
+  for (int base = 0; base < G; base += kPlanThreads) {
+    const int gg = base + threadIdx.x;
+    const int ni = gg < G ? ld_coherent(&desc[gg].n_int) : 0;
+    int tot;
+    const int bx = block_excl_scan(gg < G ? ni * ni + 1 : 0, sh_scan, &tot);
+    size_t off[POOL_KINDS];
+    unsigned long long tot_k[POOL_KINDS];
+    for (int k = 0; k < POOL_KINDS; ++k) {
+      // pool parts are multiples of 64 elements: scan them in units of 64
+      int t64;
+      const int u = block_excl_scan(gg < G ? (int)(pool_elems(k, ni) / 64) : 0, sh_scan, &t64);
+      off[k] = (size_t)carry_off[k] + (size_t)u * 64;
+      tot_k[k] = (unsigned long long)t64 * 64;
+    }
+    if (gg < G) {
+      desc[gg].box_base = carry_box + bx;
+      desc[gg].off_c = off[POOL_C];
+      desc[gg].off_q = off[POOL_Q];
+      desc[gg].off_k = off[POOL_K];
+      desc[gg].off_o = off[POOL_O];
+      desc[gg].off_p = off[POOL_P];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      carry_box += tot;
+      for (int k = 0; k < POOL_KINDS; ++k) carry_off[k] += tot_k[k];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    *btotal = carry_box;
+    *counter = 0u;
+  }
 }
 
 hipError_t launch_trim_plan(Problem& P, const float2* X, const PlanParams& pp, bool with_hist,
@@ -494,10 +536,10 @@ struct StepK {
 
 __global__ __launch_bounds__(256) void k_step(float2* X, float2* upd, float2* gains,
                                               const float2* __restrict__ Gr, int n,
-                                              const int* __restrict__ goff, int G,
+                                              const int* __restrict__ vgraph, int G,
                                               const GraphInfo* __restrict__ gi, StepK sk) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const float eta = sk.eta > 0.f ? sk.eta : gi[G == 1 ? 0 : graph_of(goff, G, i)].lr;
+    const float eta = sk.eta > 0.f ? sk.eta : gi[G == 1 ? 0 : vgraph[i]].lr;
     const float2 g = Gr[i];
     float2 u = upd[i], k = gains[i], x = X[i];
     k.x = ((g.x > 0.f) != (u.x > 0.f)) ? k.x + sk.up : k.x * sk.down;
@@ -524,7 +566,7 @@ hipError_t launch_step(Problem& P, float2* X, float2* upd, float2* gains, const 
   sk.down = (float)sp.gain_down;
   int blocks = (P.n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_step, dim3(blocks), dim3(256), 0, s, X, upd, gains, G, P.n, P.goff_d, P.G,
+  hipLaunchKernelGGL(k_step, dim3(blocks), dim3(256), 0, s, X, upd, gains, G, P.n, P.vgraph, P.G,
                      P.ginfo, sk);
   return hipGetLastError();
 }

@@ -146,6 +146,7 @@ struct Problem {
   // device: graph data
   GraphInfo* ginfo = nullptr;
   int* goff_d = nullptr;              // [G+1]
+  int* vgraph = nullptr;              // [n] graph of every vertex (batches only)
   int* chunk_graph = nullptr;         // [num_chunks]
   int* chunk_start = nullptr;
   int* chunk_end = nullptr;
@@ -154,6 +155,7 @@ struct Problem {
   int* col = nullptr;
   float* val = nullptr;
   int* row_order = nullptr;           // [n] rows by decreasing length (attraction order)
+  int attract_blocks = 0;             // blocks of the row attraction the device holds at once
   // device: tiled copy of P for the attraction (row tiles x column windows)
   int tile_T = 0, tile_R = 0, tile_NC = 0;  // row tiles, slots per tile, column windows
   int* tile_rows = nullptr;           // [T * R] vertex of each slot, -1 if unused
