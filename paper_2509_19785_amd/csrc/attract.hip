@@ -55,11 +55,11 @@ constexpr int kRowBatch = 4;
 // unconditional. Entries past b get weight 0 and column 0: what was read
 // there may belong to no row (P with no entries holds one unset element).
 __device__ __forceinline__ void row_batch(const int* __restrict__ col, const float* __restrict__ val,
-                                          int64_t a, int64_t b, int lane, int (&j)[kRowBatch],
+                                          int a, int b, int lane, int (&j)[kRowBatch],
                                           float (&p)[kRowBatch]) {
 #pragma unroll
   for (int u = 0; u < kRowBatch; ++u) {
-    const int64_t e = max(min(a + lane + u * kWave, b - 1), (int64_t)0);
+    const int e = max(min(a + lane + u * kWave, b - 1), 0);
     j[u] = col[e];
     p[u] = val[e];
   }
@@ -76,7 +76,7 @@ __device__ __forceinline__ void row_terms(float2 xi, const float2 (&xj)[kRowBatc
 #pragma unroll
   for (int u = 0; u < kRowBatch; ++u) {
     const float dx = xi.x - xj[u].x, dy = xi.y - xj[u].y;
-    const float w = p[u] / (1.0f + dx * dx + dy * dy);
+    const float w = p[u] * __builtin_amdgcn_rcpf(1.0f + dx * dx + dy * dy);
     fx += w * dx;
     fy += w * dy;
   }
@@ -87,7 +87,9 @@ __device__ __forceinline__ void row_terms(float2 xi, const float2 (&xj)[kRowBatc
 // dependent loads of a row (row id -> row bounds -> columns -> x_j) is not
 // waited out row by row: while the x_j of row t are gathered, the columns of
 // row t + S, the bounds of row t + 2S and the id of row t + 3S are in flight.
-// Rows past n are read at the clamped index n - 1 and never written.
+// Rows past n are read at the clamped index n - 1 and never written. Entry
+// offsets are 32-bit (P holds fewer than 2^31 entries); the weight uses the
+// hardware reciprocal (1 ulp), as the tiled kernel does.
 __global__ __launch_bounds__(256) void k_attract(
     const float2* __restrict__ X, const int64_t* __restrict__ rowptr, const int* __restrict__ col,
     const float* __restrict__ val, const int* __restrict__ order, int n,
@@ -102,7 +104,7 @@ __global__ __launch_bounds__(256) void k_attract(
   auto row_at = [&](int64_t q) { return order[q < n ? q : n - 1]; };
   // row t: bounds, x_i, graph and first batch
   int i0 = row_at(t);
-  int64_t a0 = rowptr[i0], b0 = rowptr[i0 + 1];
+  int a0 = (int)rowptr[i0], b0 = (int)rowptr[i0 + 1];
   float2 x0 = X[i0];
   int g0 = G == 1 ? 0 : vgraph[i0];
   int j0[kRowBatch];
@@ -110,7 +112,7 @@ __global__ __launch_bounds__(256) void k_attract(
   row_batch(col, val, a0, b0, lane, j0, p0);
   // row t + S: bounds; row t + 2S: id
   int i1 = row_at((int64_t)t + S);
-  int64_t a1 = rowptr[i1], b1 = rowptr[i1 + 1];
+  int a1 = (int)rowptr[i1], b1 = (int)rowptr[i1 + 1];
   float2 x1 = X[i1];
   int g1 = G == 1 ? 0 : vgraph[i1];
   int i2 = row_at((int64_t)t + 2 * (int64_t)S);
@@ -126,7 +128,7 @@ __global__ __launch_bounds__(256) void k_attract(
     int j1[kRowBatch];
     float p1[kRowBatch];
     row_batch(col, val, a1, b1, lane, j1, p1);
-    const int64_t a2 = rowptr[i2], b2 = rowptr[i2 + 1];
+    const int a2 = (int)rowptr[i2], b2 = (int)rowptr[i2 + 1];
     const float2 x2 = X[i2];
     const int g2 = G == 1 ? 0 : vgraph[i2];
     const int i3 = row_at((int64_t)t + 3 * (int64_t)S);
@@ -134,12 +136,12 @@ __global__ __launch_bounds__(256) void k_attract(
     float fx = 0.f, fy = 0.f;
     row_terms(x0, xj, p0, fx, fy);
     // entries past the first batch of a long row (not pipelined)
-    for (int64_t e0 = a0 + lane + kRowBatch * kWave; e0 < b0; e0 += kRowBatch * kWave) {
+    for (int e0 = a0 + lane + kRowBatch * kWave; e0 < b0; e0 += kRowBatch * kWave) {
       int j[kRowBatch];
       float p[kRowBatch];
 #pragma unroll
       for (int u = 0; u < kRowBatch; ++u) {
-        const int64_t e = min(e0 + u * kWave, b0 - 1);
+        const int e = min(e0 + u * kWave, b0 - 1);
         j[u] = col[e];
         p[u] = val[e];
       }
