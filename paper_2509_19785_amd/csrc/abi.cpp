@@ -159,9 +159,13 @@ static void free_problem(Problem& P) {
   dfree(P.col);
   dfree(P.val);
   dfree(P.tile_rows);
+  dfree(P.tile_wlo);
+  dfree(P.tile_boff);
+  dfree(P.tile_graph);
   dfree(P.tile_bstart);
   dfree(P.tile_ent);
-  P.tile_T = P.tile_R = P.tile_NC = 0;
+  P.tile_T = P.tile_R = 0;
+  P.tile_NB = 0;
   dfree(P.beta);
   dfree(P.rstatus);
   dfree(P.cond_len);
@@ -331,13 +335,13 @@ static int ensure_grid(Problem& P, int cap) {
 static int finish_problem(Problem& P, hipStream_t s) {
   if (P.nnz >= ((int64_t)1 << 31)) return fail(TSNET_EINVAL, "P has more than 2^31 nonzeros");
   int rc = build_row_order(P);
-  if (!rc && P.n >= kTileAutoMinN && tiles_supported(P.n)) rc = build_tiles(P, s);
+  if (!rc && P.n >= kTileAutoMinN && tiles_supported(P)) rc = build_tiles(P, s);
   return rc;
 }
 
 static bool use_tiles(const Problem& P, const tsnet_params& prm) {
   if (prm.attract_layout == TSNET_ATTRACT_TILED) return true;
-  return prm.attract_layout == TSNET_ATTRACT_AUTO && P.n >= kTileAutoMinN && tiles_supported(P.n);
+  return prm.attract_layout == TSNET_ATTRACT_AUTO && P.n >= kTileAutoMinN && tiles_supported(P);
 }
 
 static int check_params(const tsnet_params* p) {

@@ -7,15 +7,17 @@
 // so most of those gathers miss L2 and refetch whole lines. Here the gathers
 // come from LDS instead:
 //
-//  * rows are dealt to T row tiles in snake order over decreasing row length
-//    (every tile holds about nnz / T entries); the rows of a tile get slots
-//    0 .. R-1;
-//  * columns are cut into windows of kTileCols vertices;
+//  * the rows of each graph are dealt to the graph's row tiles in snake order
+//    over decreasing row length (every tile of a graph holds about the same
+//    number of entries); the rows of a tile get slots 0 .. R-1;
+//  * columns are cut into windows of kTileCols vertices; a tile spans the
+//    windows that its graph's vertices fall in (P is block-diagonal over the
+//    graphs of a batch, so no entry of a tile lies outside them);
 //  * block (t, c) holds the entries of tile t's rows whose column lies in
-//    window c, ordered by slot and packed as {slot << 13 | column offset in
-//    the window, value bits}.
+//    the tile's c-th window, ordered by slot and packed as {slot << 13 |
+//    column offset in the window, value bits}.
 //
-// One workgroup per row tile walks the windows in order, with X[window] in LDS
+// One workgroup per row tile walks its windows in order, with X[window] in LDS
 // (the next window is fetched into registers while the current one is in use)
 // and the row sums of its tile in LDS. A block is cut into 16 equal pieces,
 // one per wave; a lane walks a run of up to 6 consecutive entries, and partial
@@ -50,13 +52,14 @@ static_assert(kTileSlotBits + kTileColBits <= 32, "packed entry too wide");
 
 struct TileArgs {
   const float2* X;
-  int n, R, NC;
+  int n, R;
   int last;               // nnz - 1 (at least 0: the entry array has one element or more)
   const int* tile_rows;   // [T * R] vertex of each slot, -1 for an unused slot
-  const int* bstart;      // [T * NC + 1] first entry of every block
+  const int* wlo;         // [T] first column window of each tile
+  const int* boff;        // [T + 1] first block of each tile
+  const int* tgraph;      // [T] graph of each tile
+  const int* bstart;      // [NB + 1] first entry of every block
   const uint2* ent;       // [nnz]
-  const int* goff;
-  int G;
   const GraphInfo* gi;
   const double* zg;
   const float4* rep_ent;  // (F_rep, F_ent) of each vertex
@@ -253,10 +256,12 @@ __global__ __launch_bounds__(kTileThreads) void k_attract_tiled(TileArgs a) {
   __shared__ float2 hval[kTileWaves];
   __shared__ int bst[kTileMaxNC + 1];
   const int t = blockIdx.x, tid = threadIdx.x, lane = lane_id(), wv = wave_id();
-  const int R = a.R, NC = a.NC, n = a.n;
+  const int R = a.R, n = a.n;
+  const int b0 = a.boff[t], NC = a.boff[t + 1] - b0;  // the tile's windows
+  const int xw = a.wlo[t] * kTileCols;                 // first vertex of its first window
   // the tile's block starts: read once, so no window waits on a load of them
   static_assert(kTileMaxNC < kTileThreads, "one block start per thread");
-  if (tid <= NC) bst[tid] = a.bstart[(size_t)t * NC + tid];
+  if (tid <= NC) bst[tid] = a.bstart[(size_t)b0 + tid];
   // the tile's rows and the first window: every load issued before any is used
   {
     int iv[kTileRowsPerThread];
@@ -265,7 +270,7 @@ __global__ __launch_bounds__(kTileThreads) void k_attract_tiled(TileArgs a) {
 #pragma unroll
     for (int q = 0; q < kTileRowsPerThread; ++q) xv[q] = a.X[max(iv[q], 0)];
 #pragma unroll
-    for (int q = 0; q < PRE; ++q) wv0[q] = a.X[min(q * kTileThreads + tid, n - 1)];
+    for (int q = 0; q < PRE; ++q) wv0[q] = a.X[min(xw + q * kTileThreads + tid, n - 1)];
 #pragma unroll
     for (int q = 0; q < kTileRowsPerThread; ++q) {
       const int s = q * kTileThreads + tid;
@@ -296,7 +301,7 @@ __global__ __launch_bounds__(kTileThreads) void k_attract_tiled(TileArgs a) {
     float2 pre[PRE];
 #pragma unroll
     for (int q = 0; q < PRE; ++q)
-      pre[q] = a.X[min(cn * kTileCols + q * kTileThreads + tid, n - 1)];
+      pre[q] = a.X[min(xw + cn * kTileCols + q * kTileThreads + tid, n - 1)];
     const Piece pn = piece_of(a, bst, cn, wv);
     int ns0, ncnt;
     run_of(pn.p0, pn.p1, lane, ns0, ncnt);
@@ -372,18 +377,18 @@ __global__ __launch_bounds__(kTileThreads) void k_attract_tiled(TileArgs a) {
   tile_row_ids(a, t, tid, iv);
 #pragma unroll
   for (int q = 0; q < kTileRowsPerThread; ++q) rv[q] = a.rep_ent[max(iv[q], 0)];
+  const int g = a.tgraph[t];
+  const double Z = a.zg[g];
+  const float inv_z = Z > 0.0 ? (float)(1.0 / Z) : 0.0f;
+  const float cn = a.lc * a.gi[g].inv_n, rn = a.lr * a.gi[g].inv_n2;
 #pragma unroll
   for (int q = 0; q < kTileRowsPerThread; ++q) {
     const int s = q * kTileThreads + tid, i = iv[q];
     if (i < 0) continue;
     const float4 rs = rec[s];
     const float2 f = make_float2(rs.z, rs.w), xi = make_float2(rs.x, rs.y);
-    const int g = a.G == 1 ? 0 : graph_of(a.goff, a.G, i);
-    const double Z = a.zg[g];
-    const float inv_z = Z > 0.0 ? (float)(1.0 / Z) : 0.0f;
     const float4 re = rv[q];
     const float2 rp = make_float2(re.x, re.y), en = make_float2(re.z, re.w);
-    const float cn = a.lc * a.gi[g].inv_n, rn = a.lr * a.gi[g].inv_n2;
     float2 o;
     o.x = a.lkl4 * (f.x - rp.x * inv_z) + cn * xi.x - rn * en.x;
     o.y = a.lkl4 * (f.y - rp.y * inv_z) + cn * xi.y - rn * en.y;
@@ -398,13 +403,13 @@ hipError_t launch_attract_tiled(Problem& P, const float2* X, const tsnet_params&
   a.X = X;
   a.n = P.n;
   a.R = P.tile_R;
-  a.NC = P.tile_NC;
   a.last = P.nnz > 0 ? (int)(P.nnz - 1) : 0;
   a.tile_rows = P.tile_rows;
+  a.wlo = P.tile_wlo;
+  a.boff = P.tile_boff;
+  a.tgraph = P.tile_graph;
   a.bstart = P.tile_bstart;
   a.ent = P.tile_ent;
-  a.goff = P.goff_d;
-  a.G = P.G;
   a.gi = P.ginfo;
   a.zg = P.zg;
   a.rep_ent = P.rep_ent;
@@ -424,13 +429,16 @@ hipError_t launch_attract_tiled(Problem& P, const float2* X, const tsnet_params&
 __global__ __launch_bounds__(256) void k_tile_keys(const int64_t* __restrict__ rowptr,
                                                    const int* __restrict__ col,
                                                    const int* __restrict__ tslot, int n, int R,
-                                                   int NC, unsigned* keys, unsigned* vals) {
+                                                   const int* __restrict__ wlo,
+                                                   const int* __restrict__ boff, unsigned* keys,
+                                                   unsigned* vals) {
   const int lane = lane_id();
   for (int i = blockIdx.x * 4 + wave_id(); i < n; i += gridDim.x * 4) {
     const int ts = tslot[i];
     const unsigned tile = (unsigned)(ts / R), slot = (unsigned)(ts % R);
+    const unsigned bt = (unsigned)boff[tile], wt = (unsigned)wlo[tile];
     for (int64_t e = rowptr[i] + lane; e < rowptr[i + 1]; e += kWave) {
-      const unsigned b = tile * (unsigned)NC + ((unsigned)col[e] >> kTileColBits);
+      const unsigned b = bt + ((unsigned)col[e] >> kTileColBits) - wt;
       keys[e] = (b << kTileSlotBits) | slot;
       vals[e] = (unsigned)e;
     }
@@ -463,37 +471,79 @@ __global__ __launch_bounds__(256) void k_tile_bounds(const unsigned* __restrict_
   }
 }
 
-bool tiles_supported(int n) {
-  const int64_t T = std::max<int64_t>(kTileMinTiles, (n + kTileMaxRows - 1) / kTileMaxRows);
-  const int64_t NC = (n + kTileCols - 1) / kTileCols;
-  return NC <= kTileMaxNC && T * NC < ((int64_t)1 << (32 - kTileSlotBits));
+// Row tiles of every graph: at least one per kTileMaxRows rows, and about
+// kTileMinTiles in all over the batch (in proportion to the graphs' sizes),
+// never more than the graph's rows. Each tile of graph g spans the column
+// windows from the one holding g's first vertex to the one holding its last.
+struct TilePlan {
+  int T = 0, R = 1;
+  int64_t nb = 0;
+  std::vector<int> first;  // [G + 1] first tile of each graph
+  std::vector<int> nw;     // [G] windows of each graph's tiles
+  bool ok = false;
+};
+
+static TilePlan plan_tiles(const Problem& P) {
+  TilePlan tp;
+  tp.first.assign(P.G + 1, 0);
+  tp.nw.assign(P.G, 0);
+  const int64_t n = std::max(P.n, 1);
+  for (int g = 0; g < P.G; ++g) {
+    const int lo = P.goff[g], ng = P.goff[g + 1] - lo;
+    int64_t Tg = 0;
+    if (ng > 0) {
+      Tg = std::max<int64_t>((ng + kTileMaxRows - 1) / kTileMaxRows,
+                             ((int64_t)kTileMinTiles * ng + n - 1) / n);
+      Tg = std::min<int64_t>(Tg, ng);
+      tp.R = std::max<int>(tp.R, (int)((ng + Tg - 1) / Tg));
+      tp.nw[g] = ((lo + ng - 1) >> kTileColBits) - (lo >> kTileColBits) + 1;
+      if (tp.nw[g] > kTileMaxNC) return tp;
+    }
+    tp.first[g + 1] = tp.first[g] + (int)Tg;
+    tp.nb += Tg * tp.nw[g];
+  }
+  tp.T = tp.first[P.G];
+  tp.ok = tp.T > 0 && tp.R <= kTileMaxRows && tp.nb < ((int64_t)1 << (32 - kTileSlotBits));
+  return tp;
 }
+
+bool tiles_supported(const Problem& P) { return plan_tiles(P).ok; }
 
 int build_tiles(Problem& P, hipStream_t s) {
   const int n = P.n;
   const int64_t nnz = P.nnz;
-  if (!tiles_supported(n)) return fail(TSNET_EINVAL, "tiled attraction: too many vertices");
-  const int T = std::max(kTileMinTiles, (n + kTileMaxRows - 1) / kTileMaxRows);
-  const int R = (n + T - 1) / T;
-  const int NC = (n + kTileCols - 1) / kTileCols;
-  const int nb = T * NC;
-  // rows dealt to tiles: snake order over decreasing length
+  const TilePlan tp = plan_tiles(P);
+  if (!tp.ok) return fail(TSNET_EINVAL, "tiled attraction: a graph spans too many column windows");
+  const int T = tp.T, R = tp.R;
+  const int nb = (int)tp.nb;
+  // rows dealt to each graph's tiles: snake order over decreasing length
   std::vector<int64_t> rp(n + 1);
   TSNET_HIP(hipMemcpyAsync(rp.data(), P.rowptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s));
   TSNET_HIP(hipStreamSynchronize(s));
   std::vector<int> order(n);
   std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-    return rp[x + 1] - rp[x] > rp[y + 1] - rp[y];
-  });
   std::vector<int> tslot(n), rows((size_t)T * R, -1);
-  for (int q = 0; q < n; ++q) {
-    const int round = q / T, idx = q % T;
-    const int tile = (round & 1) ? T - 1 - idx : idx;
-    tslot[order[q]] = tile * R + round;
-    rows[(size_t)tile * R + round] = order[q];
+  std::vector<int> wlo(T), boff(T + 1), tgraph(T);
+  for (int g = 0; g < P.G; ++g) {
+    const int lo = P.goff[g], hi = P.goff[g + 1];
+    const int Tg = tp.first[g + 1] - tp.first[g];
+    std::stable_sort(order.begin() + lo, order.begin() + hi, [&](int x, int y) {
+      return rp[x + 1] - rp[x] > rp[y + 1] - rp[y];
+    });
+    for (int q = 0; q < hi - lo; ++q) {
+      const int round = q / Tg, idx = q % Tg;
+      const int tile = tp.first[g] + ((round & 1) ? Tg - 1 - idx : idx);
+      tslot[order[lo + q]] = tile * R + round;
+      rows[(size_t)tile * R + round] = order[lo + q];
+    }
+    for (int t = tp.first[g]; t < tp.first[g + 1]; ++t) {
+      wlo[t] = lo >> kTileColBits;
+      tgraph[t] = g;
+      boff[t + 1] = boff[t] + tp.nw[g];
+    }
   }
   int *rows_d = nullptr, *bstart_d = nullptr, *tslot_d = nullptr;
+  int *wlo_d = nullptr, *boff_d = nullptr, *tgraph_d = nullptr;
   uint2* ent_d = nullptr;
   unsigned *keys = nullptr, *vals = nullptr, *kt = nullptr, *vt = nullptr;
   int *hist = nullptr, *tsum = nullptr;
@@ -517,24 +567,34 @@ int build_tiles(Problem& P, hipStream_t s) {
   };
   int rc;
   if ((rc = alloc(&rows_d, (size_t)T * R, "tile rows")) ||
+      (rc = alloc(&wlo_d, (size_t)T, "tile windows")) ||
+      (rc = alloc(&boff_d, (size_t)T + 1, "tile block offsets")) ||
+      (rc = alloc(&tgraph_d, (size_t)T, "tile graphs")) ||
       (rc = alloc(&bstart_d, (size_t)nb + 1, "tile blocks")) ||
       (rc = alloc(&ent_d, (size_t)nnz, "tile entries")) ||
       (rc = alloc(&tslot_d, (size_t)n, "tile slots")) || (rc = alloc(&keys, (size_t)nnz, "keys")) ||
       (rc = alloc(&vals, (size_t)nnz, "vals")) || (rc = alloc(&kt, (size_t)nnz, "keys")) ||
       (rc = alloc(&vt, (size_t)nnz, "vals")) || (rc = alloc(&hist, (size_t)hist_len + 1, "hist")) ||
       (rc = alloc(&tsum, (size_t)tsum_len, "scan"))) {
-    release({rows_d, bstart_d, ent_d, tslot_d, keys, vals, kt, vt, hist, tsum});
+    release({rows_d, wlo_d, boff_d, tgraph_d, bstart_d, ent_d, tslot_d, keys, vals, kt, vt, hist,
+             tsum});
     return rc;
   }
   hipError_t e = hipMemcpyAsync(rows_d, rows.data(), sizeof(int) * rows.size(),
                                 hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
+    e = hipMemcpyAsync(wlo_d, wlo.data(), sizeof(int) * T, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(boff_d, boff.data(), sizeof(int) * (T + 1), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(tgraph_d, tgraph.data(), sizeof(int) * T, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
     e = hipMemcpyAsync(tslot_d, tslot.data(), sizeof(int) * n, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) {
     int wb = (n + 3) / 4;
     if (wb > 16384) wb = 16384;
-    hipLaunchKernelGGL(k_tile_keys, dim3(wb), dim3(256), 0, s, P.rowptr, P.col, tslot_d, n, R, NC,
-                       keys, vals);
+    hipLaunchKernelGGL(k_tile_keys, dim3(wb), dim3(256), 0, s, P.rowptr, P.col, tslot_d, n, R,
+                       wlo_d, boff_d, keys, vals);
     int bits = kTileSlotBits;
     while (((int64_t)1 << (bits - kTileSlotBits)) <= nb) ++bits;
     e = hipGetLastError();
@@ -553,15 +613,18 @@ int build_tiles(Problem& P, hipStream_t s) {
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   release({tslot_d, keys, vals, kt, vt, hist, tsum});
   if (e != hipSuccess) {
-    release({rows_d, bstart_d, ent_d});
+    release({rows_d, wlo_d, boff_d, tgraph_d, bstart_d, ent_d});
     return fail(TSNET_EHIP, std::string("tiled layout: ") + hipGetErrorString(e));
   }
   P.tile_rows = rows_d;
+  P.tile_wlo = wlo_d;
+  P.tile_boff = boff_d;
+  P.tile_graph = tgraph_d;
   P.tile_bstart = bstart_d;
   P.tile_ent = ent_d;
   P.tile_T = T;
   P.tile_R = R;
-  P.tile_NC = NC;
+  P.tile_NB = nb;
   return TSNET_OK;
 }
 

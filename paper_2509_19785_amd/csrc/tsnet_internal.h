@@ -157,9 +157,13 @@ struct Problem {
   int* row_order = nullptr;           // [n] rows by decreasing length (attraction order)
   int attract_blocks = 0;             // blocks of the row attraction the device holds at once
   // device: tiled copy of P for the attraction (row tiles x column windows)
-  int tile_T = 0, tile_R = 0, tile_NC = 0;  // row tiles, slots per tile, column windows
+  int tile_T = 0, tile_R = 0;         // row tiles, slots per tile
+  int64_t tile_NB = 0;                // blocks (tile, column window) in all
   int* tile_rows = nullptr;           // [T * R] vertex of each slot, -1 if unused
-  int* tile_bstart = nullptr;         // [T * NC + 1] first entry of each block
+  int* tile_wlo = nullptr;            // [T] first column window of each tile
+  int* tile_boff = nullptr;           // [T + 1] first block of each tile
+  int* tile_graph = nullptr;          // [T] graph of each tile's rows
+  int* tile_bstart = nullptr;         // [NB + 1] first entry of each block
   uint2* tile_ent = nullptr;          // [nnz] {slot << 13 | column in window, value bits}
   // device: conditional rows and calibration (absent for host-made P)
   double* beta = nullptr;
@@ -255,7 +259,7 @@ hipError_t launch_copy_terms(Problem& P, float2* F_rep, float2* F_ent, float* Z_
 int build_row_order(Problem& P);
 
 // tiled copy of P for the attraction (tile.hip), built once per problem
-bool tiles_supported(int n);
+bool tiles_supported(const Problem& P);
 int build_tiles(Problem& P, hipStream_t s);
 
 // stable LSD radix sort of (key, value) pairs by the low `bits` key bits, 8-bit

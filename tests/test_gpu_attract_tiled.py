@@ -114,6 +114,30 @@ def test_random_sparse(api, ctx, n, mean_len, hubs, hub_len, empty, seed):
                      max_intervals=64)
 
 
+def test_batch_tiles_per_graph(api, ctx):
+    """A batch whose graphs start and end inside column windows: graphs of 1,
+    300 and 5000 vertices sharing windows, one of 20000 spanning four, hub
+    rows and empty rows. Each graph's rows get tiles of their own that walk
+    only the windows of that graph."""
+    sizes = [5000, 1, 12000, 300, 20000, 9000, 1, 7000]
+    parts, off = [], [0]
+    for k, m in enumerate(sizes):
+        if m == 1:
+            parts.append((np.zeros(2, np.int64), np.zeros(0, np.int32), np.zeros(0)))
+        else:
+            parts.append(graphs.random_affinity(m, 25.0, 40 + k, 2 if m > 1000 else 0,
+                                                min(m - 1, 3000), 0.1))
+        off.append(off[-1] + m)
+    rowptr = np.concatenate([[0]] + [p[0][1:] + sum(q[1].shape[0] for q in parts[:k])
+                                     for k, p in enumerate(parts)]).astype(np.int64)
+    col = np.concatenate([p[1] + off[k] for k, p in enumerate(parts)]).astype(np.int32)
+    val = np.concatenate([p[2] for p in parts])
+    goff = np.asarray(off, np.int64)
+    X = graphs.initial_layout(off[-1], 8, std=3.0)
+    _compare_layouts(api, ctx, rowptr, col, val, X, "batch of 8, windows shared and spanned",
+                     goff=goff, min_intervals=8, max_intervals=64)
+
+
 def test_empty_P(api, ctx):
     n = 5000
     rowptr = np.zeros(n + 1, np.int64)
