@@ -173,7 +173,6 @@ static void free_problem(Problem& P) {
   dfree(P.cond_dist);
   dfree(P.desc);
   dfree(P.bbox_part);
-  dfree(P.counters);
   dfree(P.btotal);
   dfree(P.keys);
   dfree(P.keys_tmp);
@@ -256,7 +255,7 @@ static int init_problem(Ctx& c, Problem& P, int n, const int32_t* goff_host, int
   if ((rc = dmalloc(&P.ginfo, G, "ginfo")) || (rc = dmalloc(&P.goff_d, G + 1, "goff")) ||
       (rc = dmalloc(&P.chunk_graph, nc, "chunks")) || (rc = dmalloc(&P.chunk_start, nc, "chunks")) ||
       (rc = dmalloc(&P.chunk_end, nc, "chunks")) || (rc = dmalloc(&P.desc, G, "desc")) ||
-      (rc = dmalloc(&P.bbox_part, nc, "bbox")) || (rc = dmalloc(&P.counters, 8, "counters")) ||
+      (rc = dmalloc(&P.bbox_part, nc, "bbox")) ||
       (rc = dmalloc(&P.btotal, 1, "btotal")) || (rc = dmalloc(&P.keys, n, "keys")) ||
       (rc = dmalloc(&P.keys_tmp, n, "keys")) || (rc = dmalloc(&P.perm_tmp, n, "perm")) ||
       (rc = dmalloc(&P.perm_tmp2, n, "perm")) || (rc = dmalloc(&P.skeys, n, "keys")) ||
@@ -284,7 +283,6 @@ static int init_problem(Ctx& c, Problem& P, int n, const int32_t* goff_host, int
   TSNET_HIP(hipMemcpy(P.chunk_graph, cg.data(), sizeof(int) * nc, hipMemcpyHostToDevice));
   TSNET_HIP(hipMemcpy(P.chunk_start, cs.data(), sizeof(int) * nc, hipMemcpyHostToDevice));
   TSNET_HIP(hipMemcpy(P.chunk_end, ce.data(), sizeof(int) * nc, hipMemcpyHostToDevice));
-  TSNET_HIP(hipMemset(P.counters, 0, sizeof(unsigned) * 8));
   TSNET_HIP(hipMemset(P.zg, 0, sizeof(double) * G));
   return TSNET_OK;
 }

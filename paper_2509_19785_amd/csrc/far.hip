@@ -19,6 +19,7 @@
 // One launch, blocks (j, g): j < nbx take far points j, j + nbx, ... of graph
 // g (a block sums over all nodes of the graph), j >= nbx sweep the graph's
 // nodes with its far points staged in LDS. Every sum runs in a fixed order.
+// Kernel values use the hardware reciprocal (1 ulp).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -30,7 +31,7 @@ namespace tsnet {
 
 constexpr int kFarThreads = 512;
 constexpr int kFarBatch = 512;  // far points staged in LDS at a time (node role)
-constexpr int kFarNodes = 4;    // nodes a thread loads ahead per step (far-point role)
+constexpr int kFarNodes = 8;    // nodes a thread loads ahead per step (far-point role)
 constexpr int kFarSums = 14;    // 8 node channels + 6 far-far direct sums
 
 struct FarArgs {
@@ -88,9 +89,9 @@ __global__ __launch_bounds__(kFarThreads) void k_far(FarArgs A) {
             const float dx = xo.x - (d.x0 + ((float)ax + 0.5f) * d.spacing);
             const float dy = xo.y - (d.y0 + ((float)ay + 0.5f) * d.spacing);
             const float r2 = dx * dx + dy * dy;
-            const float k1 = 1.0f / (1.0f + r2);
+            const float k1 = __builtin_amdgcn_rcpf(1.0f + r2);
             const float k2 = k1 * k1;
-            const float ke = 1.0f / (A.eps + r2);
+            const float ke = __builtin_amdgcn_rcpf(A.eps + r2);
             acc[0] += k2 * w1[u];
             acc[1] += k2 * wx[u];
             acc[2] += k2 * wy[u];
@@ -107,9 +108,9 @@ __global__ __launch_bounds__(kFarThreads) void k_far(FarArgs A) {
         const float2 xq = A.xs[q];
         const float dx = xo.x - xq.x, dy = xo.y - xq.y;
         const float r2 = dx * dx + dy * dy;
-        const float k1 = 1.0f / (1.0f + r2);
+        const float k1 = __builtin_amdgcn_rcpf(1.0f + r2);
         const float k2 = k1 * k1;
-        const float ke = 1.0f / (A.eps + r2);
+        const float ke = __builtin_amdgcn_rcpf(A.eps + r2);
         acc[8] += k2 * dx;
         acc[9] += k2 * dy;
         acc[10] += ke * dx;
@@ -170,9 +171,9 @@ __global__ __launch_bounds__(kFarThreads) void k_far(FarArgs A) {
           const float4 o = fp[q];
           const float dx = nx - o.x, dy = ny - o.y;
           const float r2 = dx * dx + dy * dy;
-          const float k1 = 1.0f / (1.0f + r2);
+          const float k1 = __builtin_amdgcn_rcpf(1.0f + r2);
           const float k2 = k1 * k1;
-          const float ke = 1.0f / (A.eps + r2);
+          const float ke = __builtin_amdgcn_rcpf(A.eps + r2);
           acc[CH_K2_1] += k2;
           acc[CH_K2_X] += k2 * o.z;
           acc[CH_K2_Y] += k2 * o.w;

@@ -13,38 +13,52 @@
 namespace tsnet {
 
 // ---------------------------------------------------------------------------
-// Bounding box per chunk; the last block to finish reduces the boxes of every
-// graph and starts its descriptor: the box, the bin scales of the far-point
+// Bounding box per chunk (k_bbox_part, the bounds of every chunk to
+// part[chunk]); then one wave per graph reduces its chunks and starts the
+// graph's descriptor (k_bbox_join): the box, the bin scales of the far-point
 // rule and whether that rule can apply (t = min(far_trim, n / 64) >= 1 and a
 // positive width). The grid itself is planned by k_trim_plan.
-// One block of kChunkThreads per chunk (a few vertices per thread); the bounds
-// of every chunk go to part[chunk]. One counter update per chunk: many more
-// blocks would queue on it.
+//
+// Partial results pass between blocks through a kernel boundary, never
+// through a last-block counter: on this GPU a device-wide fence writes back
+// and invalidates the L2 of the block's XCD, and one per block cost more than
+// the work it guards.
 constexpr int kChunkThreads = 1024;
 constexpr int kPartBatch = 8;  // chunk partials a lane of the final reduction loads at once
 
-__global__ __launch_bounds__(kChunkThreads) void k_bbox_plan(
-    const float2* __restrict__ X, const int* __restrict__ chunk_start,
-    const int* __restrict__ chunk_end, int nblocks, float4* part, unsigned* counter,
-    const GraphInfo* __restrict__ gi, int G, PlanParams pp, GridDesc* desc) {
-  __shared__ float red[kChunkThreads / kWave][4];
+constexpr int kBboxThreads = 256;
+constexpr int kBboxPer = kChunk / kBboxThreads;  // points per thread, loaded together
+
+// Per chunk: the bounding box of its finite points, NaN in part[c].x when the
+// chunk holds a non-finite coordinate.
+__global__ __launch_bounds__(kBboxThreads) void k_bbox_part(const float2* __restrict__ X,
+                                                            const int* __restrict__ chunk_start,
+                                                            const int* __restrict__ chunk_end,
+                                                            float4* part) {
+  __shared__ float red[kBboxThreads / kWave][4];
   __shared__ int bad_s;
-  __shared__ int last_s;
   const int c = blockIdx.x;
   if (threadIdx.x == 0) bad_s = 0;
   __syncthreads();
   float xmn = FLT_MAX, xmx = -FLT_MAX, ymn = FLT_MAX, ymx = -FLT_MAX;
   int bad = 0;
-  for (int i = chunk_start[c] + threadIdx.x; i < chunk_end[c]; i += kChunkThreads) {
-    const float2 p = X[i];
-    if (!(isfinite(p.x) && isfinite(p.y))) {
-      bad = 1;
-      continue;
+  {
+    const int i0 = chunk_start[c] + threadIdx.x, i1 = chunk_end[c];
+    float2 p[kBboxPer];
+#pragma unroll
+    for (int u = 0; u < kBboxPer; ++u) p[u] = X[min(i0 + u * kBboxThreads, i1 - 1)];
+#pragma unroll
+    for (int u = 0; u < kBboxPer; ++u) {
+      if (i0 + u * kBboxThreads >= i1) continue;
+      if (!(isfinite(p[u].x) && isfinite(p[u].y))) {
+        bad = 1;
+        continue;
+      }
+      xmn = fminf(xmn, p[u].x);
+      xmx = fmaxf(xmx, p[u].x);
+      ymn = fminf(ymn, p[u].y);
+      ymx = fmaxf(ymx, p[u].y);
     }
-    xmn = fminf(xmn, p.x);
-    xmx = fmaxf(xmx, p.x);
-    ymn = fminf(ymn, p.y);
-    ymx = fmaxf(ymx, p.y);
   }
   xmn = wave_min(xmn);
   xmx = wave_max(xmx);
@@ -59,73 +73,72 @@ __global__ __launch_bounds__(kChunkThreads) void k_bbox_plan(
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int w = 1; w < (int)(blockDim.x / kWave); ++w) {
+    for (int w = 1; w < kBboxThreads / kWave; ++w) {
       xmn = fminf(xmn, red[w][0]);
       xmx = fmaxf(xmx, red[w][1]);
       ymn = fminf(ymn, red[w][2]);
       ymx = fmaxf(ymx, red[w][3]);
     }
     part[c] = make_float4(bad_s ? NAN : xmn, xmx, ymn, ymx);
-    __threadfence();
-    const unsigned prev = atomicAdd(counter, 1u);
-    last_s = (prev == (unsigned)(nblocks - 1));
   }
-  __syncthreads();
-  if (!last_s) return;
-  __threadfence();
-  // one wave per graph: lanes stride over the graph's chunks
-  for (int g = wave_id(); g < G; g += blockDim.x / kWave) {
-    float a = FLT_MAX, b = -FLT_MAX, e = FLT_MAX, f = -FLT_MAX;
-    int nonfinite = 0;
-    const int c1 = gi[g].chunk_end;
-    for (int k0 = gi[g].chunk_begin + lane_id(); k0 < c1; k0 += kPartBatch * kWave) {
-      float4 q[kPartBatch];  // the batch's loads in flight together
+}
+
+// One wave per graph: the graph's box from its chunks, and the far-point
+// rule's parameters (bins, trimming count).
+__global__ __launch_bounds__(256) void k_bbox_join(const float4* __restrict__ part,
+                                                   const GraphInfo* __restrict__ gi, int G,
+                                                   PlanParams pp, GridDesc* desc) {
+  const int g = blockIdx.x * (256 / kWave) + wave_id();
+  if (g >= G) return;
+  float a = FLT_MAX, b = -FLT_MAX, e = FLT_MAX, f = -FLT_MAX;
+  int nonfinite = 0;
+  const int c1 = gi[g].chunk_end;
+  for (int k0 = gi[g].chunk_begin + lane_id(); k0 < c1; k0 += kPartBatch * kWave) {
+    float4 q[kPartBatch];  // the batch's loads in flight together
 #pragma unroll
-      for (int j = 0; j < kPartBatch; ++j)
-        q[j] = k0 + j * kWave < c1 ? ld_coherent4(&part[k0 + j * kWave])
-                                   : make_float4(FLT_MAX, -FLT_MAX, FLT_MAX, -FLT_MAX);
+    for (int j = 0; j < kPartBatch; ++j)
+      q[j] = k0 + j * kWave < c1 ? part[k0 + j * kWave]
+                                 : make_float4(FLT_MAX, -FLT_MAX, FLT_MAX, -FLT_MAX);
 #pragma unroll
-      for (int j = 0; j < kPartBatch; ++j) {
-        if (isnan(q[j].x)) nonfinite = 1;
-        if (q[j].y >= q[j].x) {  // chunk had at least one finite point
-          a = fminf(a, q[j].x);
-          b = fmaxf(b, q[j].y);
-          e = fminf(e, q[j].z);
-          f = fmaxf(f, q[j].w);
-        }
+    for (int j = 0; j < kPartBatch; ++j) {
+      if (isnan(q[j].x)) nonfinite = 1;
+      if (q[j].y >= q[j].x) {  // chunk had at least one finite point
+        a = fminf(a, q[j].x);
+        b = fmaxf(b, q[j].y);
+        e = fminf(e, q[j].z);
+        f = fmaxf(f, q[j].w);
       }
     }
-    a = wave_min(a);
-    b = wave_max(b);
-    e = wave_min(e);
-    f = wave_max(f);
-    nonfinite = __any(nonfinite);
-    if (lane_id() != 0) continue;
-    if (!(b >= a)) {  // no finite point at all
-      a = b = e = f = 0.f;
-    }
-    GridDesc d = {};
-    d.bmin_x = a;
-    d.bmax_x = b;
-    d.bmin_y = e;
-    d.bmax_y = f;
-    d.flags = nonfinite ? TSNET_STATUS_NONFINITE : 0;
-    const double wx = (double)b - (double)a, wy = (double)f - (double)e;
-    d.s_x = wx > 0.0 ? (double)kTrimBins / wx : 0.0;
-    d.s_y = wy > 0.0 ? (double)kTrimBins / wy : 0.0;
-    const int t = min(pp.far_trim, gi[g].n / kTrimMinPoints);
-    d.trim_t = t;
-    d.trimmed = (t >= 1 && fmax(wx, wy) > 0.0 && !nonfinite) ? 1 : 0;
-    desc[g] = d;
   }
-  __syncthreads();
-  if (threadIdx.x == 0) *counter = 0u;
+  a = wave_min(a);
+  b = wave_max(b);
+  e = wave_min(e);
+  f = wave_max(f);
+  nonfinite = __any(nonfinite);
+  if (lane_id() != 0) return;
+  if (!(b >= a)) {  // no finite point at all
+    a = b = e = f = 0.f;
+  }
+  GridDesc d = {};
+  d.bmin_x = a;
+  d.bmax_x = b;
+  d.bmin_y = e;
+  d.bmax_y = f;
+  d.flags = nonfinite ? TSNET_STATUS_NONFINITE : 0;
+  const double wx = (double)b - (double)a, wy = (double)f - (double)e;
+  d.s_x = wx > 0.0 ? (double)kTrimBins / wx : 0.0;
+  d.s_y = wy > 0.0 ? (double)kTrimBins / wy : 0.0;
+  const int t = min(pp.far_trim, gi[g].n / kTrimMinPoints);
+  d.trim_t = t;
+  d.trimmed = (t >= 1 && fmax(wx, wy) > 0.0 && !nonfinite) ? 1 : 0;
+  desc[g] = d;
 }
 
 hipError_t launch_bbox_plan(Problem& P, const float2* X, const PlanParams& pp, hipStream_t s) {
-  hipLaunchKernelGGL(k_bbox_plan, dim3(P.num_chunks), dim3(kChunkThreads), 0, s, X, P.chunk_start,
-                     P.chunk_end, P.num_chunks, P.bbox_part, P.counters + 0, P.ginfo, P.G, pp,
-                     P.desc);
+  hipLaunchKernelGGL(k_bbox_part, dim3(P.num_chunks), dim3(kBboxThreads), 0, s, X, P.chunk_start,
+                     P.chunk_end, P.bbox_part);
+  hipLaunchKernelGGL(k_bbox_join, dim3((P.G + 3) / 4), dim3(256), 0, s, P.bbox_part, P.ginfo, P.G,
+                     pp, P.desc);
   return hipGetLastError();
 }
 
@@ -177,16 +190,15 @@ __global__ __launch_bounds__(kTrimThreads) void k_trim_hist(
 // grid centred on the region. Decisions in FP64 with every operation rounded
 // on its own (no contraction), so the far points and the grid are those of
 // the same rule evaluated anywhere else in IEEE FP64. The counts are cleared
-// for the next call. The last block to finish numbers the boxes of the batch.
+// for the next call. Then k_plan_pools (one block) sizes the batch's grid
+// buffers, fits them into the workspace pools and numbers the boxes.
 constexpr int kPlanThreads = 256;
 constexpr int kPlanBins = kTrimBins / kPlanThreads;  // consecutive bins per thread
 
-__global__ __launch_bounds__(kPlanThreads) void k_trim_plan(
-    GridDesc* desc, int G, int* hist, PlanParams pp, unsigned* counter, int* btotal,
-    unsigned* status) {
+__global__ __launch_bounds__(kPlanThreads) void k_trim_plan(GridDesc* desc, int* hist,
+                                                             PlanParams pp, unsigned* status) {
   __shared__ int sh[kPlanThreads / kWave + 1];
   __shared__ int bounds[4];  // lo_x, hi_x, lo_y, hi_y
-  __shared__ int last_s;
   const int g = blockIdx.x;
   GridDesc d = desc[g];
   if (d.trimmed) {  // uniform over the block
@@ -271,18 +283,18 @@ __global__ __launch_bounds__(kPlanThreads) void k_trim_plan(
     d.flags = flags;
     desc[g] = d;
     if (flags) atomicOr(status, (unsigned)flags);
-    __threadfence();
-    last_s = (atomicAdd(counter, 1u) == (unsigned)(G - 1));
   }
-  __syncthreads();
-  if (!last_s) return;
-  __threadfence();
-  // the grid buffers every graph needs, before and after fitting them into
-  // the workspace pools (the whole block: one graph per thread and step)
+}
+
+// The grid buffers every graph needs, before and after fitting them into the
+// workspace pools, then the box ids and pool offsets of every graph (one
+// block: one graph per thread and step).
+__global__ __launch_bounds__(kPlanThreads) void k_plan_pools(GridDesc* desc, int G, PlanParams pp,
+                                                              int* btotal, unsigned* status) {
   __shared__ unsigned long long red_need[POOL_KINDS][kPlanThreads / kWave];
   size_t need[POOL_KINDS] = {0, 0, 0, 0, 0};
   for (int gg = threadIdx.x; gg < G; gg += kPlanThreads) {
-    const int ni = ld_coherent(&desc[gg].n_int);
+    const int ni = desc[gg].n_int;
     for (int k = 0; k < POOL_KINDS; ++k) need[k] += pool_elems(k, ni);
   }
   for (int k = 0; k < POOL_KINDS; ++k) {
@@ -311,7 +323,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_trim_plan(
         if (fits) break;
         int big = -1, bn = 1;
         for (int gg = 0; gg < G; ++gg) {
-          const int ni = ld_coherent(&desc[gg].n_int);
+          const int ni = ld_coherent(&desc[gg].n_int);  // this thread's own stores included
           if (ni > bn) {
             bn = ni;
             big = gg;
@@ -335,7 +347,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_trim_plan(
         d2.M = 2 * kNodes * nn;
         d2.flags |= (int)raised;
         desc[big] = d2;
-        __threadfence();  // the coherent reads of n_int above see the new value
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // stored before it is read again
       }
       atomicOr(status, raised);
     }
@@ -380,10 +392,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_trim_plan(
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    *btotal = carry_box;
-    *counter = 0u;
-  }
+  if (threadIdx.x == 0) *btotal = carry_box;
 }
 
 hipError_t launch_trim_plan(Problem& P, const float2* X, const PlanParams& pp, bool with_hist,
@@ -391,8 +400,10 @@ hipError_t launch_trim_plan(Problem& P, const float2* X, const PlanParams& pp, b
   if (with_hist)
     hipLaunchKernelGGL(k_trim_hist, dim3(P.num_chunks), dim3(kTrimThreads), 0, s, X, P.chunk_graph,
                        P.chunk_start, P.chunk_end, P.desc, P.trim_hist);
-  hipLaunchKernelGGL(k_trim_plan, dim3(P.G), dim3(kPlanThreads), 0, s, P.desc, P.G, P.trim_hist, pp,
-                     P.counters + 3, P.btotal, P.ctx->status);
+  hipLaunchKernelGGL(k_trim_plan, dim3(P.G), dim3(kPlanThreads), 0, s, P.desc, P.trim_hist, pp,
+                     P.ctx->status);
+  hipLaunchKernelGGL(k_plan_pools, dim3(1), dim3(kPlanThreads), 0, s, P.desc, P.G, pp, P.btotal,
+                     P.ctx->status);
   return hipGetLastError();
 }
 
@@ -407,20 +418,18 @@ hipError_t launch_trim_plan(Problem& P, const float2* X, const PlanParams& pp, b
 // graph) were summed by k_far: their F_rep and F_ent are in place, their Z_i
 // and ln sum come from slot_z and slot_ln.
 // One block of kChunkThreads per chunk. Each block also sums the Z_i of its
-// chunk (compensated FP32, in sorted order) into zpart[chunk]; the last block
-// to finish adds the chunk sums of every graph in FP64 (fixed order, so Z is
-// reproducible) into zg and Z_out.
+// chunk (compensated FP32, in sorted order) into zpart[chunk]; k_zsum then
+// adds every graph's chunk sums in FP64 (fixed order, so Z is reproducible)
+// into zg and Z_out.
 __global__ __launch_bounds__(kChunkThreads) void k_gather(
     const float2* __restrict__ xs, const int* __restrict__ skeys, const int* __restrict__ perm,
     const int* __restrict__ chunk_graph, const int* __restrict__ chunk_start,
     const int* __restrict__ chunk_end, const GridDesc* __restrict__ desc,
     const GraphInfo* __restrict__ gi, int G, const float* __restrict__ pot,
     const float* __restrict__ slot_z, const float* __restrict__ slot_ln, float4* rep_ent,
-    float* zi, float* lnv, double* zpart, unsigned* counter, int nblocks, double* zg,
-    double* Z_out) {
+    float* zi, float* lnv, double* zpart) {
   constexpr int NW = kChunkThreads / kWave;
   __shared__ float sh_hi[NW], sh_lo[NW];
-  __shared__ int last_s;
   const int c = blockIdx.x;
   const int g = chunk_graph[c];
   const GridDesc d = desc[g];
@@ -490,30 +499,29 @@ __global__ __launch_bounds__(kChunkThreads) void k_gather(
     double v = 0.0;
     for (int w = 0; w < NW; ++w) v += (double)sh_hi[w] + (double)sh_lo[w];
     zpart[c] = v;
-    __threadfence();
-    last_s = (atomicAdd(counter, 1u) == (unsigned)(nblocks - 1));
   }
-  __syncthreads();
-  if (!last_s) return;
-  __threadfence();
-  for (int gg = wave_id(); gg < G; gg += blockDim.x / kWave) {
-    double z = 0.0;
-    const int c1 = gi[gg].chunk_end;
-    for (int k0 = gi[gg].chunk_begin + lane_id(); k0 < c1; k0 += kPartBatch * kWave) {
-      double q[kPartBatch];  // the batch's loads in flight together
+}
+
+// One wave per graph: Z = the graph's chunk sums added in FP64 in chunk order.
+__global__ __launch_bounds__(256) void k_zsum(const double* __restrict__ zpart,
+                                              const GraphInfo* __restrict__ gi, int G, double* zg,
+                                              double* Z_out) {
+  const int g = blockIdx.x * (256 / kWave) + wave_id();
+  if (g >= G) return;
+  double z = 0.0;
+  const int c1 = gi[g].chunk_end;
+  for (int k0 = gi[g].chunk_begin + lane_id(); k0 < c1; k0 += kPartBatch * kWave) {
+    double q[kPartBatch];  // the batch's loads in flight together
 #pragma unroll
-      for (int j = 0; j < kPartBatch; ++j)
-        q[j] = k0 + j * kWave < c1 ? ld_coherent(&zpart[k0 + j * kWave]) : 0.0;
+    for (int j = 0; j < kPartBatch; ++j) q[j] = k0 + j * kWave < c1 ? zpart[k0 + j * kWave] : 0.0;
 #pragma unroll
-      for (int j = 0; j < kPartBatch; ++j) z += q[j];
-    }
-    z = wave_sum(z);
-    if (lane_id() == 0) {
-      zg[gg] = z;
-      if (Z_out) Z_out[gg] = z;
-    }
+    for (int j = 0; j < kPartBatch; ++j) z += q[j];
   }
-  if (threadIdx.x == 0) *counter = 0u;
+  z = wave_sum(z);
+  if (lane_id() == 0) {
+    zg[g] = z;
+    if (Z_out) Z_out[g] = z;
+  }
 }
 
 hipError_t launch_gather(Problem& P, const float2* X, int with_ln, int with_zi, double* Z_out,
@@ -522,8 +530,8 @@ hipError_t launch_gather(Problem& P, const float2* X, int with_ln, int with_zi, 
   const int nb = P.num_chunks;
   hipLaunchKernelGGL(k_gather, dim3(nb), dim3(kChunkThreads), 0, s, P.xs, P.skeys, P.perm, P.chunk_graph,
                      P.chunk_start, P.chunk_end, P.desc, P.ginfo, P.G, P.pot,
-                     P.slot_z, P.slot_ln, P.rep_ent, with_zi ? P.zi : nullptr, with_ln ? P.lnv : nullptr, P.zpart,
-                     P.counters + 1, nb, P.zg, Z_out);
+                     P.slot_z, P.slot_ln, P.rep_ent, with_zi ? P.zi : nullptr, with_ln ? P.lnv : nullptr, P.zpart);
+  hipLaunchKernelGGL(k_zsum, dim3((P.G + 3) / 4), dim3(256), 0, s, P.zpart, P.ginfo, P.G, P.zg, Z_out);
   return hipGetLastError();
 }
 
@@ -609,12 +617,9 @@ struct CostK {
 
 __global__ __launch_bounds__(256) void k_cost_reduce(
     const float2* __restrict__ X, const float2* __restrict__ rowv, const float* __restrict__ lnv,
-    const double* __restrict__ zg, const int* __restrict__ chunk_start,
-    const int* __restrict__ chunk_end, int num_chunks, double* part, unsigned* counter,
-    const GraphInfo* __restrict__ gi, int G, CostK ck, double* cost) {
+    const int* __restrict__ chunk_start, const int* __restrict__ chunk_end, double* part) {
   constexpr int NQ = kCostTerms;
   __shared__ float sh[NQ][2][4];
-  __shared__ int last_s;
   const int c = blockIdx.x;
   CompSum acc[NQ];
   for (int i = chunk_start[c] + threadIdx.x; i < chunk_end[c]; i += blockDim.x) {
@@ -640,18 +645,23 @@ __global__ __launch_bounds__(256) void k_cost_reduce(
       for (int w = 0; w < 4; ++w) v += (double)sh[q][0][w] + (double)sh[q][1][w];
       part[(size_t)c * NQ + q] = v;
     }
-    __threadfence();
-    last_s = (atomicAdd(counter, 1u) == (unsigned)(num_chunks - 1));
   }
-  __syncthreads();
-  if (!last_s) return;
-  __threadfence();
-  for (int g = wave_id(); g < G; g += blockDim.x / kWave) {
+}
+
+// One wave per graph: the chunk sums in chunk order, then the cost terms.
+__global__ __launch_bounds__(256) void k_cost_join(const double* __restrict__ part,
+                                                   const double* __restrict__ zg,
+                                                   const GraphInfo* __restrict__ gi, int G,
+                                                   CostK ck, double* cost) {
+  constexpr int NQ = kCostTerms;
+  const int g = blockIdx.x * (256 / kWave) + wave_id();
+  if (g >= G) return;
+  {
     double s[NQ] = {0, 0, 0, 0};
     for (int k = gi[g].chunk_begin + lane_id(); k < gi[g].chunk_end; k += kWave)
-      for (int q = 0; q < NQ; ++q) s[q] += ld_coherent(&part[(size_t)k * NQ + q]);
+      for (int q = 0; q < NQ; ++q) s[q] += part[(size_t)k * NQ + q];
     for (int q = 0; q < NQ; ++q) s[q] = wave_sum(s[q]);
-    if (lane_id() != 0) continue;
+    if (lane_id() != 0) return;
     const double n = (double)gi[g].n;
     const double Z = zg[g];
     const double kl = (n > 1 && Z > 0) ? ck.lkl * (s[0] + s[1] * log(Z)) : 0.0;
@@ -662,7 +672,6 @@ __global__ __launch_bounds__(256) void k_cost_reduce(
     cost[g * 4 + 2] = en;
     cost[g * 4 + 3] = kl + cm + en;
   }
-  if (threadIdx.x == 0) *counter = 0u;
 }
 
 hipError_t launch_cost(Problem& P, const float2* X, const tsnet_params& prm, double* cost,
@@ -674,8 +683,9 @@ hipError_t launch_cost(Problem& P, const float2* X, const tsnet_params& prm, dou
   hipLaunchKernelGGL(k_cost_rows, dim3(blocks), dim3(256), 0, s, X, P.rowptr, P.col, P.val, P.n,
                      rowv);
   CostK ck{prm.lambda_kl, prm.lambda_c, prm.lambda_r, log(prm.eps_r)};
-  hipLaunchKernelGGL(k_cost_reduce, dim3(P.num_chunks), dim3(256), 0, s, X, rowv, P.lnv, P.zg,
-                     P.chunk_start, P.chunk_end, P.num_chunks, P.cost_part, P.counters + 2, P.ginfo,
+  hipLaunchKernelGGL(k_cost_reduce, dim3(P.num_chunks), dim3(256), 0, s, X, rowv, P.lnv,
+                     P.chunk_start, P.chunk_end, P.cost_part);
+  hipLaunchKernelGGL(k_cost_join, dim3((P.G + 3) / 4), dim3(256), 0, s, P.cost_part, P.zg, P.ginfo,
                      P.G, ck, cost);
   return hipGetLastError();
 }

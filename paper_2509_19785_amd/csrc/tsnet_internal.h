@@ -175,7 +175,6 @@ struct Problem {
   int cap = 0;                        // max_intervals the grid buffers are sized for
   GridDesc* desc = nullptr;           // [G]
   float4* bbox_part = nullptr;        // [num_chunks]
-  unsigned* counters = nullptr;       // [8] last-block counters (kept at zero)
   int* btotal = nullptr;              // [1] total boxes of the batch
   int* keys = nullptr;                // [n] box id of every vertex
   int* keys_tmp = nullptr;            // [n] radix ping-pong
