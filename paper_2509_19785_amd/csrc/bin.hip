@@ -247,8 +247,9 @@ __device__ __forceinline__ void node_store(float* out, int ng, int bx, int by, c
     }
 }
 
-__device__ __forceinline__ int graph_of_box(const GridDesc* __restrict__ desc, int G, int key) {
-  int lo = 0, hi = G;
+// Graph of global box id `key` among graphs [lo, hi) (key lies in one of them).
+__device__ __forceinline__ int graph_of_box(const GridDesc* __restrict__ desc, int lo, int hi,
+                                            int key) {
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
     if (desc[mid].box_base <= key) lo = mid; else hi = mid;
@@ -262,9 +263,10 @@ struct BoxAt {
   GridDesc d;
 };
 
-__device__ __forceinline__ BoxAt box_at(const GridDesc* __restrict__ desc, int G, int key) {
+__device__ __forceinline__ BoxAt box_at(const GridDesc* __restrict__ desc, int glo, int ghi,
+                                        int key) {
   BoxAt b;
-  b.g = G == 1 ? 0 : graph_of_box(desc, G, key);
+  b.g = ghi - glo == 1 ? glo : graph_of_box(desc, glo, ghi, key);
   b.d = desc[b.g];
   const int local = key - b.d.box_base;
   b.far = local == b.d.n_int * b.d.n_int;
@@ -273,17 +275,16 @@ __device__ __forceinline__ BoxAt box_at(const GridDesc* __restrict__ desc, int G
   return b;
 }
 
-__device__ __forceinline__ bool is_far_key(const GridDesc* __restrict__ desc, int G, int key) {
-  const GridDesc& d = desc[G == 1 ? 0 : graph_of_box(desc, G, key)];
-  return key == far_key(d);
+__device__ __forceinline__ bool is_far_key(const GridDesc* __restrict__ desc, int g, int key) {
+  return key == far_key(desc[g]);
 }
 
 // Adds the 27 node contributions of point x of box (bx, by), times w0, to acc
 // (w0 = 0 for the padding of a batch).
 __device__ __forceinline__ void add_point(const BoxAt& b, float2 x, float w0, float (&acc)[kVals]) {
   const GridDesc& d = b.d;
-  const float s = (x.x - d.x0) / d.h - (float)b.bx;
-  const float t = (x.y - d.y0) / d.h - (float)b.by;
+  const float s = (x.x - d.x0) * d.inv_h - (float)b.bx;
+  const float t = (x.y - d.y0) * d.inv_h - (float)b.by;
   float lx[3], ly[3];
   lagrange3(s, lx);
   lagrange3(t, ly);
@@ -371,12 +372,17 @@ __global__ __launch_bounds__(kRangeWaves * kWave) void k_spread_ranges(
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // the graphs of the range's first and last points: every box of the
+    // range belongs to a graph between them (keys are ordered by graph)
+    const int k0 = __builtin_amdgcn_readfirstlane(kv[0]);
+    const int kl = skeys[p1 - 1];
+    const int g0 = G == 1 ? 0 : graph_of_box(desc, 0, G, k0);
+    const int g1 = G == 1 ? 0 : graph_of_box(desc, g0, G, kl);
     if (lane == 0) {  // which end pieces of the range are partials
-      const int k0 = skeys[p0], kl = skeys[p1 - 1];
       const bool whole0 = box_off[k0] == p0 && box_off[k0 + 1] == seg[1];
       const bool wholel = box_off[kl] == seg[nseg - 1] && box_off[kl + 1] == p1;
-      head_box[r] = (whole0 || is_far_key(desc, G, k0)) ? -1 : k0;
-      tail_box[r] = (nseg > 1 && !wholel && !is_far_key(desc, G, kl)) ? kl : -1;
+      head_box[r] = (whole0 || is_far_key(desc, g0, k0)) ? -1 : k0;
+      tail_box[r] = (nseg > 1 && !wholel && !is_far_key(desc, g1, kl)) ? kl : -1;
     }
     for (int s0 = 0; s0 < nseg; s0 += kWave) {
       const int s = s0 + lane;
@@ -384,7 +390,7 @@ __global__ __launch_bounds__(kRangeWaves * kWave) void k_spread_ranges(
       const int a = mine ? seg[s] : 0, b = mine ? seg[s + 1] : 0;
       if (mine && b - a < kLongSeg) {
         const int key = skeys[a];
-        const BoxAt bx = box_at(desc, G, key);
+        const BoxAt bx = box_at(desc, g0, g1 + 1, key);
         if (!bx.far) {  // far points are not spread
           float acc[kVals];
 #pragma unroll
@@ -399,7 +405,7 @@ __global__ __launch_bounds__(kRangeWaves * kWave) void k_spread_ranges(
         todo &= todo - 1;
         const int la = __shfl(a, src, kWave), lb = __shfl(b, src, kWave);
         const int key = skeys[la];
-        const BoxAt bx = box_at(desc, G, key);
+        const BoxAt bx = box_at(desc, g0, g1 + 1, key);
         if (bx.far) continue;  // uniform over the wave: far points are not spread
         float acc[kVals];
 #pragma unroll
@@ -447,7 +453,7 @@ __device__ __forceinline__ void spread_dense_box(int b, const int* __restrict__ 
 #pragma unroll
   for (int q = 0; q < kVals; ++q) tot[q] = wave_sum_to_last((float)acc[q]);
   if (lane == kWave - 1) {
-    const BoxAt bx = box_at(desc, G, b);
+    const BoxAt bx = box_at(desc, 0, G, b);
     node_store(charges + bx.d.off_c, bx.d.ng, bx.bx, bx.by, tot);
   }
 }
@@ -473,7 +479,8 @@ __global__ __launch_bounds__(256) void k_spread_boxes(
       }
     }
     // holds points, not written whole by phase 1, not a far box
-    const bool mine = b < B && be > bs && r0 != r1 && !is_far_key(desc, G, b);
+    const bool mine =
+        b < B && be > bs && r0 != r1 && !is_far_key(desc, graph_of_box(desc, 0, G, b), b);
     if (mine && r1 - r0 < kDenseRanges) {
       double acc[kVals];
 #pragma unroll
@@ -483,7 +490,7 @@ __global__ __launch_bounds__(256) void k_spread_boxes(
 #pragma unroll
         for (int q = 0; q < kVals; ++q) acc[q] += (double)src[q];
       }
-      const BoxAt bx = box_at(desc, G, b);
+      const BoxAt bx = box_at(desc, 0, G, b);
       node_store(charges + bx.d.off_c, bx.d.ng, bx.bx, bx.by, acc);
     }
   }
@@ -496,7 +503,8 @@ __global__ __launch_bounds__(256) void k_spread_boxes(
     bool dense = false;
     if (bl < B) {
       const int bs = box_off[bl], be = box_off[bl + 1];
-      dense = be > bs && (be - 1) / range - bs / range >= kDenseRanges && !is_far_key(desc, G, bl);
+      dense = be > bs && (be - 1) / range - bs / range >= kDenseRanges &&
+              !is_far_key(desc, graph_of_box(desc, 0, G, bl), bl);
     }
     u64 todo = __ballot(dense);
     while (todo) {

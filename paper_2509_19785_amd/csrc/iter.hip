@@ -436,19 +436,36 @@ __global__ __launch_bounds__(kChunkThreads) void k_gather(
   const float* pg = pot + d.off_p;
   const bool single = gi[g].n == 1;
   CompSum zs;
-  for (int p = chunk_start[c] + threadIdx.x; p < chunk_end[c]; p += kChunkThreads) {
-    const float2 x = xs[p];
-    const int local = skeys[p] - d.box_base;
+  // the thread's points (every chunk holds at most kChunk), their slot data
+  // loaded together (clamped into the chunk) before any is used
+  constexpr int PPT = kChunk / kChunkThreads;
+  static_assert(kChunk % kChunkThreads == 0, "whole points per thread");
+  const int pa = chunk_start[c] + threadIdx.x, pe = chunk_end[c];
+  float2 xv[PPT];
+  int kv[PPT], iv[PPT];
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
+    const int q = min(pa + u * kChunkThreads, pe - 1);
+    xv[u] = xs[q];
+    kv[u] = skeys[q];
+    iv[u] = perm[q];
+  }
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
+    const int p = pa + u * kChunkThreads;
+    if (p >= pe) continue;
+    const float2 x = xv[u];
+    const int local = kv[u] - d.box_base;
     if (local == d.n_int * d.n_int) {  // a far point: its sums come from k_far
       const float z = slot_z[p];
-      if (zi) zi[perm[p]] = z;
-      if (lnv) lnv[perm[p]] = slot_ln[p];
+      if (zi) zi[iv[u]] = z;
+      if (lnv) lnv[iv[u]] = slot_ln[p];
       zs.add(z);
       continue;
     }
     const int by = local / d.n_int, bx = local - by * d.n_int;
-    const float s = (x.x - d.x0) / d.h - (float)bx;
-    const float t = (x.y - d.y0) / d.h - (float)by;
+    const float s = (x.x - d.x0) * d.inv_h - (float)bx;
+    const float t = (x.y - d.y0) * d.inv_h - (float)by;
     float lx[3], ly[3];
     lagrange3(s, lx);
     lagrange3(t, ly);
@@ -483,7 +500,7 @@ __global__ __launch_bounds__(kChunkThreads) void k_gather(
       e = make_float2(0.f, 0.f);
       z = 0.f;
     }
-    const int i = perm[p];
+    const int i = iv[u];
     rep_ent[i] = make_float4(r.x, r.y, e.x, e.y);  // one scattered 16-byte store
     if (zi) zi[i] = z;
     if (lnv) lnv[i] = single ? 0.f : phi[CH_KLN_1];
