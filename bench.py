@@ -31,8 +31,8 @@ HBM_PEAK_GBS = 8000.0
 # (FETCH_SIZE x 2 + WRITE_SIZE x 1, KiB x 1024; the factors from a 1 GiB device
 # copy), summarised under profiles/. They hold for the kernel source with the
 # hash below only: for any other source the traffic is reported as null.
-ATTRACT_TRAFFIC_BYTES = 1_822_643_104
-ATTRACT_TRAFFIC_SOURCE_SHA256 = "3e09ae0f20769c8f26ed83598c5b41605f888b4fed5a6877bd6978d66814e0a1"
+ATTRACT_TRAFFIC_BYTES = 1_824_707_635
+ATTRACT_TRAFFIC_SOURCE_SHA256 = "1fef192adfeb8e9e097dffadf443e88bc96f4e4a21f3b34497dd55fbaf47e858"
 
 
 def attract_traffic():
@@ -482,7 +482,7 @@ def kernel_algorithmic_bytes(kernel: str, n: int, nnz: int, ni: int):
     ng, Mh = 3 * ni, 3 * ni + 1
     return {
         "k_attract_tiled": 8 * nnz + 40 * n + 8,
-        "k_bbox_plan": 8 * n,
+        "k_bbox_part": 8 * n,
         "k_bin_keys": 12 * n,
         "k_box_bounds": 12 * ng * ng,                         # clears the 3 charge grids
         "k_spread_ranges": 12 * n + 12 * ng * ng,
