@@ -443,7 +443,8 @@ def workload_legs(api, ctx, which, iters):
 
 
 # --------------------------------------------------------------------------- per-kernel table
-FIXED_GRID_STDS = (6.0, 12.0)   # layouts N(0, std^2): 256 and 512 intervals at n = 1e6
+# layouts N(0, std^2) and the interval cap: 256, 512 and 1024 intervals at n = 1e6
+FIXED_GRID_PHASES = ((6.0, 512), (12.0, 512), (25.0, 1024))
 FIXED_GRID_EVALS = 20
 
 
@@ -459,9 +460,10 @@ def fixed_grids(info_path: str):
     dev = torch.device("cuda", 0)
     prob = api.Problem.build(ctx, torch.as_tensor(g.indptr).to(dev), torch.as_tensor(g.indices).to(dev),
                              40.0, seed=3)
-    prm, sp = api.Params(), api.StepParams()
+    sp = api.StepParams()
     info = {"n": prob.n, "nnz": prob.nnz, "phases": []}
-    for std in FIXED_GRID_STDS:
+    for std, max_int in FIXED_GRID_PHASES:
+        prm = api.Params(max_intervals=max_int)
         X = torch.tensor(graphs.initial_layout(g.n, 1, std=std), device=dev)
         upd, gains = torch.zeros_like(X), torch.ones_like(X)
         G, Z = torch.empty_like(X), torch.empty(1, dtype=torch.float64, device=dev)
@@ -497,9 +499,13 @@ def kernel_algorithmic_bytes(kernel: str, n: int, nnz: int, ni: int):
 def kernel_table(trace_csv: str, info_path: str):
     """Markdown table of the per-iteration kernels from a rocprofv3 kernel trace
     of --fixed-grids: mean duration per layout, algorithmic bytes, GB/s and the
-    fraction of the 8 TB/s HBM peak."""
+    fraction of the 8 TB/s HBM peak. Launches are assigned to the layouts by
+    time (the step kernel runs once per evaluation in every layout); a
+    transform kernel of the large class (FFT length 6144) is listed as such
+    and only where it ran."""
     import collections
     import csv
+    import re
     info = json.load(open(info_path))
     n, nnz, phases = info["n"], info["nnz"], info["phases"]
     seq = collections.defaultdict(list)
@@ -507,19 +513,26 @@ def kernel_table(trace_csv: str, info_path: str):
         name = r["Kernel_Name"]
         name = name[:name.index("(")] if "(" in name else name
         name = name.replace("void ", "").replace("tsnet::", "")
+        m = re.match(r"(\w+)<FftCfg<(\d+), \d+> >", name)
+        if m:
+            name = m.group(1) + (" (M <= 3072)" if int(m.group(2)) <= 3072 else " (M 6144)")
         seq[name].append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
-    per_eval = len(phases) * FIXED_GRID_EVALS
+    steps = sorted(seq["k_step"])
+    per = FIXED_GRID_EVALS
+    # phase p spans its per-evaluation steps (the last step of the previous phase to its own last)
+    ends = [steps[(p + 1) * per - 1][0] for p in range(len(phases))]
+    starts = [0] + [steps[p * per - 1][0] for p in range(1, len(phases))]
     print("| kernel | intervals | launches | mean us | algorithmic bytes | GB/s | of 8 TB/s |")
     print("|---|---:|---:|---:|---:|---:|---:|")
     for k in sorted(seq, key=lambda x: -sum(d for _, d in seq[x])):
-        v = sorted(seq[k])
-        if len(v) < per_eval or len(v) % per_eval:
-            continue  # not a once-per-iteration kernel of this workload
-        per = len(v) // len(phases)
         for p, ph in enumerate(phases):
-            d = [x[1] for x in v[p * per:(p + 1) * per]]
+            d = [dur for t, dur in seq[k] if starts[p] < t <= ends[p]]
+            if len(d) < per or len(d) % per:
+                continue  # not a once-per-evaluation kernel of this layout
+            if k.endswith("(M <= 3072)") and ph["n_int"] > 512:
+                continue  # launched, but its blocks leave the grid to the large class
             avg_us = sum(d) / len(d) / 1e3
-            b = kernel_algorithmic_bytes(k, n, nnz, ph["n_int"])
+            b = kernel_algorithmic_bytes(k.split(" ")[0], n, nnz, ph["n_int"])
             if b:
                 gbs = b / (avg_us * 1e-6) / 1e9
                 print(f"| {k} | {ph['n_int']} | {len(d)} | {avg_us:.1f} | {b:,} | {gbs:.0f} | "

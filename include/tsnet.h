@@ -87,9 +87,13 @@ typedef struct tsnet_P_s*   tsnet_P;     /* one problem: graph batch, P, workspa
  *    core point's argument only (the far point adds its charges at the nodes
  *    before the gather; its own sums run over the node charges), far points
  *    meet each other exactly. Otherwise the grid covers the bounding box.
- *  min_intervals >= 1, max_intervals a power of two in [min_intervals, 512].
+ *  min_intervals >= 1, max_intervals a power of two in [min_intervals, 1024]
+ *    (default 512). Above 512 every evaluation also launches the transform
+ *    kernels of FFT length 6144 (75 KB of LDS per block; TSNET_EINVAL where
+ *    the device cannot give that).
  *  Evaluation workspace: a single graph holds grid buffers for a
- *  max_intervals grid (about 600 MB at 512, 9.5 MB at 64). A batch's grid
+ *  max_intervals grid (about 2.4 GB at 1024, 600 MB at 512, 9.5 MB at 64).
+ *  A batch's grid
  *  buffers are pools with every graph at its own offset, sized by the first
  *  evaluation (which waits once for its grid plan) at four times what its
  *  grids need, at most max_intervals grids in every graph; when a later plan

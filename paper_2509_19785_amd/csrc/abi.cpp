@@ -347,7 +347,7 @@ static int check_params(const tsnet_params* p) {
   if (p->nodes_per_interval != kNodes) return fail(TSNET_EINVAL, "nodes_per_interval must be 3");
   const int mx = p->max_intervals, mn = p->min_intervals;
   if (mx < 1 || mx > kMaxIntervals || (mx & (mx - 1)))
-    return fail(TSNET_EINVAL, "max_intervals must be a power of two in [1, 512]");
+    return fail(TSNET_EINVAL, "max_intervals must be a power of two in [1, 1024]");
   if (mn < 1 || mn > mx) return fail(TSNET_EINVAL, "min_intervals must be in [1, max_intervals]");
   if (p->far_trim < 0 || p->far_trim > kMaxFarTrim)
     return fail(TSNET_EINVAL, "far_trim must be in [0, 1024]");
@@ -431,6 +431,8 @@ static int ensure_pools(Problem& P, const float2* X, const PlanParams& pp, bool 
 static int run_interp(Problem& P, const float2* X, const tsnet_params& prm, int with_ln,
                       int with_zi, double* Z_out, hipStream_t s) {
   Ctx& c = *P.ctx;
+  if (prm.max_intervals > kFftSmallM / (2 * kNodes) && !c.fft_large)
+    return fail(TSNET_EINVAL, "max_intervals above 512 needs 75 KB of LDS per block, which this device does not give");
   int rc = ensure_grid(P, prm.max_intervals);
   if (rc) return rc;
   PlanParams pp{};
@@ -460,7 +462,7 @@ static int run_interp(Problem& P, const float2* X, const tsnet_params& prm, int 
   }
   {
     StageScope t(c, ST_FFT, s);
-    TSNET_LAUNCH(launch_fft_conv(P, (float)prm.eps_r, with_ln, s));
+    TSNET_LAUNCH(launch_fft_conv(P, (float)prm.eps_r, with_ln, prm.max_intervals, s));
   }
   if (may_trim) {
     StageScope t(c, ST_FAR, s);
@@ -590,6 +592,7 @@ int tsnet_ctx_create(tsnet_ctx* out, int device) {
     delete c;
     return fail(TSNET_EHIP, std::string("context set-up: ") + hipGetErrorString(e));
   }
+  c->c.fft_large = fft_large_init();
   // the allocation-free direct call's scratch on this device (device current)
   if ((rc = static_scratch(device, &c->c.static_scratch))) {
     dfree(c->c.twiddle);

@@ -27,9 +27,9 @@
 // passes (the last power-of-two pass 8, 4 or 2) and one radix-12 pass, each
 // butterfly an in-register DFT; every pass reads the buffer into registers,
 // synchronises and writes back in place. Each block owns one padded LDS
-// buffer of kFftElems complex values and the first M / 2 twiddles of its
+// buffer of C::Elems complex values and the first M / 2 twiddles of its
 // transform length (copied from the context's table once per block);
-// sequences of length M share a block up to kFftElems / M at a time (fewer
+// sequences of length M share a block up to C::Elems / M at a time (fewer
 // when there are fewer sequences than blocks, so small grids stay spread).
 #include <hip/hip_runtime.h>
 
@@ -41,13 +41,26 @@
 
 namespace tsnet {
 
-constexpr int kFftElems = kMaxM;              // complex values per transform buffer
-constexpr int kFftBuf = kFftElems + kFftElems / 16;  // the same, padded (one spare slot per 16)
-constexpr int kFftLds = (kFftBuf + kFftElems / 2) * 8;  // bytes of LDS per FFT block: buffer + half twiddles
-constexpr int kFftThreads = 256;
-constexpr int kPerThread = kFftElems / kFftThreads;  // register slots per thread
-constexpr int kColBatch = 4;                         // loads in flight per thread in the column stage
-static_assert(kPerThread % kColBatch == 0, "whole batches");
+// A size class of the transform kernels: buffer length E complex values and
+// T threads per block, so every thread holds E / T slots in registers (12 in
+// both classes). The small class takes every length up to 3072 (512
+// intervals); the large class only 6144 (1024 intervals), with twice the
+// threads and 75 KB of LDS per block. Each kernel is instantiated per class
+// and a block returns at once when its graph's length belongs to the other.
+template <int E, int T>
+struct FftCfg {
+  static constexpr int Elems = E;              // complex values per transform buffer
+  static constexpr int Threads = T;
+  static constexpr int Buf = E + E / 16;       // the buffer, padded (one spare slot per 16)
+  static constexpr int Lds = (Buf + E / 2) * 8;  // bytes of LDS per block: buffer + half twiddles
+  static constexpr int PerThread = E / T;      // register slots per thread
+  __device__ static bool handles(int M) { return E > kFftSmallM ? M > kFftSmallM : M <= kFftSmallM; }
+};
+using FftSmall = FftCfg<kFftSmallM, 256>;
+using FftLarge = FftCfg<kMaxM, 512>;
+constexpr int kColBatch = 4;  // loads in flight per thread in the column stage
+static_assert(FftSmall::PerThread % kColBatch == 0 && FftLarge::PerThread % kColBatch == 0,
+              "whole batches");
 
 // e^{-2 pi i m / L}, 0 <= m < L, from the half table th[r] = e^{-2 pi i r / L},
 // r < L / 2 (the second half is the negated first half).
@@ -66,12 +79,12 @@ __device__ __forceinline__ float2 twh(const float2* th, int m) {
 // and the output stride NS are multiples of 16 the padded addresses are a
 // base plus constant offsets. INV: inverse transform (conjugate twiddles),
 // fixed at compile time so the sign folds into the arithmetic.
-template <int R, int L, int NS, bool INV>
+template <int R, int L, int NS, bool INV, class C>
 __device__ __forceinline__ void pass_ip(float2* buf, int nb, const float2* th) {
   constexpr float sgn = INV ? 1.f : -1.f;
   constexpr int nbut = L / R;
   constexpr int tstep = L / (NS * R);
-  constexpr int BPT = (kFftElems / R + kFftThreads - 1) / kFftThreads;
+  constexpr int BPT = (C::Elems / R + C::Threads - 1) / C::Threads;
   constexpr bool in_lin = nbut % 16 == 0;
   constexpr bool out_lin = NS % 16 == 0 || (NS == 1 && R == 16);
   const int total = nb * nbut;
@@ -79,7 +92,7 @@ __device__ __forceinline__ void pass_ip(float2* buf, int nb, const float2* th) {
   int ob[BPT];
 #pragma unroll
   for (int u = 0; u < BPT; ++u) {
-    const int idx = threadIdx.x + u * kFftThreads;
+    const int idx = threadIdx.x + u * C::Threads;
     ob[u] = -1;
     if (idx < total) {
       const int sq = idx / nbut, j = idx - sq * nbut, k = j & (NS - 1);
@@ -121,15 +134,15 @@ __device__ __forceinline__ void pass_ip(float2* buf, int nb, const float2* th) {
 }
 
 // The passes of fft_plan for a length known at compile time.
-template <int L, int NS, int P2, bool INV>
+template <int L, int NS, int P2, bool INV, class C>
 struct FftPasses {
   __device__ __forceinline__ static void run(float2* buf, int nb, const float2* th) {
     if constexpr (P2 > 1) {
       constexpr int R = P2 >= 16 ? 16 : P2;
-      pass_ip<R, L, NS, INV>(buf, nb, th);
-      FftPasses<L, NS * R, P2 / R, INV>::run(buf, nb, th);
+      pass_ip<R, L, NS, INV, C>(buf, nb, th);
+      FftPasses<L, NS * R, P2 / R, INV, C>::run(buf, nb, th);
     } else {
-      pass_ip<L / NS, L, NS, INV>(buf, nb, th);  // the radix-12 (6, 3) pass
+      pass_ip<L / NS, L, NS, INV, C>(buf, nb, th);  // the radix-12 (6, 3) pass
     }
   }
 };
@@ -138,38 +151,43 @@ struct FftPasses {
 // kernels pick the length at run time (it comes from the grid plan on the
 // device), and inlining every length into one body inflates the register
 // allocation.
-template <int L, bool INV>
+template <int L, bool INV, class C>
 __device__ __noinline__ void fft_len(float2* buf, int nb, const float2* th) {
   constexpr int p2 = L / 3;
   constexpr int r3 = p2 >= 4 ? 12 : (p2 == 2 ? 6 : 3);
-  FftPasses<L, 1, p2 / (r3 / 3), INV>::run(buf, nb, th);
+  FftPasses<L, 1, p2 / (r3 / 3), INV, C>::run(buf, nb, th);
 }
 
-template <bool INV>
+template <bool INV, class C>
 __device__ void block_fft_dir(float2* buf, int nb, int L, const float2* th) {
-  switch (L) {
-    case 3072: fft_len<3072, INV>(buf, nb, th); break;
-    case 1536: fft_len<1536, INV>(buf, nb, th); break;
-    case 768: fft_len<768, INV>(buf, nb, th); break;
-    case 384: fft_len<384, INV>(buf, nb, th); break;
-    case 192: fft_len<192, INV>(buf, nb, th); break;
-    case 96: fft_len<96, INV>(buf, nb, th); break;
-    case 48: fft_len<48, INV>(buf, nb, th); break;
-    case 24: fft_len<24, INV>(buf, nb, th); break;
-    case 12: fft_len<12, INV>(buf, nb, th); break;
-    default: fft_len<6, INV>(buf, nb, th); break;
+  if constexpr (C::Elems > kFftSmallM) {  // the large class has one length
+    fft_len<C::Elems, INV, C>(buf, nb, th);
+  } else {
+    switch (L) {
+      case 3072: fft_len<3072, INV, C>(buf, nb, th); break;
+      case 1536: fft_len<1536, INV, C>(buf, nb, th); break;
+      case 768: fft_len<768, INV, C>(buf, nb, th); break;
+      case 384: fft_len<384, INV, C>(buf, nb, th); break;
+      case 192: fft_len<192, INV, C>(buf, nb, th); break;
+      case 96: fft_len<96, INV, C>(buf, nb, th); break;
+      case 48: fft_len<48, INV, C>(buf, nb, th); break;
+      case 24: fft_len<24, INV, C>(buf, nb, th); break;
+      case 12: fft_len<12, INV, C>(buf, nb, th); break;
+      default: fft_len<6, INV, C>(buf, nb, th); break;
+    }
   }
 }
 
-// nb sequences of length L (= 6 * 2^a <= kFftElems, nb L <= kFftElems) at
+// nb sequences of length L (= 6 * 2^a <= C::Elems, nb L <= C::Elems) at
 // buf[pad(s L + i)], transformed in place; th is the half twiddle table of
 // length L in LDS. sgn = -1 forward, +1 inverse (unnormalised). Must be
 // reached by every thread of the block.
+template <class C>
 __device__ __forceinline__ void block_fft(float2* buf, int nb, int L, const float2* th, float sgn) {
   if (sgn > 0.f)
-    block_fft_dir<true>(buf, nb, L, th);
+    block_fft_dir<true, C>(buf, nb, L, th);
   else
-    block_fft_dir<false>(buf, nb, L, th);
+    block_fft_dir<false, C>(buf, nb, L, th);
 }
 
 // The first half of the twiddles of length M from the context table (length
@@ -185,9 +203,10 @@ __device__ __forceinline__ void load_twiddles(float2* th, const float2* __restri
 // then keep many blocks busy instead of a few full ones; at M = 1536 the
 // column stage measured faster with 2 columns per block (385 blocks) than
 // with 1 (769 blocks), so the target is the CU count, not the grid.
+template <class C>
 __device__ __forceinline__ int fft_pack(int M, int jobs) {
   constexpr int kSpreadBlocks = 256;
-  const int smax = kFftElems / M;
+  const int smax = C::Elems / M;
   const int target = (int)gridDim.x < kSpreadBlocks ? (int)gridDim.x : kSpreadBlocks;
   const int want = jobs / target;
   return want < 1 ? 1 : (want < smax ? want : smax);
@@ -213,16 +232,18 @@ struct FftArgs {
 // Row transforms of the charges and kernels. Sequence s of a graph:
 //   s < 2 ng:        charge row s / 2, part s % 2 (0: q0 + i q1, 1: q2)
 //   otherwise:       kernel row (s - 2 ng) / 2 in [0, M/2], part (0: K2 + i K1, 1: Ke + i Kln)
-__global__ __launch_bounds__(kFftThreads, 4) void k_fft_rows_fwd(FftArgs A) {
+template <class C>
+__global__ __launch_bounds__(C::Threads, 4) void k_fft_rows_fwd(FftArgs A) {
   extern __shared__ float2 lds[];
   const int g = blockIdx.y;
   const GridDesc d = A.desc[g];
   const int M = d.M, ng = d.ng, Mh = M / 2 + 1;
+  if (!C::handles(M)) return;  // the other size class transforms this graph
   float2* bufA = lds;
-  float2* twl = lds + kFftBuf;  // half twiddle table
+  float2* twl = lds + C::Buf;  // half twiddle table
   load_twiddles(twl, A.tw, M);
   const int nseq = 2 * ng + 2 * Mh;
-  const int S = fft_pack(M, nseq);  // sequences per block iteration
+  const int S = fft_pack<C>(M, nseq);  // sequences per block iteration
   const float* ch = A.charges + d.off_c;
   float2* qs = A.qr + d.off_q;
   float* ks = A.kr + d.off_k;
@@ -231,10 +252,10 @@ __global__ __launch_bounds__(kFftThreads, 4) void k_fft_rows_fwd(FftArgs A) {
     const int ns = nseq - s0 < S ? nseq - s0 : S;
     if (s0 + ns <= 2 * ng) {
       // charge rows only: every load is issued before any is used
-      float2 vin[kPerThread];
+      float2 vin[C::PerThread];
 #pragma unroll
-      for (int q = 0; q < kPerThread; ++q) {
-        const int idx = threadIdx.x + q * kFftThreads;
+      for (int q = 0; q < C::PerThread; ++q) {
+        const int idx = threadIdx.x + q * C::Threads;
         vin[q] = make_float2(0.f, 0.f);
         if (idx >= ns * M) continue;
         const int sl = idx / M, x = idx - sl * M;
@@ -247,8 +268,8 @@ __global__ __launch_bounds__(kFftThreads, 4) void k_fft_rows_fwd(FftArgs A) {
         }
       }
 #pragma unroll
-      for (int q = 0; q < kPerThread; ++q) {
-        const int idx = threadIdx.x + q * kFftThreads;
+      for (int q = 0; q < C::PerThread; ++q) {
+        const int idx = threadIdx.x + q * C::Threads;
         if (idx < ns * M) bufA[fft_pad(idx)] = vin[q];
       }
     } else {
@@ -282,7 +303,7 @@ __global__ __launch_bounds__(kFftThreads, 4) void k_fft_rows_fwd(FftArgs A) {
       }
     }
     __syncthreads();
-    block_fft(bufA, ns, M, twl, -1.f);
+    block_fft<C>(bufA, ns, M, twl, -1.f);
     const float2* res = bufA;
     for (int idx = threadIdx.x; idx < ns * Mh; idx += blockDim.x) {
       const int sl = idx / Mh, k = idx - sl * Mh;
@@ -361,14 +382,16 @@ __global__ __launch_bounds__(256) void k_fft_transpose(FftArgs A, int which) {
 }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kFftThreads, 3) void k_fft_cols(FftArgs A) {
+template <class C>
+__global__ __launch_bounds__(C::Threads, 3) void k_fft_cols(FftArgs A) {
   extern __shared__ float2 lds[];
   const int g = blockIdx.y;
   const GridDesc d = A.desc[g];
   const int M = d.M, ng = d.ng, Mh = M / 2 + 1;
-  const int S = fft_pack(M, Mh);  // columns per block iteration
+  if (!C::handles(M)) return;  // the other size class transforms this graph
+  const int S = fft_pack<C>(M, Mh);  // columns per block iteration
   float2* B0 = lds;
-  float2* twl = lds + kFftBuf;  // half twiddle table
+  float2* twl = lds + C::Buf;  // half twiddle table
   load_twiddles(twl, A.tw, M);
   const float2* qt = A.qt + d.off_q;
   const float* kt = A.kt + d.off_k;
@@ -377,16 +400,16 @@ __global__ __launch_bounds__(kFftThreads, 3) void k_fft_cols(FftArgs A) {
   for (int c0 = blockIdx.x * S; c0 < Mh; c0 += gridDim.x * S) {
     const int ncc = Mh - c0 < S ? Mh - c0 : S;
     const int tot = ncc * M;
-    float kh[4][kPerThread];
+    float kh[4][C::PerThread];
     // kernel spectra: two packed real columns per transform, kept in registers
     for (int pair = 0; pair < 2; ++pair) {
       // loads in groups of kColBatch in flight (registers are scarce here)
 #pragma unroll 1
-      for (int q0 = 0; q0 < kPerThread; q0 += kColBatch) {
+      for (int q0 = 0; q0 < C::PerThread; q0 += kColBatch) {
         float2 t[kColBatch];
 #pragma unroll
         for (int j = 0; j < kColBatch; ++j) {
-          const int idx = threadIdx.x + (q0 + j) * kFftThreads;
+          const int idx = threadIdx.x + (q0 + j) * C::Threads;
           if (idx >= tot) continue;
           const int col = idx / M, y = idx - col * M;
           const int ry = y < M - y ? y : M - y;
@@ -395,16 +418,16 @@ __global__ __launch_bounds__(kFftThreads, 3) void k_fft_cols(FftArgs A) {
         }
 #pragma unroll
         for (int j = 0; j < kColBatch; ++j) {
-          const int idx = threadIdx.x + (q0 + j) * kFftThreads;
+          const int idx = threadIdx.x + (q0 + j) * C::Threads;
           if (idx < tot) B0[fft_pad(idx)] = t[j];
         }
       }
       __syncthreads();
-      block_fft(B0, ncc, M, twl, -1.f);
+      block_fft<C>(B0, ncc, M, twl, -1.f);
       const float2* r = B0;
 #pragma unroll
-      for (int q = 0; q < kPerThread; ++q) {
-        const int idx = threadIdx.x + q * kFftThreads;
+      for (int q = 0; q < C::PerThread; ++q) {
+        const int idx = threadIdx.x + q * C::Threads;
         const float2 v = idx < tot ? r[fft_pad(idx)] : make_float2(0.f, 0.f);
         kh[2 * pair][q] = v.x;
         kh[2 * pair + 1][q] = v.y;
@@ -413,27 +436,27 @@ __global__ __launch_bounds__(kFftThreads, 3) void k_fft_cols(FftArgs A) {
     }
     for (int c = 0; c < 3; ++c) {
 #pragma unroll 1
-      for (int q0 = 0; q0 < kPerThread; q0 += kColBatch) {
+      for (int q0 = 0; q0 < C::PerThread; q0 += kColBatch) {
         float2 t[kColBatch];
 #pragma unroll
         for (int j = 0; j < kColBatch; ++j) {
-          const int idx = threadIdx.x + (q0 + j) * kFftThreads;
+          const int idx = threadIdx.x + (q0 + j) * C::Threads;
           const int col = idx / M, y = idx - col * M;
           t[j] = (idx < tot && y < ng) ? qt[((size_t)c * Mh + c0 + col) * ng + y] : make_float2(0.f, 0.f);
         }
 #pragma unroll
         for (int j = 0; j < kColBatch; ++j) {
-          const int idx = threadIdx.x + (q0 + j) * kFftThreads;
+          const int idx = threadIdx.x + (q0 + j) * C::Threads;
           if (idx < tot) B0[fft_pad(idx)] = t[j];
         }
       }
       __syncthreads();
-      block_fft(B0, ncc, M, twl, -1.f);
+      block_fft<C>(B0, ncc, M, twl, -1.f);
       const float2* Q = B0;
-      float2 qh[kPerThread];
+      float2 qh[C::PerThread];
 #pragma unroll
-      for (int q = 0; q < kPerThread; ++q) {
-        const int idx = threadIdx.x + q * kFftThreads;
+      for (int q = 0; q < C::PerThread; ++q) {
+        const int idx = threadIdx.x + q * C::Threads;
         qh[q] = idx < tot ? Q[fft_pad(idx)] : make_float2(0.f, 0.f);
       }
       __syncthreads();
@@ -448,15 +471,15 @@ __global__ __launch_bounds__(kFftThreads, 3) void k_fft_cols(FftArgs A) {
           kk = t == 0 ? 0 : 2;
         }
 #pragma unroll
-        for (int q = 0; q < kPerThread; ++q) {
-          const int idx = threadIdx.x + q * kFftThreads;
+        for (int q = 0; q < C::PerThread; ++q) {
+          const int idx = threadIdx.x + q * C::Threads;
           if (idx < tot) {
             const float kv = kk == 0 ? kh[0][q] : (kk == 1 ? kh[1][q] : (kk == 2 ? kh[2][q] : kh[3][q]));
             B0[fft_pad(idx)] = make_float2(kv * qh[q].x, kv * qh[q].y);
           }
         }
         __syncthreads();
-        block_fft(B0, ncc, M, twl, +1.f);
+        block_fft<C>(B0, ncc, M, twl, +1.f);
         const float2* r = B0;
         for (int idx = threadIdx.x; idx < ncc * ng; idx += blockDim.x) {
           const int col = idx / ng, y = idx - col * ng;
@@ -470,26 +493,28 @@ __global__ __launch_bounds__(kFftThreads, 3) void k_fft_cols(FftArgs A) {
 
 // ---------------------------------------------------------------------------
 // Inverse rows: job (row y, pair p) transforms F_{2p} + i F_{2p+1}.
-__global__ __launch_bounds__(kFftThreads) void k_fft_rows_inv(FftArgs A) {
+template <class C>
+__global__ __launch_bounds__(C::Threads) void k_fft_rows_inv(FftArgs A) {
   extern __shared__ float2 lds[];
   const int g = blockIdx.y;
   const GridDesc d = A.desc[g];
   const int M = d.M, ng = d.ng, Mh = M / 2 + 1;
+  if (!C::handles(M)) return;  // the other size class transforms this graph
   float2* bufA = lds;
-  float2* twl = lds + kFftBuf;  // half twiddle table
+  float2* twl = lds + C::Buf;  // half twiddle table
   load_twiddles(twl, A.tw, M);
   const int jobs = ng * 4;
-  const int S = fft_pack(M, jobs);
+  const int S = fft_pack<C>(M, jobs);
   const float2* orr = A.orr + d.off_o;
   float* pg = A.pot + d.off_p;
   const float scale = 1.0f / ((float)M * (float)M);
   for (int j0 = blockIdx.x * S; j0 < jobs; j0 += gridDim.x * S) {
     const int nj = jobs - j0 < S ? jobs - j0 : S;
     // every load of the block's jobs is issued before any is used
-    float2 f0[kPerThread], f1[kPerThread];
+    float2 f0[C::PerThread], f1[C::PerThread];
 #pragma unroll
-    for (int q = 0; q < kPerThread; ++q) {
-      const int idx = threadIdx.x + q * kFftThreads;
+    for (int q = 0; q < C::PerThread; ++q) {
+      const int idx = threadIdx.x + q * C::Threads;
       f0[q] = f1[q] = make_float2(0.f, 0.f);
       if (idx >= nj * M) continue;
       const int jl = idx / M, k = idx - jl * M;
@@ -501,8 +526,8 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_inv(FftArgs A) {
       if (!(o1 == CH_KLN_1 && !A.with_ln)) f1[q] = orr[((size_t)o1 * ng + ry) * Mh + kk];
     }
 #pragma unroll
-    for (int q = 0; q < kPerThread; ++q) {
-      const int idx = threadIdx.x + q * kFftThreads;
+    for (int q = 0; q < C::PerThread; ++q) {
+      const int idx = threadIdx.x + q * C::Threads;
       if (idx >= nj * M) continue;
       const int k = idx - (idx / M) * M;
       float2 a = f0[q], b = f1[q];
@@ -513,7 +538,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_inv(FftArgs A) {
       bufA[fft_pad(idx)] = make_float2(a.x - b.y, a.y + b.x);
     }
     __syncthreads();
-    block_fft(bufA, nj, M, twl, +1.f);
+    block_fft<C>(bufA, nj, M, twl, +1.f);
     const float2* res = bufA;
     for (int idx = threadIdx.x; idx < nj * ng; idx += blockDim.x) {
       const int jl = idx / ng, x = idx - jl * ng;
@@ -528,7 +553,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_inv(FftArgs A) {
   }
 }
 
-hipError_t launch_fft_conv(Problem& P, float eps, int with_ln, hipStream_t s) {
+hipError_t launch_fft_conv(Problem& P, float eps, int with_ln, int max_intervals, hipStream_t s) {
   FftArgs A;
   A.desc = P.desc;
   A.tw = P.ctx->twiddle;
@@ -544,12 +569,44 @@ hipError_t launch_fft_conv(Problem& P, float eps, int with_ln, hipStream_t s) {
   A.with_ln = with_ln;
   const int bx = P.G >= 64 ? 4 : (P.G >= 8 ? 32 : 1024);
   const int tb = P.G >= 64 ? 16 : (P.G >= 8 ? 64 : 1024);
-  hipLaunchKernelGGL(k_fft_rows_fwd, dim3(bx, P.G), dim3(kFftThreads), kFftLds, s, A);
+  // the large class only where the plan may give a graph 1024 intervals
+  const bool large = max_intervals > kFftSmallM / (2 * kNodes);
+  hipLaunchKernelGGL(k_fft_rows_fwd<FftSmall>, dim3(bx, P.G), dim3(FftSmall::Threads), FftSmall::Lds,
+                     s, A);
+  if (large)
+    hipLaunchKernelGGL(k_fft_rows_fwd<FftLarge>, dim3(bx, P.G), dim3(FftLarge::Threads),
+                       FftLarge::Lds, s, A);
   hipLaunchKernelGGL(k_fft_transpose, dim3(2 * tb, P.G), dim3(256), 0, s, A, 0);
-  hipLaunchKernelGGL(k_fft_cols, dim3(bx, P.G), dim3(kFftThreads), kFftLds, s, A);
+  hipLaunchKernelGGL(k_fft_cols<FftSmall>, dim3(bx, P.G), dim3(FftSmall::Threads), FftSmall::Lds, s,
+                     A);
+  if (large)
+    hipLaunchKernelGGL(k_fft_cols<FftLarge>, dim3(bx, P.G), dim3(FftLarge::Threads), FftLarge::Lds,
+                       s, A);
   hipLaunchKernelGGL(k_fft_transpose, dim3(tb, P.G), dim3(256), 0, s, A, 2);
-  hipLaunchKernelGGL(k_fft_rows_inv, dim3(bx, P.G), dim3(kFftThreads), kFftLds, s, A);
+  hipLaunchKernelGGL(k_fft_rows_inv<FftSmall>, dim3(bx, P.G), dim3(FftSmall::Threads), FftSmall::Lds,
+                     s, A);
+  if (large)
+    hipLaunchKernelGGL(k_fft_rows_inv<FftLarge>, dim3(bx, P.G), dim3(FftLarge::Threads),
+                       FftLarge::Lds, s, A);
   return hipGetLastError();
+}
+
+// Allows the large class its dynamic LDS (more than 64 KB per block); false
+// when the device cannot give it, and then grids stay at 512 intervals.
+bool fft_large_init() {
+  int dev = 0, lim = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+      lim < FftLarge::Lds)
+    return false;
+  const void* ks[3] = {reinterpret_cast<const void*>(k_fft_rows_fwd<FftLarge>),
+                       reinterpret_cast<const void*>(k_fft_cols<FftLarge>),
+                       reinterpret_cast<const void*>(k_fft_rows_inv<FftLarge>)};
+  for (const void* k : ks)
+    if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, FftLarge::Lds) !=
+        hipSuccess)
+      return false;
+  return true;
 }
 
 }  // namespace tsnet

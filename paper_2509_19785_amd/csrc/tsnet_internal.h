@@ -13,7 +13,8 @@ namespace tsnet {
 
 // ---------------------------------------------------------------- constants
 constexpr int kNodes = 3;                 // interpolation nodes per box and axis
-constexpr int kMaxIntervals = 512;        // boxes per axis (power of two)
+constexpr int kMaxIntervals = 1024;       // boxes per axis (power of two)
+constexpr int kFftSmallM = 3072;          // FFT lengths of the small transform class (512 intervals)
 constexpr int kMaxNg = kNodes * kMaxIntervals;
 constexpr int kMaxM = 2 * kMaxNg;         // FFT length per axis (3 * 2^b)
 constexpr int kPotCh = 8;                 // potential channels per node (4 planes of pairs)
@@ -120,6 +121,7 @@ enum Stage {
 struct Ctx {
   int device = 0;
   float2* twiddle = nullptr;          // e^{-2 pi i m / kMaxM}, m < kMaxM
+  bool fft_large = false;             // grids of 1024 intervals available on this device
   double* static_scratch = nullptr;   // this device's scratch array of the allocation-free call
   unsigned* status = nullptr;         // device status word
   int lds_per_block = 65536;
@@ -269,7 +271,9 @@ hipError_t radix_sort(unsigned* keys, unsigned* vals, unsigned* kt, unsigned* vt
                       int* hist, int* tsum, hipStream_t s);
 
 // FFT convolution (fft.hip)
-hipError_t launch_fft_conv(Problem& P, float eps, int with_ln, hipStream_t s);
+hipError_t launch_fft_conv(Problem& P, float eps, int with_ln, int max_intervals, hipStream_t s);
+// Enables the transform class for 1024 intervals on the current device (false: not available).
+bool fft_large_init();
 
 // direct FP64 baseline (direct.hip); the pair sums go to `pairs`, which holds
 // (n + nrows) * 5 doubles with rows, n * 5 without

@@ -266,6 +266,14 @@ def initial_layout(n: int, seed: int, std: float = 0.01) -> np.ndarray:
     return rng.normal(0.0, std, size=(n, 2)).astype(np.float32)
 
 
+def uniform_square(n: int, side: float, seed: int) -> np.ndarray:
+    """n positions uniform in the square [-side/2, side/2]^2 (a spread-out
+    layout with no far points: its interpolation grid covers the whole box).
+    float32 [n, 2]."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-0.5 * side, 0.5 * side, size=(n, 2)).astype(np.float32)
+
+
 def bulk_with_far_points(n: int, seed: int, n_far: int = 100, std: float = 0.18,
                          r_min: float = 1.0, r_max: float = 60.0) -> np.ndarray:
     """A dense bulk N(0, std^2 I) with ``n_far`` of its points moved far out: at

@@ -31,7 +31,7 @@ int main() {
   std::mt19937 rng(1);
   std::normal_distribution<float> nd;
   int bad = 0;
-  for (int L : {6, 12, 24, 48, 96, 192, 384, 768, 1536, 3072}) {  // every M = 6 n_int
+  for (int L : {6, 12, 24, 48, 96, 192, 384, 768, 1536, 3072, 6144}) {  // every M = 6 n_int
     for (float sgn : {-1.f, 1.f}) {
       const int nb = 3;
       std::vector<float2> tw(L);

@@ -1,5 +1,5 @@
 """Host build of the FFT building blocks (no GPU): every transform length
-L = 6 * 2^a up to 3072, forward and inverse, against a plain DFT in double."""
+L = 6 * 2^a up to 6144, forward and inverse, against a plain DFT in double."""
 import os
 import shutil
 import subprocess

@@ -138,6 +138,45 @@ def test_capped_grid_flags_status(api, ctx, grid_problem):
     assert ctx.status() & _lib.TSNET_STATUS_GRID_CAPPED
 
 
+@pytest.mark.parametrize("max_int", [1024, 512])
+def test_span_200_grid(api, ctx, max_int):
+    """A uniform square of side 200 (no far points) needs 800 boxes of 0.25
+    per axis. With max_intervals = 1024 the grid has 1024 intervals (FFT
+    length 6144, the large transform class), is not capped, and every term
+    matches exact pair sums on sampled rows within the interpolation error
+    at h = 0.195 (the FP64 interpolation oracle gives 2.6e-4 for F_rep,
+    1.8e-4 for F_ent and 1.1e-5 for Z_i on a square of the same density and
+    box side) plus FP32 rounding amplified by the half-span. With the cap of
+    512 the same layout is capped (h = 0.39, about 8x those errors) and
+    flagged."""
+    from paper_2509_19785_amd import _lib
+    n = 60000
+    X = graphs.uniform_square(n, 200.0, 21)
+    rowptr, col, val = graphs.random_affinity(n, 8.0, 3)
+    prob = api.Problem.from_host(ctx, rowptr, col, val.astype(np.float32))
+    prm = api.Params(max_intervals=max_int)
+    say(f"[grad parity] uniform square side 200, n={n}, max_intervals {max_int}")
+    ctx.status()
+    t = _terms(api, prob, X, prm)
+    st = ctx.status()
+    ni = int(prob.grid_info()["n_intervals"][0])
+    rows = np.arange(0, n, 117)
+    zi, frep, fent = gradient.pair_sums(X.astype(np.float64), prm.eps_r, rows)
+    e_rep = rel_l2(t["F_rep"][rows], frep)
+    e_ent = rel_l2(t["F_ent"][rows], fent)
+    e_z = rel_l2(t["Z_i"][rows], zi)
+    say(f"   n_int {ni}, status {st:#x}: F_rep {e_rep:.2e} F_ent {e_ent:.2e} Z_i {e_z:.2e}")
+    if max_int == 1024:
+        assert ni == 1024
+        assert not st & _lib.TSNET_STATUS_GRID_CAPPED
+        assert e_rep <= 1e-3 and e_ent <= 1e-3 and e_z <= 3e-4
+    else:
+        assert ni == 512
+        assert st & _lib.TSNET_STATUS_GRID_CAPPED
+        assert e_rep <= 1e-2 and e_ent <= 1e-2
+    prob.free()
+
+
 def test_converged_layout(api, ctx, grid_problem):
     g, P = grid_problem
     X = graphs.initial_layout(g.n, 0).astype(np.float64)
