@@ -31,7 +31,7 @@ namespace tsnet {
 
 constexpr int kFarThreads = 512;
 constexpr int kFarBatch = 512;  // far points staged in LDS at a time (node role)
-constexpr int kFarNodes = 8;    // nodes a thread loads ahead per step (far-point role)
+constexpr int kFarNodes = 16;   // nodes a thread loads ahead per step (far-point role)
 constexpr int kFarSums = 14;    // 8 node channels + 6 far-far direct sums
 
 struct FarArgs {

@@ -333,26 +333,51 @@ __global__ __launch_bounds__(C::Threads, 4) void k_fft_rows_fwd(FftArgs A) {
 
 // ---------------------------------------------------------------------------
 // Tiled transposes in[b][r][c] -> out[b][c][r], r < R, c < C (sizes per graph).
-// Blocks b0, b0 + nblk, ... of the launch take the tiles in turn.
+// Blocks b0, b0 + nblk, ... of the launch take kTrTiles consecutive tiles of
+// 32 x 32 at a time: every thread issues its loads of all of them (clamped
+// into the array, unconditional) before any is used, then the tiles go
+// through LDS and out along the other axis.
+constexpr int kTrTiles = 2;
+
 template <typename T>
 __device__ __forceinline__ void transpose_tiles(const T* __restrict__ in, T* out, int R, int C,
-                                                int nb, T (*tile)[33], int b0, int nblk) {
+                                                int nb, T (*tile)[32][33], int b0, int nblk) {
   const int tilesR = (R + 31) / 32, tilesC = (C + 31) / 32;
   const int per = tilesR * tilesC;
+  const int total = nb * per;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads
-  for (int t = b0; t < nb * per; t += nblk) {
-    const int b = t / per, rem = t - b * per;
-    const int tr = rem / tilesC, tc = rem - tr * tilesC;
-    const T* ib = in + (size_t)b * R * C;
-    T* ob = out + (size_t)b * R * C;
-    for (int k = ty; k < 32; k += 8) {
-      const int r = tr * 32 + k, c = tc * 32 + tx;
-      if (r < R && c < C) tile[k][tx] = ib[(size_t)r * C + c];
+  const size_t last = (size_t)nb * R * C - 1;
+  for (int t0 = b0 * kTrTiles; t0 < total; t0 += nblk * kTrTiles) {
+    T v[kTrTiles][4];
+#pragma unroll
+    for (int u = 0; u < kTrTiles; ++u) {
+      const int t = min(t0 + u, total - 1);
+      const int b = t / per, rem = t - b * per;
+      const int tr = rem / tilesC, tc = rem - tr * tilesC;
+      const int c = min(tc * 32 + tx, C - 1);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int r = min(tr * 32 + ty + 8 * k, R - 1);
+        v[u][k] = in[min((size_t)b * R * C + (size_t)r * C + c, last)];
+      }
     }
+#pragma unroll
+    for (int u = 0; u < kTrTiles; ++u)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) tile[u][ty + 8 * k][tx] = v[u][k];
     __syncthreads();
-    for (int k = ty; k < 32; k += 8) {
-      const int c = tc * 32 + k, r = tr * 32 + tx;
-      if (r < R && c < C) ob[(size_t)c * R + r] = tile[tx][k];
+#pragma unroll
+    for (int u = 0; u < kTrTiles; ++u) {
+      const int t = t0 + u;
+      if (t >= total) break;
+      const int b = t / per, rem = t - b * per;
+      const int tr = rem / tilesC, tc = rem - tr * tilesC;
+      T* ob = out + (size_t)b * R * C;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int c = tc * 32 + ty + 8 * k, r = tr * 32 + tx;
+        if (r < R && c < C) ob[(size_t)c * R + r] = tile[u][tx][ty + 8 * k];
+      }
     }
     __syncthreads();
   }
@@ -364,14 +389,14 @@ __global__ __launch_bounds__(256) void k_fft_transpose(FftArgs A, int which) {
   const int g = blockIdx.y;
   const GridDesc d = A.desc[g];
   const int ng = d.ng, Mh = d.M / 2 + 1;
-  __shared__ float2 tc[32][33];
+  __shared__ float2 tc[kTrTiles][32][33];
   if (which == 0) {
     const int half = gridDim.x / 2;
     if ((int)blockIdx.x < half) {
       transpose_tiles<float2>(A.qr + d.off_q, A.qt + d.off_q, ng, Mh, 3, tc,
                               blockIdx.x, half);
     } else {
-      float (*tf)[33] = reinterpret_cast<float (*)[33]>(&tc[0][0]);
+      float (*tf)[32][33] = reinterpret_cast<float (*)[32][33]>(&tc[0][0][0]);
       transpose_tiles<float>(A.kr + d.off_k, A.kt + d.off_k, Mh, Mh, 4, tf,
                              blockIdx.x - half, gridDim.x - half);
     }
@@ -568,7 +593,7 @@ hipError_t launch_fft_conv(Problem& P, float eps, int with_ln, int max_intervals
   A.eps = eps;
   A.with_ln = with_ln;
   const int bx = P.G >= 64 ? 4 : (P.G >= 8 ? 32 : 1024);
-  const int tb = P.G >= 64 ? 16 : (P.G >= 8 ? 64 : 1024);
+  const int tb = P.G >= 64 ? 64 : (P.G >= 8 ? 256 : 2048);  // transpose blocks per graph
   // the large class only where the plan may give a graph 1024 intervals
   const bool large = max_intervals > kFftSmallM / (2 * kNodes);
   hipLaunchKernelGGL(k_fft_rows_fwd<FftSmall>, dim3(bx, P.G), dim3(FftSmall::Threads), FftSmall::Lds,

@@ -190,13 +190,18 @@ __global__ __launch_bounds__(kTrimThreads) void k_trim_hist(
 // grid centred on the region. Decisions in FP64 with every operation rounded
 // on its own (no contraction), so the far points and the grid are those of
 // the same rule evaluated anywhere else in IEEE FP64. The counts are cleared
-// for the next call. Then k_plan_pools (one block) sizes the batch's grid
-// buffers, fits them into the workspace pools and numbers the boxes.
+// for the next call. Then k_plan_pools (one block; for a single graph the
+// plan's own block) sizes the grid buffers, fits them into the workspace
+// pools and numbers the boxes.
 constexpr int kPlanThreads = 256;
 constexpr int kPlanBins = kTrimBins / kPlanThreads;  // consecutive bins per thread
 
+__device__ void plan_pools_block(GridDesc* desc, int G, const PlanParams& pp, int* btotal,
+                                 unsigned* status);
+
 __global__ __launch_bounds__(kPlanThreads) void k_trim_plan(GridDesc* desc, int* hist,
-                                                             PlanParams pp, unsigned* status) {
+                                                             PlanParams pp, unsigned* status,
+                                                             int* single_btotal) {
   __shared__ int sh[kPlanThreads / kWave + 1];
   __shared__ int bounds[4];  // lo_x, hi_x, lo_y, hi_y
   const int g = blockIdx.x;
@@ -284,17 +289,22 @@ __global__ __launch_bounds__(kPlanThreads) void k_trim_plan(GridDesc* desc, int*
     desc[g] = d;
     if (flags) atomicOr(status, (unsigned)flags);
   }
+  if (single_btotal) {  // a single graph: this block also fits the pools (no second launch)
+    __syncthreads();
+    plan_pools_block(desc, 1, pp, single_btotal, status);
+  }
 }
 
 // The grid buffers every graph needs, before and after fitting them into the
 // workspace pools, then the box ids and pool offsets of every graph (one
-// block: one graph per thread and step).
-__global__ __launch_bounds__(kPlanThreads) void k_plan_pools(GridDesc* desc, int G, PlanParams pp,
-                                                              int* btotal, unsigned* status) {
+// block: one graph per thread and step). Descriptors are read past the
+// non-coherent cache: the block may have written them itself.
+__device__ void plan_pools_block(GridDesc* desc, int G, const PlanParams& pp, int* btotal,
+                                 unsigned* status) {
   __shared__ unsigned long long red_need[POOL_KINDS][kPlanThreads / kWave];
   size_t need[POOL_KINDS] = {0, 0, 0, 0, 0};
   for (int gg = threadIdx.x; gg < G; gg += kPlanThreads) {
-    const int ni = desc[gg].n_int;
+    const int ni = ld_coherent(&desc[gg].n_int);
     for (int k = 0; k < POOL_KINDS; ++k) need[k] += pool_elems(k, ni);
   }
   for (int k = 0; k < POOL_KINDS; ++k) {
@@ -395,15 +405,21 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_pools(GridDesc* desc, int
   if (threadIdx.x == 0) *btotal = carry_box;
 }
 
+__global__ __launch_bounds__(kPlanThreads) void k_plan_pools(GridDesc* desc, int G, PlanParams pp,
+                                                              int* btotal, unsigned* status) {
+  plan_pools_block(desc, G, pp, btotal, status);
+}
+
 hipError_t launch_trim_plan(Problem& P, const float2* X, const PlanParams& pp, bool with_hist,
                             hipStream_t s) {
   if (with_hist)
     hipLaunchKernelGGL(k_trim_hist, dim3(P.num_chunks), dim3(kTrimThreads), 0, s, X, P.chunk_graph,
                        P.chunk_start, P.chunk_end, P.desc, P.trim_hist);
   hipLaunchKernelGGL(k_trim_plan, dim3(P.G), dim3(kPlanThreads), 0, s, P.desc, P.trim_hist, pp,
-                     P.ctx->status);
-  hipLaunchKernelGGL(k_plan_pools, dim3(1), dim3(kPlanThreads), 0, s, P.desc, P.G, pp, P.btotal,
-                     P.ctx->status);
+                     P.ctx->status, P.G == 1 ? P.btotal : nullptr);
+  if (P.G > 1)
+    hipLaunchKernelGGL(k_plan_pools, dim3(1), dim3(kPlanThreads), 0, s, P.desc, P.G, pp, P.btotal,
+                       P.ctx->status);
   return hipGetLastError();
 }
 

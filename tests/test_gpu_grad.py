@@ -276,6 +276,41 @@ def test_batch_of_graphs(api, ctx):
         assert rel_l2(got["G"][a0:a1], ex.G[a0:a1]) <= 1e-3
 
 
+def test_batch_of_72_column_layouts(api, ctx):
+    """72 small graphs with grids of 8, 16 and 32 intervals in one batch
+    (FFT lengths 48, 96 and 192 side by side; with 64 graphs or more every
+    graph gets four blocks per transform stage, each packing several
+    sequences). Every graph against the FP64 interpolation oracle on its own."""
+    parts, stds = [], []
+    for k in range(72):
+        parts.append(graphs.grid(6, 7) if k % 2 else graphs.random_recursive_tree(50 + k % 9, 100 + k))
+        stds.append((0.25, 0.5, 1.0)[k % 3])
+    b = graphs.concat_graphs(parts)
+    P = affinities.build_P(b.indptr, b.indices, 5.0, seed=2, graph_offsets=b.graph_offsets)
+    prob = _upload(api, ctx, P, b.graph_offsets)
+    n = b.indptr.shape[0] - 1
+    X = np.zeros((n, 2), np.float32)
+    for k in range(72):
+        a0, a1 = int(b.graph_offsets[k]), int(b.graph_offsets[k + 1])
+        X[a0:a1] = graphs.initial_layout(a1 - a0, 500 + k, std=stds[k])
+    prm = api.Params(min_intervals=8, max_intervals=32)
+    say(f"[grad parity] batch G=72 n={n}, 8-32 intervals")
+    got = _terms(api, prob, X, prm)
+    gi = prob.grid_info()
+    X64 = X.astype(np.float64)
+    seen = set()
+    for k in range(72):
+        a0, a1 = int(b.graph_offsets[k]), int(b.graph_offsets[k + 1])
+        it = interp.interp_terms(X64[a0:a1], prm.eps_r, prm.interval_width, prm.min_intervals,
+                                 prm.max_intervals, far_trim=prm.far_trim)
+        assert int(gi["n_intervals"][k]) == it.grid.n_int
+        seen.add(it.grid.n_int)
+        assert rel_l2(got["F_rep"][a0:a1], it.F_rep) <= 2e-5, k
+        assert rel_l2(got["F_ent"][a0:a1], it.F_ent) <= 2e-5, k
+        assert rel_l2(got["Z_i"][a0:a1], it.Z_i) <= 2e-5, k
+    assert {8, 16, 32} <= seen
+
+
 def test_batch_workspace_grows(api, ctx):
     """A batch's grid buffers are pools sized from its first plan (four times
     its needs). A layout whose grids need more is planned down once, with
