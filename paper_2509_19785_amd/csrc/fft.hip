@@ -406,6 +406,99 @@ __global__ __launch_bounds__(256) void k_fft_transpose(FftArgs A, int which) {
   }
 }
 
+// The products of a column group: output channel, kernel (K2, K1, Ke, Kln)
+// and charge (1, x, y) of each, in the order the column stage forms them.
+__device__ __forceinline__ void product_of(int t, int& o, int& kk, int& c) {
+  switch (t) {
+    case 0: o = CH_K2_1; kk = 0; c = 0; break;
+    case 1: o = CH_K1_1; kk = 1; c = 0; break;
+    case 2: o = CH_KE_1; kk = 2; c = 0; break;
+    case 3: o = CH_K2_X; kk = 0; c = 1; break;
+    case 4: o = CH_KE_X; kk = 2; c = 1; break;
+    case 5: o = CH_K2_Y; kk = 0; c = 2; break;
+    case 6: o = CH_KE_Y; kk = 2; c = 2; break;
+    default: o = CH_KLN_1; kk = 3; c = 0; break;
+  }
+}
+
+// Column stage for a column group whose every transform fits the buffer at
+// once (8 ncc M <= C::Elems: small grids of a single graph, one column per
+// block): the two kernel-spectrum transforms run as one batch, the three
+// charge transforms as another and the 7 (8 with ln) inverse transforms of
+// the products as a third, instead of one call per transform. Each
+// transform is the same sequence of passes as in the unbatched path, so
+// the results are the same bit for bit.
+template <class C>
+__device__ __noinline__ void cols_batched(const FftArgs& A, float2* B0, const float2* twl,
+                                             int M, int ng, int Mh, int c0, int ncc,
+                                             const float2* qt, const float* kt, float2* ot) {
+  constexpr int PB = (C::PerThread + 7) / 8;  // a thread's elements of one column group
+  const int tot = ncc * M;
+  const int nout = A.with_ln ? 8 : 7;
+  // kernel spectra, pair p at sequences [p ncc, (p + 1) ncc)
+  for (int e = threadIdx.x; e < 2 * tot; e += C::Threads) {
+    const int pair = e >= tot, r = e - pair * tot;
+    const int col = r / M, y = r - col * M;
+    const int ry = y < M - y ? y : M - y;
+    const size_t o = (size_t)(c0 + col) * Mh + ry;
+    B0[fft_pad(e)] = make_float2(kt[(size_t)(2 * pair) * Mh * Mh + o], kt[(size_t)(2 * pair + 1) * Mh * Mh + o]);
+  }
+  __syncthreads();
+  block_fft<C>(B0, 2 * ncc, M, twl, -1.f);
+  float kh[4][PB];
+#pragma unroll
+  for (int q = 0; q < PB; ++q) {
+    const int idx = threadIdx.x + q * C::Threads;
+    const float2 v0 = idx < tot ? B0[fft_pad(idx)] : make_float2(0.f, 0.f);
+    const float2 v1 = idx < tot ? B0[fft_pad(tot + idx)] : make_float2(0.f, 0.f);
+    kh[0][q] = v0.x;
+    kh[1][q] = v0.y;
+    kh[2][q] = v1.x;
+    kh[3][q] = v1.y;
+  }
+  __syncthreads();
+  // charges 1, x, y at sequences [c ncc, (c + 1) ncc)
+  for (int e = threadIdx.x; e < 3 * tot; e += C::Threads) {
+    const int c = e / tot, r = e - c * tot;
+    const int col = r / M, y = r - col * M;
+    B0[fft_pad(e)] = y < ng ? qt[((size_t)c * Mh + c0 + col) * ng + y] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  block_fft<C>(B0, 3 * ncc, M, twl, -1.f);
+  float2 qh[3][PB];
+#pragma unroll
+  for (int q = 0; q < PB; ++q) {
+    const int idx = threadIdx.x + q * C::Threads;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      qh[c][q] = idx < tot ? B0[fft_pad(c * tot + idx)] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  // products, output t at sequences [t ncc, (t + 1) ncc), then one inverse batch
+  for (int t = 0; t < nout; ++t) {
+    int o, kk, c;
+    product_of(t, o, kk, c);
+#pragma unroll
+    for (int q = 0; q < PB; ++q) {
+      const int idx = threadIdx.x + q * C::Threads;
+      if (idx >= tot) continue;
+      const float kv = kk == 0 ? kh[0][q] : (kk == 1 ? kh[1][q] : (kk == 2 ? kh[2][q] : kh[3][q]));
+      const float2 qv = c == 0 ? qh[0][q] : (c == 1 ? qh[1][q] : qh[2][q]);
+      B0[fft_pad(t * tot + idx)] = make_float2(kv * qv.x, kv * qv.y);
+    }
+  }
+  __syncthreads();
+  block_fft<C>(B0, nout * ncc, M, twl, +1.f);
+  for (int e = threadIdx.x; e < nout * ncc * ng; e += C::Threads) {
+    const int t = e / (ncc * ng), r = e - t * (ncc * ng);
+    const int col = r / ng, y = r - col * ng;
+    int o, kk, c;
+    product_of(t, o, kk, c);
+    ot[((size_t)o * Mh + c0 + col) * ng + y] = B0[fft_pad(t * tot + col * M + y)];
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 template <class C>
 __global__ __launch_bounds__(C::Threads, 3) void k_fft_cols(FftArgs A) {
@@ -422,6 +515,11 @@ __global__ __launch_bounds__(C::Threads, 3) void k_fft_cols(FftArgs A) {
   const float* kt = A.kt + d.off_k;
   float2* ot = A.ot + d.off_o;
   const int nout0 = A.with_ln ? 4 : 3;
+  if (8 * S * M <= C::Elems) {  // every transform of a column group fits at once
+    for (int c0 = blockIdx.x * S; c0 < Mh; c0 += gridDim.x * S)
+      cols_batched<C>(A, B0, twl, M, ng, Mh, c0, Mh - c0 < S ? Mh - c0 : S, qt, kt, ot);
+    return;
+  }
   for (int c0 = blockIdx.x * S; c0 < Mh; c0 += gridDim.x * S) {
     const int ncc = Mh - c0 < S ? Mh - c0 : S;
     const int tot = ncc * M;
