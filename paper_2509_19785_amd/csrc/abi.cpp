@@ -268,7 +268,7 @@ static int init_problem(Ctx& c, Problem& P, int n, const int32_t* goff_host, int
       (rc = dmalloc(&P.perm, n, "perm")) || (rc = dmalloc(&P.rep_ent, n, "rep_ent")) ||
       (rc = dmalloc(&P.zi, n, "zi")) ||
       (rc = dmalloc(&P.lnv, n, "lnv")) || (rc = dmalloc(&P.slot_z, n, "slot_z")) ||
-      (rc = dmalloc(&P.slot_ln, n, "slot_ln")) || (rc = dmalloc(&P.zpart, nc, "zpart")) ||
+      (rc = dmalloc(&P.slot_ln, n, "slot_ln")) || (rc = dmalloc(&P.zpart, (size_t)nc * kGatherSplit, "zpart")) ||
       (rc = dmalloc(&P.zg, G, "zg")) || (rc = dmalloc(&P.cost_part, (size_t)nc * kCostTerms, "cost")))
     return rc;
   TSNET_HIP(hipMemcpy(P.ginfo, P.ginfo_h.data(), sizeof(GraphInfo) * G, hipMemcpyHostToDevice));

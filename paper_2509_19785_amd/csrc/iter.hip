@@ -433,42 +433,47 @@ hipError_t launch_trim_plan(Problem& P, const float2* X, const PlanParams& pp, b
 // record, Z_i only when it is asked for). Far points (the last box of their
 // graph) were summed by k_far: their F_rep and F_ent are in place, their Z_i
 // and ln sum come from slot_z and slot_ln.
-// One block of kChunkThreads per chunk. Each block also sums the Z_i of its
-// chunk (compensated FP32, in sorted order) into zpart[chunk]; k_zsum then
-// adds every graph's chunk sums in FP64 (fixed order, so Z is reproducible)
-// into zg and Z_out.
-__global__ __launch_bounds__(kChunkThreads) void k_gather(
+// kGatherSplit blocks of kGatherThreads per chunk, each taking one part of
+// its sorted slots (several blocks of a CU keep more points in flight than one
+// large block, which the gather's registers would make the only one). Each
+// block also sums the Z_i of its part (compensated FP32, in sorted order) into
+// zpart[chunk * kGatherSplit + part]; k_zsum then adds every graph's part sums
+// in FP64 (fixed order, so Z is reproducible) into zg and Z_out.
+constexpr int kGatherThreads = 256;
+static_assert(kGatherSplit * kGatherThreads * 2 == kChunk, "two points per thread");
+
+__global__ __launch_bounds__(kGatherThreads) void k_gather(
     const float2* __restrict__ xs, const int* __restrict__ skeys, const int* __restrict__ perm,
     const int* __restrict__ chunk_graph, const int* __restrict__ chunk_start,
     const int* __restrict__ chunk_end, const GridDesc* __restrict__ desc,
     const GraphInfo* __restrict__ gi, int G, const float* __restrict__ pot,
     const float* __restrict__ slot_z, const float* __restrict__ slot_ln, float4* rep_ent,
     float* zi, float* lnv, double* zpart) {
-  constexpr int NW = kChunkThreads / kWave;
+  constexpr int NW = kGatherThreads / kWave;
   __shared__ float sh_hi[NW], sh_lo[NW];
-  const int c = blockIdx.x;
+  const int c = blockIdx.x / kGatherSplit, part = blockIdx.x - c * kGatherSplit;
   const int g = chunk_graph[c];
   const GridDesc d = desc[g];
   const float* pg = pot + d.off_p;
   const bool single = gi[g].n == 1;
   CompSum zs;
-  // the thread's points (every chunk holds at most kChunk), their slot data
-  // loaded together (clamped into the chunk) before any is used
-  constexpr int PPT = kChunk / kChunkThreads;
-  static_assert(kChunk % kChunkThreads == 0, "whole points per thread");
-  const int pa = chunk_start[c] + threadIdx.x, pe = chunk_end[c];
+  // the thread's points of the part, their slot data loaded together
+  // (clamped into the chunk) before any is used
+  constexpr int PPT = 2;
+  const int cs = chunk_start[c], pe = chunk_end[c];
+  const int pa = cs + part * (PPT * kGatherThreads) + threadIdx.x;
   float2 xv[PPT];
   int kv[PPT], iv[PPT];
 #pragma unroll
   for (int u = 0; u < PPT; ++u) {
-    const int q = min(pa + u * kChunkThreads, pe - 1);
+    const int q = max(min(pa + u * kGatherThreads, pe - 1), cs);
     xv[u] = xs[q];
     kv[u] = skeys[q];
     iv[u] = perm[q];
   }
 #pragma unroll
   for (int u = 0; u < PPT; ++u) {
-    const int p = pa + u * kChunkThreads;
+    const int p = pa + u * kGatherThreads;
     if (p >= pe) continue;
     const float2 x = xv[u];
     const int local = kv[u] - d.box_base;
@@ -531,19 +536,20 @@ __global__ __launch_bounds__(kChunkThreads) void k_gather(
   if (threadIdx.x == 0) {
     double v = 0.0;
     for (int w = 0; w < NW; ++w) v += (double)sh_hi[w] + (double)sh_lo[w];
-    zpart[c] = v;
+    zpart[blockIdx.x] = v;
   }
 }
 
-// One wave per graph: Z = the graph's chunk sums added in FP64 in chunk order.
+// One wave per graph: Z = the graph's part sums added in FP64 in chunk and
+// part order.
 __global__ __launch_bounds__(256) void k_zsum(const double* __restrict__ zpart,
                                               const GraphInfo* __restrict__ gi, int G, double* zg,
                                               double* Z_out) {
   const int g = blockIdx.x * (256 / kWave) + wave_id();
   if (g >= G) return;
   double z = 0.0;
-  const int c1 = gi[g].chunk_end;
-  for (int k0 = gi[g].chunk_begin + lane_id(); k0 < c1; k0 += kPartBatch * kWave) {
+  const int c1 = gi[g].chunk_end * kGatherSplit;
+  for (int k0 = gi[g].chunk_begin * kGatherSplit + lane_id(); k0 < c1; k0 += kPartBatch * kWave) {
     double q[kPartBatch];  // the batch's loads in flight together
 #pragma unroll
     for (int j = 0; j < kPartBatch; ++j) q[j] = k0 + j * kWave < c1 ? zpart[k0 + j * kWave] : 0.0;
@@ -561,7 +567,7 @@ hipError_t launch_gather(Problem& P, const float2* X, int with_ln, int with_zi, 
                          hipStream_t s) {
   (void)X;
   const int nb = P.num_chunks;
-  hipLaunchKernelGGL(k_gather, dim3(nb), dim3(kChunkThreads), 0, s, P.xs, P.skeys, P.perm, P.chunk_graph,
+  hipLaunchKernelGGL(k_gather, dim3(nb * kGatherSplit), dim3(kGatherThreads), 0, s, P.xs, P.skeys, P.perm, P.chunk_graph,
                      P.chunk_start, P.chunk_end, P.desc, P.ginfo, P.G, P.pot,
                      P.slot_z, P.slot_ln, P.rep_ent, with_zi ? P.zi : nullptr, with_ln ? P.lnv : nullptr, P.zpart);
   hipLaunchKernelGGL(k_zsum, dim3((P.G + 3) / 4), dim3(256), 0, s, P.zpart, P.ginfo, P.G, P.zg, Z_out);

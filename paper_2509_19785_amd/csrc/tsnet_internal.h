@@ -20,6 +20,7 @@ constexpr int kMaxM = 2 * kMaxNg;         // FFT length per axis (3 * 2^b)
 constexpr int kPotCh = 8;                 // potential channels per node (4 planes of pairs)
 constexpr int kCostTerms = 4;             // chunk sums of the cost reduction
 constexpr int kSpreadRange = 1024;        // sorted points per wave in the spread (at most)
+constexpr int kGatherSplit = 4;           // gather blocks per chunk
 constexpr int kChunk = 2048;              // vertices per chunk of per-vertex kernels
 constexpr int kMaxK = 1024;               // neighbours per vertex in tsnet_build_P
 constexpr double kSpanFloor = 1e-4;       // smallest grid span (degenerate layouts)
@@ -211,7 +212,7 @@ struct Problem {
   float4* rep_ent = nullptr;          // [n] (F_rep.x, F_rep.y, F_ent.x, F_ent.y) of each vertex
   float* zi = nullptr;                // [n]
   float* lnv = nullptr;               // [n] interpolated sum_j ln(eps + r^2) (cost path)
-  double* zpart = nullptr;            // [num_chunks] Z chunk sums of the gather
+  double* zpart = nullptr;            // [num_chunks * kGatherSplit] Z sums of the gather's parts
   double* zg = nullptr;               // [G]
   double* cost_part = nullptr;        // [num_chunks * 5]
   double* direct_part = nullptr;      // scratch of the FP64 direct kernel
