@@ -246,10 +246,10 @@ static int init_problem(Ctx& c, Problem& P, int n, const int32_t* goff_host, int
   const int nc = P.num_chunks;
   const size_t tiles = ((size_t)n + kBinTileH - 1) / kBinTileH;
   // sorted points per wave of the spread: kSpreadRange, halved (down to 64)
-  // while the problem has fewer than 256 ranges, so a small problem's spread
-  // still runs on many waves
+  // while the problem has fewer than 2048 ranges (8 waves per CU), so the
+  // spread of all but the largest problems still keeps the chip busy
   int sr = kSpreadRange;
-  while (sr > 64 && ((size_t)n + sr - 1) / sr < 256) sr >>= 1;
+  while (sr > 64 && ((size_t)n + sr - 1) / sr < 2048) sr >>= 1;
   P.spread_range = sr;
   const size_t ranges = ((size_t)n + sr - 1) / sr;
   if ((rc = dmalloc(&P.ginfo, G, "ginfo")) || (rc = dmalloc(&P.goff_d, G + 1, "goff")) ||

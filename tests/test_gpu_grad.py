@@ -379,12 +379,13 @@ def test_batch_of_twelve_graphs(api, ctx):
         assert rel_l2(got["G"][a0:a1], ex.G[a0:a1]) <= 1e-3
 
 
-@pytest.mark.parametrize("n", [40000, 100000, 200000])
+@pytest.mark.parametrize("n", [100000, 300000, 600000, 1200000])
 def test_mid_size_interpolated_terms(api, ctx, n):
-    # sizes whose spread ranges are 128, 256 and 512 sorted points (smaller
-    # problems take 64, from 261,121 vertices on 1024); 30% of the points in a
-    # tight cluster, so dense boxes span many ranges: every vertex's
-    # interpolated sums against the oracle's
+    # sizes whose spread ranges are 64, 128, 256 and 512 sorted points (the
+    # range halves from 1024 while the problem has fewer than 2048 ranges; from
+    # 2,096,129 vertices on it stays 1024); 30% of the points in a tight
+    # cluster, so dense boxes span many ranges: every vertex's interpolated
+    # sums against the oracle's
     rowptr, col, val = graphs.random_affinity(n, 4.0, 50)
     prob = api.Problem.from_host(ctx, rowptr, col, val.astype(np.float32))
     rng = np.random.default_rng(n)
