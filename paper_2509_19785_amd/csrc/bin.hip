@@ -139,7 +139,8 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const int* __restrict__ kin
       peers &= bit ? bb : ~bb;
     }
     const int rank_w = __popcll(peers & lt);
-    if (valid && (peers & lt) == 0) wc[w][dg] = __popcll(peers);
+    const bool leader = valid && (peers & lt) == 0;  // first lane of its digit in the wave
+    if (leader) wc[w][dg] = __popcll(peers);
     __syncthreads();
     if (valid) {
       int pos = run[dg] + rank_w;
@@ -149,11 +150,14 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const int* __restrict__ kin
       if (Xs) Xs[pos] = xr[round];
     }
     __syncthreads();
-    for (int d = tid; d < kDigits; d += 256) {
-      run[d] += wc[0][d] + wc[1][d] + wc[2][d] + wc[3][d];
-      for (int q = 0; q < 4; ++q) wc[q][d] = 0;
+    // only the digits of this round move on: each wave's leader adds its
+    // count (integer sums, so the order of the adds does not matter) and
+    // clears its own slot; the next round's first barrier orders these
+    // against its reads
+    if (leader) {
+      atomicAdd(&run[dg], wc[w][dg]);
+      wc[w][dg] = 0;
     }
-    __syncthreads();
   }
 }
 
