@@ -18,7 +18,8 @@
 //
 // One launch, blocks (j, g): j < nbx take far points j, j + nbx, ... of graph
 // g (a block sums over all nodes of the graph), j >= nbx sweep the graph's
-// nodes with its far points staged in LDS. Every sum runs in a fixed order.
+// nodes with its far points staged in LDS (four threads per node, each over
+// every fourth far point). Every sum runs in a fixed order.
 // Kernel values use the hardware reciprocal (1 ulp).
 #include <hip/hip_runtime.h>
 
@@ -33,6 +34,8 @@ constexpr int kFarThreads = 512;
 constexpr int kFarBatch = 512;  // far points staged in LDS at a time (node role)
 constexpr int kFarNodes = 16;   // nodes a thread loads ahead per step (far-point role)
 constexpr int kFarSums = 14;    // 8 node channels + 6 far-far direct sums
+constexpr int kFarParts = 4;    // threads per node in the node role
+constexpr int kFarNodesPerBlock = kFarThreads / kFarParts;
 
 struct FarArgs {
   const GridDesc* desc;
@@ -52,6 +55,7 @@ struct FarArgs {
 __global__ __launch_bounds__(kFarThreads) void k_far(FarArgs A) {
   __shared__ float4 fp[kFarBatch];
   __shared__ double red[kFarThreads / kWave][kFarSums];
+  __shared__ float nsum[kFarParts][8][kFarNodesPerBlock];
   const int g = blockIdx.y;
   const GridDesc d = A.desc[g];
   if (!d.trimmed) return;
@@ -145,12 +149,15 @@ __global__ __launch_bounds__(kFarThreads) void k_far(FarArgs A) {
     }
     return;
   }
-  // ---- far charges at the nodes
+  // ---- far charges at the nodes: kFarParts threads per node, each over
+  // every kFarParts-th far point, their sums joined in part order
   const int j = blockIdx.x - A.nbx;
+  const int nbn = gridDim.x - A.nbx;
+  const int part = tid / kFarNodesPerBlock, lt = tid - part * kFarNodesPerBlock;
   float2* pl = reinterpret_cast<float2*>(A.pot + d.off_p);  // 4 planes of ng^2
-  const int sweep = A.nbx * kFarThreads;
-  for (int base = j * kFarThreads; base < nodes; base += sweep) {  // uniform over the block
-    const int a = base + tid;
+  const int sweep = nbn * kFarNodesPerBlock;
+  for (int base = j * kFarNodesPerBlock; base < nodes; base += sweep) {  // uniform over the block
+    const int a = base + lt;
     const bool active = a < nodes;
     const int ay = active ? a / ng : 0, ax = active ? a - ay * ng : 0;
     const float nx = d.x0 + ((float)ax + 0.5f) * d.spacing;
@@ -167,7 +174,7 @@ __global__ __launch_bounds__(kFarThreads) void k_far(FarArgs A) {
       }
       __syncthreads();
       if (active) {
-        for (int q = 0; q < nb; ++q) {
+        for (int q = part; q < nb; q += kFarParts) {
           const float4 o = fp[q];
           const float dx = nx - o.x, dy = ny - o.y;
           const float r2 = dx * dx + dy * dy;
@@ -185,12 +192,18 @@ __global__ __launch_bounds__(kFarThreads) void k_far(FarArgs A) {
         }
       }
     }
-    if (active) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) nsum[part][k][lt] = acc[k];
+    __syncthreads();
+    if (part == 0 && active) {
 #pragma unroll
       for (int pr = 0; pr < kPotCh / 2; ++pr) {
         float2 v = pl[(size_t)pr * nodes + a];
-        v.x += acc[2 * pr];
-        v.y += acc[2 * pr + 1];
+#pragma unroll
+        for (int q = 0; q < kFarParts; ++q) {
+          v.x += nsum[q][2 * pr][lt];
+          v.y += nsum[q][2 * pr + 1][lt];
+        }
         pl[(size_t)pr * nodes + a] = v;
       }
     }
@@ -217,7 +230,7 @@ hipError_t launch_far(Problem& P, int far_trim, float eps, int with_ln, hipStrea
   A.eps = eps;
   A.with_ln = with_ln;
   A.nbx = nbx;
-  hipLaunchKernelGGL(k_far, dim3(2 * nbx, P.G), dim3(kFarThreads), 0, s, A);
+  hipLaunchKernelGGL(k_far, dim3(3 * nbx, P.G), dim3(kFarThreads), 0, s, A);  // nbx far-point blocks, 2 nbx node blocks
   return hipGetLastError();
 }
 
