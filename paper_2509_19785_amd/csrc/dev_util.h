@@ -156,16 +156,11 @@ __device__ __forceinline__ void locate(const GridDesc& d, float x, float y, int&
   t = fy - cy;
 }
 
-// Loads that bypass the non-coherent per-CU cache: used by the last block of a
-// grid to read partial results that other blocks wrote in the same launch.
+// Loads that bypass the non-coherent per-CU cache: used where a block reads
+// back values that its own threads wrote (the grid plan's descriptors).
 template <typename T>
 __device__ __forceinline__ T ld_coherent(const T* p) {
   return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ float4 ld_coherent4(const float4* p) {
-  const float* f = reinterpret_cast<const float*>(p);
-  return make_float4(ld_coherent(f), ld_coherent(f + 1), ld_coherent(f + 2), ld_coherent(f + 3));
 }
 
 __device__ __forceinline__ int graph_of(const int* goff, int G, int v) {

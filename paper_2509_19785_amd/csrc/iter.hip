@@ -23,7 +23,6 @@ namespace tsnet {
 // through a last-block counter: on this GPU a device-wide fence writes back
 // and invalidates the L2 of the block's XCD, and one per block cost more than
 // the work it guards.
-constexpr int kChunkThreads = 1024;
 constexpr int kPartBatch = 8;  // chunk partials a lane of the final reduction loads at once
 
 constexpr int kBboxThreads = 256;
@@ -623,8 +622,8 @@ hipError_t launch_step(Problem& P, float2* X, float2* upd, float2* gains, const 
 //  per row: sum_j p_ij (ln p_ij + ln(1 + r_ij^2)) over p > 0 and sum_j p_ij;
 //  per chunk: compensated sums of those, of ||X_i||^2 and of the interpolated
 //  sum_j ln(eps + r_ij^2) (self term ln eps included);
-//  per graph (last block): C_KL = l_kl (S_pl + S_p ln Z) with the Z the gather
-//  reduced, C_CMP, C_ENT, total.
+//  per graph (k_cost_join): C_KL = l_kl (S_pl + S_p ln Z) with the Z the
+//  gather reduced, C_CMP, C_ENT, total.
 __global__ __launch_bounds__(256) void k_cost_rows(const float2* __restrict__ X,
                                                    const int64_t* __restrict__ rowptr,
                                                    const int* __restrict__ col,
