@@ -700,8 +700,12 @@ hipError_t launch_fft_conv(Problem& P, float eps, int with_ln, int max_intervals
     hipLaunchKernelGGL(k_fft_rows_fwd<FftLarge>, dim3(bx, P.G), dim3(FftLarge::Threads),
                        FftLarge::Lds, s, A);
   hipLaunchKernelGGL(k_fft_transpose, dim3(2 * tb, P.G), dim3(256), 0, s, A, 0);
-  hipLaunchKernelGGL(k_fft_cols<FftSmall>, dim3(bx, P.G), dim3(FftSmall::Threads), FftSmall::Lds, s,
-                     A);
+  // the column kernel's registers hold three of its blocks per CU: in a batch
+  // of 256 graphs, three blocks per graph fill the chip in one round where
+  // four would take a second, mostly idle one
+  const int cbx = P.G >= 64 ? 3 : bx;
+  hipLaunchKernelGGL(k_fft_cols<FftSmall>, dim3(cbx, P.G), dim3(FftSmall::Threads), FftSmall::Lds,
+                     s, A);
   if (large)
     hipLaunchKernelGGL(k_fft_cols<FftLarge>, dim3(bx, P.G), dim3(FftLarge::Threads), FftLarge::Lds,
                        s, A);
