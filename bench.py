@@ -31,8 +31,8 @@ HBM_PEAK_GBS = 8000.0
 # (FETCH_SIZE x 2 + WRITE_SIZE x 1, KiB x 1024; the factors from a 1 GiB device
 # copy), summarised under profiles/. They hold for the kernel source with the
 # hash below only: for any other source the traffic is reported as null.
-ATTRACT_TRAFFIC_BYTES = 1_824_707_635
-ATTRACT_TRAFFIC_SOURCE_SHA256 = "1fef192adfeb8e9e097dffadf443e88bc96f4e4a21f3b34497dd55fbaf47e858"
+ATTRACT_TRAFFIC_BYTES = 1_824_396_638
+ATTRACT_TRAFFIC_SOURCE_SHA256 = "35f8a3af941ac3538812a2266335c839df048d2bb97f11072ef6373272e006ba"
 
 
 def attract_traffic():

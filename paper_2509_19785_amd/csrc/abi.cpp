@@ -162,6 +162,7 @@ static void free_problem(Problem& P) {
   dfree(P.tile_wlo);
   dfree(P.tile_boff);
   dfree(P.tile_graph);
+  dfree(P.tile_order);
   dfree(P.tile_bstart);
   dfree(P.tile_ent);
   P.tile_T = P.tile_R = 0;

@@ -58,6 +58,7 @@ struct TileArgs {
   const int* wlo;         // [T] first column window of each tile
   const int* boff;        // [T + 1] first block of each tile
   const int* tgraph;      // [T] graph of each tile
+  const int* order;       // [T] tile of each block: tiles by decreasing entry count
   const int* bstart;      // [NB + 1] first entry of every block
   const uint2* ent;       // [nnz]
   const GraphInfo* gi;
@@ -255,7 +256,7 @@ __global__ __launch_bounds__(kTileThreads) void k_attract_tiled(TileArgs a) {
   __shared__ int hrow[kTileWaves];
   __shared__ float2 hval[kTileWaves];
   __shared__ int bst[kTileMaxNC + 1];
-  const int t = blockIdx.x, tid = threadIdx.x, lane = lane_id(), wv = wave_id();
+  const int t = a.order[blockIdx.x], tid = threadIdx.x, lane = lane_id(), wv = wave_id();
   const int R = a.R, n = a.n;
   const int b0 = a.boff[t], NC = a.boff[t + 1] - b0;  // the tile's windows
   const int xw = a.wlo[t] * kTileCols;                 // first vertex of its first window
@@ -408,6 +409,7 @@ hipError_t launch_attract_tiled(Problem& P, const float2* X, const tsnet_params&
   a.wlo = P.tile_wlo;
   a.boff = P.tile_boff;
   a.tgraph = P.tile_graph;
+  a.order = P.tile_order;
   a.bstart = P.tile_bstart;
   a.ent = P.tile_ent;
   a.gi = P.ginfo;
@@ -524,6 +526,7 @@ int build_tiles(Problem& P, hipStream_t s) {
   std::iota(order.begin(), order.end(), 0);
   std::vector<int> tslot(n), rows((size_t)T * R, -1);
   std::vector<int> wlo(T), boff(T + 1), tgraph(T);
+  std::vector<int64_t> tnnz(T, 0);  // entries per tile
   for (int g = 0; g < P.G; ++g) {
     const int lo = P.goff[g], hi = P.goff[g + 1];
     const int Tg = tp.first[g + 1] - tp.first[g];
@@ -535,6 +538,7 @@ int build_tiles(Problem& P, hipStream_t s) {
       const int tile = tp.first[g] + ((round & 1) ? Tg - 1 - idx : idx);
       tslot[order[lo + q]] = tile * R + round;
       rows[(size_t)tile * R + round] = order[lo + q];
+      tnnz[tile] += rp[order[lo + q] + 1] - rp[order[lo + q]];
     }
     for (int t = tp.first[g]; t < tp.first[g + 1]; ++t) {
       wlo[t] = lo >> kTileColBits;
@@ -543,7 +547,12 @@ int build_tiles(Problem& P, hipStream_t s) {
     }
   }
   int *rows_d = nullptr, *bstart_d = nullptr, *tslot_d = nullptr;
-  int *wlo_d = nullptr, *boff_d = nullptr, *tgraph_d = nullptr;
+  // blocks take the tiles largest first, so the last blocks of a launch with
+  // more tiles than CUs are the shortest (tiles of one graph are equal)
+  std::vector<int> torder(T);
+  std::iota(torder.begin(), torder.end(), 0);
+  std::stable_sort(torder.begin(), torder.end(), [&](int x, int y) { return tnnz[x] > tnnz[y]; });
+  int *wlo_d = nullptr, *boff_d = nullptr, *tgraph_d = nullptr, *torder_d = nullptr;
   uint2* ent_d = nullptr;
   unsigned *keys = nullptr, *vals = nullptr, *kt = nullptr, *vt = nullptr;
   int *hist = nullptr, *tsum = nullptr;
@@ -570,14 +579,15 @@ int build_tiles(Problem& P, hipStream_t s) {
       (rc = alloc(&wlo_d, (size_t)T, "tile windows")) ||
       (rc = alloc(&boff_d, (size_t)T + 1, "tile block offsets")) ||
       (rc = alloc(&tgraph_d, (size_t)T, "tile graphs")) ||
+      (rc = alloc(&torder_d, (size_t)T, "tile order")) ||
       (rc = alloc(&bstart_d, (size_t)nb + 1, "tile blocks")) ||
       (rc = alloc(&ent_d, (size_t)nnz, "tile entries")) ||
       (rc = alloc(&tslot_d, (size_t)n, "tile slots")) || (rc = alloc(&keys, (size_t)nnz, "keys")) ||
       (rc = alloc(&vals, (size_t)nnz, "vals")) || (rc = alloc(&kt, (size_t)nnz, "keys")) ||
       (rc = alloc(&vt, (size_t)nnz, "vals")) || (rc = alloc(&hist, (size_t)hist_len + 1, "hist")) ||
       (rc = alloc(&tsum, (size_t)tsum_len, "scan"))) {
-    release({rows_d, wlo_d, boff_d, tgraph_d, bstart_d, ent_d, tslot_d, keys, vals, kt, vt, hist,
-             tsum});
+    release({rows_d, wlo_d, boff_d, tgraph_d, torder_d, bstart_d, ent_d, tslot_d, keys, vals, kt,
+             vt, hist, tsum});
     return rc;
   }
   hipError_t e = hipMemcpyAsync(rows_d, rows.data(), sizeof(int) * rows.size(),
@@ -588,6 +598,8 @@ int build_tiles(Problem& P, hipStream_t s) {
     e = hipMemcpyAsync(boff_d, boff.data(), sizeof(int) * (T + 1), hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(tgraph_d, tgraph.data(), sizeof(int) * T, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(torder_d, torder.data(), sizeof(int) * T, hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(tslot_d, tslot.data(), sizeof(int) * n, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) {
@@ -613,13 +625,14 @@ int build_tiles(Problem& P, hipStream_t s) {
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   release({tslot_d, keys, vals, kt, vt, hist, tsum});
   if (e != hipSuccess) {
-    release({rows_d, wlo_d, boff_d, tgraph_d, bstart_d, ent_d});
+    release({rows_d, wlo_d, boff_d, tgraph_d, torder_d, bstart_d, ent_d});
     return fail(TSNET_EHIP, std::string("tiled layout: ") + hipGetErrorString(e));
   }
   P.tile_rows = rows_d;
   P.tile_wlo = wlo_d;
   P.tile_boff = boff_d;
   P.tile_graph = tgraph_d;
+  P.tile_order = torder_d;
   P.tile_bstart = bstart_d;
   P.tile_ent = ent_d;
   P.tile_T = T;

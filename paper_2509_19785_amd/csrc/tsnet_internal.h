@@ -166,6 +166,7 @@ struct Problem {
   int* tile_wlo = nullptr;            // [T] first column window of each tile
   int* tile_boff = nullptr;           // [T + 1] first block of each tile
   int* tile_graph = nullptr;          // [T] graph of each tile's rows
+  int* tile_order = nullptr;          // [T] tile of each block (largest tiles first)
   int* tile_bstart = nullptr;         // [NB + 1] first entry of each block
   uint2* tile_ent = nullptr;          // [nnz] {slot << 13 | column in window, value bits}
   // device: conditional rows and calibration (absent for host-made P)
