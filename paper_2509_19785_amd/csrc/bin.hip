@@ -50,7 +50,7 @@ __device__ __forceinline__ int box_key(const GridDesc& d, float x, float y) {
   return d.box_base + by * d.n_int + bx;
 }
 
-// Pass 0: keys of tile `blockIdx.x` and its digit histogram.
+// Pass 0: keys of one tile and its digit histogram.
 __global__ __launch_bounds__(256) void k_bin_keys(const float2* __restrict__ X, int n,
                                                   const int* __restrict__ vgraph, int G,
                                                   const GridDesc* __restrict__ desc, int* keys,
@@ -58,7 +58,7 @@ __global__ __launch_bounds__(256) void k_bin_keys(const float2* __restrict__ X, 
   __shared__ int cnt[kDigits];
   for (int q = threadIdx.x; q < kDigits; q += 256) cnt[q] = 0;
   __syncthreads();
-  const int base = blockIdx.x * kBinTile;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x), base = tile * kBinTile;
   float2 p[kBinRounds];  // every load of the tile issued before any is used
 #pragma unroll
   for (int r = 0; r < kBinRounds; ++r) p[r] = X[min(base + r * 256 + (int)threadIdx.x, n - 1)];
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(256) void k_bin_keys(const float2* __restrict__ X, 
     }
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < kDigits; q += 256) hist[q * tiles + blockIdx.x] = cnt[q];
+  for (int q = threadIdx.x; q < kDigits; q += 256) hist[q * tiles + tile] = cnt[q];
 }
 
 __global__ __launch_bounds__(256) void k_bin_hist(const int* __restrict__ keys, int n, int shift,
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(256) void k_bin_hist(const int* __restrict__ keys, 
   __shared__ int cnt[kDigits];
   for (int q = threadIdx.x; q < kDigits; q += 256) cnt[q] = 0;
   __syncthreads();
-  const int base = blockIdx.x * kBinTile;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x), base = tile * kBinTile;
   int k[kBinRounds];  // every load of the tile issued before any is used
 #pragma unroll
   for (int r = 0; r < kBinRounds; ++r) k[r] = keys[min(base + r * 256 + (int)threadIdx.x, n - 1)];
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(256) void k_bin_hist(const int* __restrict__ keys, 
   for (int r = 0; r < kBinRounds; ++r)
     if (base + r * 256 + (int)threadIdx.x < n) atomicAdd(&cnt[(k[r] >> shift) & (kDigits - 1)], 1);
   __syncthreads();
-  for (int q = threadIdx.x; q < kDigits; q += 256) hist[q * tiles + blockIdx.x] = cnt[q];
+  for (int q = threadIdx.x; q < kDigits; q += 256) hist[q * tiles + tile] = cnt[q];
 }
 
 // Stable scatter of one pass. vin == nullptr means the payload is the index.
@@ -102,13 +102,14 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const int* __restrict__ kin
   __shared__ int run[kDigits];
   __shared__ int wc[4][kDigits];
   const int tid = threadIdx.x, w = wave_id(), lane = lane_id();
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
   for (int d = tid; d < kDigits; d += 256) {
-    run[d] = offs[d * tiles + blockIdx.x];
+    run[d] = offs[d * tiles + tile];
     for (int q = 0; q < 4; ++q) wc[q][d] = 0;
   }
   __syncthreads();
   const u64 lt = (1ull << lane) - 1ull;
-  const int base = blockIdx.x * kBinTile;
+  const int base = tile * kBinTile;
   // the tile's keys and payloads (and on the last pass the X rows they name)
   // are loaded before the first round: one memory latency per tile, not one
   // per round

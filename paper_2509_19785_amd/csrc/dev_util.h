@@ -12,6 +12,18 @@ constexpr int kWave = 64;
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 __device__ __forceinline__ int wave_id() { return threadIdx.x / kWave; }
 
+// The dispatcher deals workgroups to the chip's 8 XCDs in turn (workgroup b
+// to XCD b % 8), and each XCD has an L2 of its own. This renumbers the
+// workgroups of a grid of nb so that XCD x takes one contiguous range of
+// tiles (a bijection of [0, nb)): tiles that share cache lines, such as
+// neighbouring columns of a digit-major count matrix or the adjacent output
+// runs of a stable scatter, then meet in one L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int x = b % kXcds, q = b / kXcds, per = nb / kXcds, rem = nb % kXcds;
+  return x * per + min(x, rem) + q;
+}
+
 // Cross-lane moves as DPP operand modifiers (VALU, no LDS traffic). Controls: row_shr:n / row_shl:n shift within rows of 16 lanes, row_bcast:15
 // and :31 carry the last lane of a row (of rows 0-1) into the next row (rows
 // 2-3), wave_shr:1 / wave_shl:1 shift by one lane across the whole wave.
