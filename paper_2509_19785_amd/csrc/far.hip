@@ -75,7 +75,11 @@ __global__ __launch_bounds__(kFarThreads) void k_far(FarArgs A) {
       float acc[kFarSums];
 #pragma unroll
       for (int k = 0; k < kFarSums; ++k) acc[k] = 0.f;
-      // kFarNodes nodes per step, all their charges loaded before any is used
+      // kFarNodes nodes per step, all their charges loaded before any is used.
+      // The thread's nodes advance by kFarThreads: their row and column are
+      // carried along (a division per node would cost a third of the loop)
+      const int sy = kFarThreads / ng, sx = kFarThreads - sy * ng;
+      int ay = tid / ng, ax = tid - ay * ng;
       for (int a0 = tid; a0 < nodes; a0 += kFarNodes * kFarThreads) {
         float w1[kFarNodes], wx[kFarNodes], wy[kFarNodes];
 #pragma unroll
@@ -89,7 +93,6 @@ __global__ __launch_bounds__(kFarThreads) void k_far(FarArgs A) {
         for (int u = 0; u < kFarNodes; ++u) {
           const int a = a0 + u * kFarThreads;
           if (a < nodes) {
-            const int ay = a / ng, ax = a - ay * ng;
             const float dx = xo.x - (d.x0 + ((float)ax + 0.5f) * d.spacing);
             const float dy = xo.y - (d.y0 + ((float)ay + 0.5f) * d.spacing);
             const float r2 = dx * dx + dy * dy;
@@ -104,6 +107,12 @@ __global__ __launch_bounds__(kFarThreads) void k_far(FarArgs A) {
             acc[5] += ke * wx[u];
             acc[6] += ke * wy[u];
             if (A.with_ln) acc[7] += logf(A.eps + r2) * w1[u];
+          }
+          ax += sx;
+          ay += sy;
+          if (ax >= ng) {
+            ax -= ng;
+            ++ay;
           }
         }
       }
