@@ -438,6 +438,36 @@ hipError_t launch_trim_plan(Problem& P, const float2* X, const PlanParams& pp, b
 // block also sums the Z_i of its part (compensated FP32, in sorted order) into
 // zpart[chunk * kGatherSplit + part]; k_zsum then adds every graph's part sums
 // in FP64 (fixed order, so Z is reproducible) into zg and Z_out.
+// phi = the 8 potential channels at x, interpolated from the 3 x 3 nodes of
+// box (bx, by): the Lagrange weights of the point times the node values (the
+// potentials are 4 planes, one per channel pair, of ng^2 float2 nodes).
+__device__ __forceinline__ void gather_box(const float* __restrict__ pg, const GridDesc& d,
+                                           float2 x, int by, int bx, float (&phi)[8]) {
+  const float s = (x.x - d.x0) * d.inv_h - (float)bx;
+  const float t = (x.y - d.y0) * d.inv_h - (float)by;
+  float lx[3], ly[3];
+  lagrange3(s, lx);
+  lagrange3(t, ly);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) phi[k] = 0.f;
+  const float2* pl = reinterpret_cast<const float2*>(pg);
+  const size_t plane = (size_t)d.ng * d.ng;
+#pragma unroll
+  for (int ty = 0; ty < 3; ++ty) {
+    const size_t row = (size_t)(3 * by + ty) * d.ng + 3 * bx;
+#pragma unroll
+    for (int tx = 0; tx < 3; ++tx) {
+      const float w = ly[ty] * lx[tx];
+#pragma unroll
+      for (int pr = 0; pr < kPotCh / 2; ++pr) {
+        const float2 v = pl[pr * plane + row + tx];
+        phi[2 * pr] += w * v.x;
+        phi[2 * pr + 1] += w * v.y;
+      }
+    }
+  }
+}
+
 constexpr int kGatherThreads = 256;
 static_assert(kGatherSplit * kGatherThreads * 2 == kChunk, "two points per thread");
 
@@ -470,45 +500,39 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(
     kv[u] = skeys[q];
     iv[u] = perm[q];
   }
+  // the box of each point (n_int is a power of two: the plan rounds up to
+  // one and only halves it); far points, the last box of their graph, take
+  // their sums from k_far
+  const int lg = __builtin_ctz((unsigned)d.n_int), far_local = d.n_int * d.n_int;
+  int loc[PPT];
+  bool act[PPT];
+  // whether, for each u, the wave's interpolated points share one box (the
+  // common case in sorted order): their node potentials then have one
+  // address per wave and come through the scalar cache. One decision for
+  // all u, so that either way every point's loads are in flight together.
+  bool uni = true;
+  int kb[PPT];
 #pragma unroll
   for (int u = 0; u < PPT; ++u) {
+    loc[u] = kv[u] - d.box_base;
+    act[u] = pa + u * kGatherThreads < pe && loc[u] != far_local;
+    const unsigned long long m = __ballot(act[u]);
+    kb[u] = m ? __builtin_amdgcn_readlane(loc[u], __ffsll((long long)m) - 1) : 0;
+    uni = uni && __ballot(act[u] && loc[u] != kb[u]) == 0;
+  }
+  auto point = [&](int u, int by, int bx) {
     const int p = pa + u * kGatherThreads;
-    if (p >= pe) continue;
-    const float2 x = xv[u];
-    const int local = kv[u] - d.box_base;
-    if (local == d.n_int * d.n_int) {  // a far point: its sums come from k_far
+    if (p >= pe) return;
+    if (!act[u]) {
       const float z = slot_z[p];
       if (zi) zi[iv[u]] = z;
       if (lnv) lnv[iv[u]] = slot_ln[p];
       zs.add(z);
-      continue;
+      return;
     }
-    const int by = local / d.n_int, bx = local - by * d.n_int;
-    const float s = (x.x - d.x0) * d.inv_h - (float)bx;
-    const float t = (x.y - d.y0) * d.inv_h - (float)by;
-    float lx[3], ly[3];
-    lagrange3(s, lx);
-    lagrange3(t, ly);
+    const float2 x = xv[u];
     float phi[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) phi[k] = 0.f;
-    // the potentials are 4 planes (channel pairs) of ng^2 float2 nodes
-    const float2* pl = reinterpret_cast<const float2*>(pg);
-    const size_t plane = (size_t)d.ng * d.ng;
-#pragma unroll
-    for (int ty = 0; ty < 3; ++ty) {
-      const size_t row = (size_t)(3 * by + ty) * d.ng + 3 * bx;
-#pragma unroll
-      for (int tx = 0; tx < 3; ++tx) {
-        const float w = ly[ty] * lx[tx];
-#pragma unroll
-        for (int pr = 0; pr < kPotCh / 2; ++pr) {
-          const float2 v = pl[pr * plane + row + tx];
-          phi[2 * pr] += w * v.x;
-          phi[2 * pr + 1] += w * v.y;
-        }
-      }
-    }
+    gather_box(pg, d, x, by, bx, phi);
     const float xt = x.x - d.cx, yt = x.y - d.cy;
     float2 r = make_float2(xt * phi[CH_K2_1] - d.half * phi[CH_K2_X],
                            yt * phi[CH_K2_1] - d.half * phi[CH_K2_Y]);
@@ -525,6 +549,13 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(
     if (zi) zi[i] = z;
     if (lnv) lnv[i] = single ? 0.f : phi[CH_KLN_1];
     zs.add(z);
+  };
+  if (uni) {
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) point(u, kb[u] >> lg, kb[u] & (d.n_int - 1));
+  } else {
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) point(u, loc[u] >> lg, loc[u] & (d.n_int - 1));
   }
   zs = wave_comp_sum(zs);
   if (lane_id() == 0) {
