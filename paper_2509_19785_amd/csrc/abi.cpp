@@ -184,6 +184,7 @@ static void free_problem(Problem& P) {
   dfree(P.xs);
   dfree(P.bin_hist);
   dfree(P.bin_tsum);
+  dfree(P.bin_used);
   dfree(P.row_order);
   dfree(P.head_box);
   dfree(P.tail_box);
@@ -263,6 +264,7 @@ static int init_problem(Ctx& c, Problem& P, int n, const int32_t* goff_host, int
       (rc = dmalloc(&P.xs, n, "xs")) ||
       (rc = dmalloc(&P.bin_hist, ((size_t)1 << kBinDigitBits) * tiles + 1, "hist")) ||
       (rc = dmalloc(&P.bin_tsum, ((size_t)1 << kBinDigitBits) * tiles / 2048 + 8, "hist")) ||
+      (rc = dmalloc(&P.bin_used, 1, "hist")) ||
       (rc = dmalloc(&P.head_box, ranges, "ranges")) || (rc = dmalloc(&P.tail_box, ranges, "ranges")) ||
       (rc = dmalloc(&P.head_val, ranges * 27, "ranges")) ||
       (rc = dmalloc(&P.tail_val, ranges * 27, "ranges")) ||

@@ -31,6 +31,12 @@ constexpr int kBinRounds = kBinTile / 256;  // points per thread of a tile
 constexpr int kDigitBits = kBinDigitBits;
 constexpr int kDigits = 1 << kDigitBits;   // buckets per pass
 
+// Digit values that occur in pass `shift` when the keys lie in [0, B): rows
+// of the digit-major count matrix past them stay unwritten and unscanned.
+__device__ __forceinline__ int digits_used(int B, int shift) {
+  return min(kDigits, ((max(B, 1) - 1) >> shift) + 1);
+}
+
 // Bin of a coordinate under the far-point rule (the grid plan's function).
 __device__ __forceinline__ int trim_bin_of(float v, float vmin, double s) {
   const double f = floor(((double)v - (double)vmin) * s);
@@ -54,7 +60,8 @@ __device__ __forceinline__ int box_key(const GridDesc& d, float x, float y) {
 __global__ __launch_bounds__(256) void k_bin_keys(const float2* __restrict__ X, int n,
                                                   const int* __restrict__ vgraph, int G,
                                                   const GridDesc* __restrict__ desc, int* keys,
-                                                  int tiles, int* hist) {
+                                                  int tiles, const int* __restrict__ btotal,
+                                                  int* hist, int64_t* used) {
   __shared__ int cnt[kDigits];
   for (int q = threadIdx.x; q < kDigits; q += 256) cnt[q] = 0;
   __syncthreads();
@@ -73,11 +80,14 @@ __global__ __launch_bounds__(256) void k_bin_keys(const float2* __restrict__ X, 
     }
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < kDigits; q += 256) hist[q * tiles + tile] = cnt[q];
+  const int D = digits_used(*btotal, 0);
+  for (int q = threadIdx.x; q < D; q += 256) hist[q * tiles + tile] = cnt[q];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *used = (int64_t)D * tiles;
 }
 
 __global__ __launch_bounds__(256) void k_bin_hist(const int* __restrict__ keys, int n, int shift,
-                                                  int tiles, int* hist) {
+                                                  int tiles, const int* __restrict__ btotal,
+                                                  int* hist, int64_t* used) {
   __shared__ int cnt[kDigits];
   for (int q = threadIdx.x; q < kDigits; q += 256) cnt[q] = 0;
   __syncthreads();
@@ -89,22 +99,26 @@ __global__ __launch_bounds__(256) void k_bin_hist(const int* __restrict__ keys, 
   for (int r = 0; r < kBinRounds; ++r)
     if (base + r * 256 + (int)threadIdx.x < n) atomicAdd(&cnt[(k[r] >> shift) & (kDigits - 1)], 1);
   __syncthreads();
-  for (int q = threadIdx.x; q < kDigits; q += 256) hist[q * tiles + tile] = cnt[q];
+  const int D = digits_used(*btotal, shift);
+  for (int q = threadIdx.x; q < D; q += 256) hist[q * tiles + tile] = cnt[q];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *used = (int64_t)D * tiles;
 }
 
 // Stable scatter of one pass. vin == nullptr means the payload is the index.
 // When Xs != nullptr (last pass) X[payload] is written to Xs in sorted order.
 __global__ __launch_bounds__(256) void k_bin_scatter(const int* __restrict__ kin,
                                                      const int* __restrict__ vin, int n, int shift,
-                                                     int tiles, const int* __restrict__ offs,
+                                                     int tiles, const int* __restrict__ btotal,
+                                                     const int* __restrict__ offs,
                                                      int* kout, int* vout,
                                                      const float2* __restrict__ X, float2* Xs) {
   __shared__ int run[kDigits];
   __shared__ int wc[4][kDigits];
   const int tid = threadIdx.x, w = wave_id(), lane = lane_id();
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int D = digits_used(*btotal, shift);  // digits past D occur in no key
   for (int d = tid; d < kDigits; d += 256) {
-    run[d] = offs[d * tiles + tile];
+    run[d] = d < D ? offs[d * tiles + tile] : 0;
     for (int q = 0; q < 4; ++q) wc[q][d] = 0;
   }
   __syncthreads();
@@ -199,12 +213,15 @@ hipError_t launch_bin(Problem& P, const float2* X, hipStream_t s) {
   int* kin = P.keys;
   int* vin = nullptr;
   hipLaunchKernelGGL(k_bin_keys, dim3(tiles), dim3(256), 0, s, X, n, P.vgraph, P.G, P.desc, P.keys,
-                     tiles, P.bin_hist);
+                     tiles, P.btotal, P.bin_hist, P.bin_used);
   for (int p = 0; p < passes; ++p) {
     const int shift = kDigitBits * p;
     if (p > 0)
-      hipLaunchKernelGGL(k_bin_hist, dim3(tiles), dim3(256), 0, s, kin, n, shift, tiles, P.bin_hist);
-    hipError_t e = exclusive_scan<int>(P.bin_hist, (int64_t)kDigits * tiles, P.bin_hist, P.bin_tsum, s);
+      hipLaunchKernelGGL(k_bin_hist, dim3(tiles), dim3(256), 0, s, kin, n, shift, tiles, P.btotal,
+                         P.bin_hist, P.bin_used);
+    // only the digit rows in use (the count matrix is digit-major)
+    hipError_t e = exclusive_scan<int>(P.bin_hist, (int64_t)kDigits * tiles, P.bin_hist, P.bin_tsum, s,
+                                       P.bin_used);
     if (e != hipSuccess) return e;
     const bool last = p == passes - 1;
     int *kout, *vout;
@@ -219,7 +236,7 @@ hipError_t launch_bin(Problem& P, const float2* X, hipStream_t s) {
       vout = P.perm_tmp2;
     }
     hipLaunchKernelGGL(k_bin_scatter, dim3(tiles), dim3(256), 0, s, kin, vin, n, shift, tiles,
-                       P.bin_hist, kout, vout, X, last ? P.xs : nullptr);
+                       P.btotal, P.bin_hist, kout, vout, X, last ? P.xs : nullptr);
     kin = kout;
     vin = vout;
   }
