@@ -149,26 +149,37 @@ __device__ __forceinline__ int trim_bin(float v, float vmin, double s) {
   return f >= 0.0 ? (f < (double)(kTrimBins - 1) ? (int)f : kTrimBins - 1) : 0;
 }
 
-// Per chunk of a graph the far-point rule may apply to: bin counts of both
-// axes in LDS, added to the graph's counts (integer atomics, so the counts do
-// not depend on the order).
+// Per cpb consecutive chunks of a graph the far-point rule may apply to (cpb
+// > 1 only for a single graph, whose chunks are all its own): bin counts of
+// both axes in LDS, added to the graph's counts (integer atomics, so the
+// counts do not depend on the order).
 constexpr int kTrimThreads = 1024;
+constexpr int kTrimChunksSingle = 4;
 
 __global__ __launch_bounds__(kTrimThreads) void k_trim_hist(
     const float2* __restrict__ X, const int* __restrict__ chunk_graph,
-    const int* __restrict__ chunk_start, const int* __restrict__ chunk_end,
+    const int* __restrict__ chunk_start, const int* __restrict__ chunk_end, int nc, int cpb,
     const GridDesc* __restrict__ desc, int* hist) {
   __shared__ int hx[kTrimBins], hy[kTrimBins];
-  const int c = blockIdx.x;
-  const int g = chunk_graph[c];
+  const int c0 = blockIdx.x * cpb, c1 = min(c0 + cpb, nc);
+  const int g = chunk_graph[c0];
   const GridDesc d = desc[g];
   if (!d.trimmed) return;
   for (int b = threadIdx.x; b < kTrimBins; b += kTrimThreads) hx[b] = hy[b] = 0;
   __syncthreads();
-  for (int i = chunk_start[c] + threadIdx.x; i < chunk_end[c]; i += kTrimThreads) {
-    const float2 p = X[i];
-    atomicAdd(&hx[trim_bin(p.x, d.bmin_x, d.s_x)], 1);
-    atomicAdd(&hy[trim_bin(p.y, d.bmin_y, d.s_y)], 1);
+  const int i0 = chunk_start[c0], i1 = chunk_end[c1 - 1];
+  constexpr int U = 4;  // points per thread loaded together
+  for (int base = i0; base < i1; base += U * kTrimThreads) {
+    float2 p[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) p[u] = X[min(base + u * kTrimThreads + (int)threadIdx.x, i1 - 1)];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (base + u * kTrimThreads + (int)threadIdx.x < i1) {
+        atomicAdd(&hx[trim_bin(p[u].x, d.bmin_x, d.s_x)], 1);
+        atomicAdd(&hy[trim_bin(p[u].y, d.bmin_y, d.s_y)], 1);
+      }
+    }
   }
   __syncthreads();
   int* h = hist + (size_t)g * 2 * kTrimBins;
@@ -411,9 +422,12 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_pools(GridDesc* desc, int
 
 hipError_t launch_trim_plan(Problem& P, const float2* X, const PlanParams& pp, bool with_hist,
                             hipStream_t s) {
-  if (with_hist)
-    hipLaunchKernelGGL(k_trim_hist, dim3(P.num_chunks), dim3(kTrimThreads), 0, s, X, P.chunk_graph,
-                       P.chunk_start, P.chunk_end, P.desc, P.trim_hist);
+  if (with_hist) {
+    const int cpb = P.G == 1 ? kTrimChunksSingle : 1;
+    hipLaunchKernelGGL(k_trim_hist, dim3((P.num_chunks + cpb - 1) / cpb), dim3(kTrimThreads), 0, s, X,
+                       P.chunk_graph, P.chunk_start, P.chunk_end, P.num_chunks, cpb, P.desc,
+                       P.trim_hist);
+  }
   hipLaunchKernelGGL(k_trim_plan, dim3(P.G), dim3(kPlanThreads), 0, s, P.desc, P.trim_hist, pp,
                      P.ctx->status, P.G == 1 ? P.btotal : nullptr);
   if (P.G > 1)
