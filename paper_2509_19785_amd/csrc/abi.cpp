@@ -183,8 +183,7 @@ static void free_problem(Problem& P) {
   dfree(P.perm);
   dfree(P.xs);
   dfree(P.bin_hist);
-  dfree(P.bin_tsum);
-  dfree(P.bin_used);
+  dfree(P.bin_rtot);
   dfree(P.row_order);
   dfree(P.head_box);
   dfree(P.tail_box);
@@ -262,9 +261,8 @@ static int init_problem(Ctx& c, Problem& P, int n, const int32_t* goff_host, int
       (rc = dmalloc(&P.keys_tmp, n, "keys")) || (rc = dmalloc(&P.perm_tmp, n, "perm")) ||
       (rc = dmalloc(&P.perm_tmp2, n, "perm")) || (rc = dmalloc(&P.skeys, n, "keys")) ||
       (rc = dmalloc(&P.xs, n, "xs")) ||
-      (rc = dmalloc(&P.bin_hist, ((size_t)1 << kBinDigitBits) * tiles + 1, "hist")) ||
-      (rc = dmalloc(&P.bin_tsum, ((size_t)1 << kBinDigitBits) * tiles / 2048 + 8, "hist")) ||
-      (rc = dmalloc(&P.bin_used, 1, "hist")) ||
+      (rc = dmalloc(&P.bin_hist, ((size_t)1 << kBinDigitBits) * tiles, "hist")) ||
+      (rc = dmalloc(&P.bin_rtot, (size_t)1 << kBinDigitBits, "hist")) ||
       (rc = dmalloc(&P.head_box, ranges, "ranges")) || (rc = dmalloc(&P.tail_box, ranges, "ranges")) ||
       (rc = dmalloc(&P.head_val, ranges * 27, "ranges")) ||
       (rc = dmalloc(&P.tail_val, ranges * 27, "ranges")) ||

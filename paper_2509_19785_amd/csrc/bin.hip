@@ -3,10 +3,12 @@
 // Binning: stable LSD radix sort (10-bit digits: two passes cover the
 // 2^18 + 1 boxes of a 512 x 512 grid and its far box) of the global box id
 // of every point. Tiles of 2048 points rank their digits in LDS with wave
-// ballots, so
-// no global atomics are needed and the order is deterministic (by box, then
-// by vertex id). Pass 0 computes the keys from X; the last pass also gathers
-// X into sorted order. box_off[b] is the first sorted slot of box b.
+// ballots, so no global atomics are needed and the order is deterministic
+// (by box, then by vertex id). Pass 0 computes the keys from X; the last
+// pass also gathers X into sorted order. Per pass, the counts of the digits
+// that occur are kept digit-major (one row per digit, one count per tile),
+// turned into row prefixes one wave per row, and each scatter tile adds the
+// digit bases itself. box_off[b] is the first sorted slot of box b.
 //
 // Spread (Sec. 2.3): node charge w[c][a] = sum over the points of the node's
 // box of L_tx(s) L_ty(t) q_c, q = (1, (x - cx) / half, (y - cy) / half).
@@ -20,7 +22,6 @@
 #include <hip/hip_runtime.h>
 
 #include "dev_util.h"
-#include "scan.h"
 #include "tsnet_internal.h"
 
 namespace tsnet {
@@ -61,7 +62,7 @@ __global__ __launch_bounds__(256) void k_bin_keys(const float2* __restrict__ X, 
                                                   const int* __restrict__ vgraph, int G,
                                                   const GridDesc* __restrict__ desc, int* keys,
                                                   int tiles, const int* __restrict__ btotal,
-                                                  int* hist, int64_t* used) {
+                                                  int* hist) {
   __shared__ int cnt[kDigits];
   for (int q = threadIdx.x; q < kDigits; q += 256) cnt[q] = 0;
   __syncthreads();
@@ -82,12 +83,11 @@ __global__ __launch_bounds__(256) void k_bin_keys(const float2* __restrict__ X, 
   __syncthreads();
   const int D = digits_used(*btotal, 0);
   for (int q = threadIdx.x; q < D; q += 256) hist[q * tiles + tile] = cnt[q];
-  if (blockIdx.x == 0 && threadIdx.x == 0) *used = (int64_t)D * tiles;
 }
 
 __global__ __launch_bounds__(256) void k_bin_hist(const int* __restrict__ keys, int n, int shift,
                                                   int tiles, const int* __restrict__ btotal,
-                                                  int* hist, int64_t* used) {
+                                                  int* hist) {
   __shared__ int cnt[kDigits];
   for (int q = threadIdx.x; q < kDigits; q += 256) cnt[q] = 0;
   __syncthreads();
@@ -101,7 +101,36 @@ __global__ __launch_bounds__(256) void k_bin_hist(const int* __restrict__ keys, 
   __syncthreads();
   const int D = digits_used(*btotal, shift);
   for (int q = threadIdx.x; q < D; q += 256) hist[q * tiles + tile] = cnt[q];
-  if (blockIdx.x == 0 && threadIdx.x == 0) *used = (int64_t)D * tiles;
+}
+
+// Offsets of a pass, in two steps instead of a scan of the whole count
+// matrix: here one wave per digit row replaces the row's counts (one per
+// tile) by their exclusive prefix and writes the row total; the scatter adds
+// the exclusive prefix of the row totals over the digits. Rows of digits that
+// occur in no key are skipped.
+constexpr int kRowBatch = 8;  // loads of a row in flight together, per lane
+__global__ __launch_bounds__(256) void k_bin_rowscan(int* hist, int tiles, int shift,
+                                                     const int* __restrict__ btotal, int* rtot) {
+  const int q = blockIdx.x * (256 / kWave) + wave_id(), lane = lane_id();
+  if (q >= digits_used(*btotal, shift)) return;
+  int* row = hist + (size_t)q * tiles;
+  int carry = 0;
+  for (int t0 = 0; t0 < tiles; t0 += kRowBatch * kWave) {
+    int v[kRowBatch];
+#pragma unroll
+    for (int j = 0; j < kRowBatch; ++j) {
+      const int t = t0 + j * kWave + lane;
+      v[j] = t < tiles ? row[t] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < kRowBatch; ++j) {
+      const int t = t0 + j * kWave + lane;
+      const int inc = wave_incl_scan(v[j]);
+      if (t < tiles) row[t] = carry + inc - v[j];
+      carry += __builtin_amdgcn_readlane(inc, kWave - 1);
+    }
+  }
+  if (lane == 0) rtot[q] = carry;
 }
 
 // Stable scatter of one pass. vin == nullptr means the payload is the index.
@@ -109,16 +138,33 @@ __global__ __launch_bounds__(256) void k_bin_hist(const int* __restrict__ keys, 
 __global__ __launch_bounds__(256) void k_bin_scatter(const int* __restrict__ kin,
                                                      const int* __restrict__ vin, int n, int shift,
                                                      int tiles, const int* __restrict__ btotal,
-                                                     const int* __restrict__ offs,
+                                                     const int* __restrict__ rowpre,
+                                                     const int* __restrict__ rtot,
                                                      int* kout, int* vout,
                                                      const float2* __restrict__ X, float2* Xs) {
   __shared__ int run[kDigits];
   __shared__ int wc[4][kDigits];
+  __shared__ int sh[256 / kWave + 1];
   const int tid = threadIdx.x, w = wave_id(), lane = lane_id();
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int D = digits_used(*btotal, shift);  // digits past D occur in no key
-  for (int d = tid; d < kDigits; d += 256) {
-    run[d] = d < D ? offs[d * tiles + tile] : 0;
+  // first slot of every digit of this tile: the digit's base (the totals of
+  // the digits below it) plus the tile's prefix within the digit's row
+  constexpr int DPT = kDigits / 256;  // consecutive digits per thread
+  int tot[DPT], pre[DPT], local = 0;
+#pragma unroll
+  for (int k = 0; k < DPT; ++k) {
+    const int d = tid * DPT + k;
+    tot[k] = d < D ? rtot[d] : 0;
+    pre[k] = d < D ? rowpre[(size_t)d * tiles + tile] : 0;
+    local += tot[k];
+  }
+  int dbase = block_excl_scan(local, sh, nullptr);
+#pragma unroll
+  for (int k = 0; k < DPT; ++k) {
+    const int d = tid * DPT + k;
+    run[d] = dbase + pre[k];
+    dbase += tot[k];
     for (int q = 0; q < 4; ++q) wc[q][d] = 0;
   }
   __syncthreads();
@@ -213,16 +259,14 @@ hipError_t launch_bin(Problem& P, const float2* X, hipStream_t s) {
   int* kin = P.keys;
   int* vin = nullptr;
   hipLaunchKernelGGL(k_bin_keys, dim3(tiles), dim3(256), 0, s, X, n, P.vgraph, P.G, P.desc, P.keys,
-                     tiles, P.btotal, P.bin_hist, P.bin_used);
+                     tiles, P.btotal, P.bin_hist);
   for (int p = 0; p < passes; ++p) {
     const int shift = kDigitBits * p;
     if (p > 0)
       hipLaunchKernelGGL(k_bin_hist, dim3(tiles), dim3(256), 0, s, kin, n, shift, tiles, P.btotal,
-                         P.bin_hist, P.bin_used);
-    // only the digit rows in use (the count matrix is digit-major)
-    hipError_t e = exclusive_scan<int>(P.bin_hist, (int64_t)kDigits * tiles, P.bin_hist, P.bin_tsum, s,
-                                       P.bin_used);
-    if (e != hipSuccess) return e;
+                         P.bin_hist);
+    hipLaunchKernelGGL(k_bin_rowscan, dim3(kDigits / (256 / kWave)), dim3(256), 0, s, P.bin_hist, tiles,
+                       shift, P.btotal, P.bin_rtot);
     const bool last = p == passes - 1;
     int *kout, *vout;
     if (last) {
@@ -236,7 +280,7 @@ hipError_t launch_bin(Problem& P, const float2* X, hipStream_t s) {
       vout = P.perm_tmp2;
     }
     hipLaunchKernelGGL(k_bin_scatter, dim3(tiles), dim3(256), 0, s, kin, vin, n, shift, tiles,
-                       P.btotal, P.bin_hist, kout, vout, X, last ? P.xs : nullptr);
+                       P.btotal, P.bin_hist, P.bin_rtot, kout, vout, X, last ? P.xs : nullptr);
     kin = kout;
     vin = vout;
   }

@@ -1,9 +1,7 @@
 // Exclusive prefix sums of a host-known length: tile sums, then each tile
 // scanned and offset by the sum of the tile sums before it (the block adds
 // them itself while there are few tiles; beyond kScanDirectTiles a one-block
-// scan of the tile sums runs in between). out may alias in. An optional
-// device-side length lim (at most N) shortens the scan at run time: tiles
-// past it do nothing, and only out[0, *lim) is written.
+// scan of the tile sums runs in between). out may alias in.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -15,11 +13,8 @@ namespace tsnet {
 constexpr int kTileScan = 2048;
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_tile_sum(const T* __restrict__ in, int64_t N,
-                                                  const int64_t* __restrict__ lim, T* tsum) {
-  if (lim && *lim < N) N = *lim;
+__global__ __launch_bounds__(256) void k_tile_sum(const T* __restrict__ in, int64_t N, T* tsum) {
   const int64_t base = (int64_t)blockIdx.x * kTileScan;
-  if (base >= N) return;  // a tile past the run-time length
   T v = 0;
   for (int k2 = threadIdx.x; k2 < kTileScan; k2 += blockDim.x) {
     const int64_t i = base + k2;
@@ -62,12 +57,8 @@ constexpr int kScanDirectTiles = 4096;
 // the block then adds up for the tiles before its own.
 template <typename T, bool SUMS_SCANNED>
 __global__ __launch_bounds__(256) void k_scan_out(const T* __restrict__ in, int64_t N,
-                                                  const int64_t* __restrict__ lim,
                                                   const T* __restrict__ tsum, T* out) {
   constexpr int per = kTileScan / 256;
-  const bool whole = lim == nullptr;
-  if (!whole && *lim < N) N = *lim;
-  if ((int64_t)blockIdx.x * kTileScan >= N) return;  // a tile past the run-time length
   __shared__ T pre_sh[5];
   T pre = 0;
   if constexpr (SUMS_SCANNED) {
@@ -108,7 +99,7 @@ __global__ __launch_bounds__(256) void k_scan_out(const T* __restrict__ in, int6
     if (i < N) out[i] = run;
     run += loc[q];
   }
-  if (whole && blockIdx.x == gridDim.x - 1 && threadIdx.x == 255) out[N] = run;
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 255) out[N] = run;
 }
 
 template <typename T>
@@ -119,19 +110,18 @@ __global__ void k_scan_empty(T* out) {
 // tsum needs ceil(N / kTileScan) entries; out needs N + 1. No memset: the
 // calls may be captured into a graph.
 template <typename T>
-inline hipError_t exclusive_scan(const T* in, int64_t N, T* out, T* tsum, hipStream_t s,
-                                 const int64_t* lim = nullptr) {
+inline hipError_t exclusive_scan(const T* in, int64_t N, T* out, T* tsum, hipStream_t s) {
   const int tiles = (int)((N + kTileScan - 1) / kTileScan);
   if (tiles == 0) {
     hipLaunchKernelGGL(k_scan_empty<T>, dim3(1), dim3(64), 0, s, out);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_tile_sum<T>, dim3(tiles), dim3(256), 0, s, in, N, lim, tsum);
+  hipLaunchKernelGGL(k_tile_sum<T>, dim3(tiles), dim3(256), 0, s, in, N, tsum);
   if (tiles <= kScanDirectTiles) {
-    hipLaunchKernelGGL((k_scan_out<T, false>), dim3(tiles), dim3(256), 0, s, in, N, lim, tsum, out);
+    hipLaunchKernelGGL((k_scan_out<T, false>), dim3(tiles), dim3(256), 0, s, in, N, tsum, out);
   } else {
     hipLaunchKernelGGL(k_scan_sums<T>, dim3(1), dim3(1024), 0, s, tsum, tiles);
-    hipLaunchKernelGGL((k_scan_out<T, true>), dim3(tiles), dim3(256), 0, s, in, N, lim, tsum, out);
+    hipLaunchKernelGGL((k_scan_out<T, true>), dim3(tiles), dim3(256), 0, s, in, N, tsum, out);
   }
   return hipGetLastError();
 }

@@ -187,9 +187,8 @@ struct Problem {
   int* skeys = nullptr;               // [n] box ids in sorted order
   int* perm = nullptr;                // [n] vertex of each sorted slot
   float2* xs = nullptr;               // [n] X in sorted order
-  int* bin_hist = nullptr;            // [256 tiles + 1] digit counts, then offsets
-  int* bin_tsum = nullptr;            // scan scratch
-  int64_t* bin_used = nullptr;        // counts in use of the current binning pass
+  int* bin_hist = nullptr;            // [kDigits][tiles] digit counts, then their row prefixes
+  int* bin_rtot = nullptr;            // [kDigits] digit totals of the current binning pass
   int* box_off = nullptr;             // [G (cap^2 + 1) + 1] first sorted slot of every box
   int* trim_hist = nullptr;           // [G][2][kTrimBins] bin counts (kept at zero between calls)
   float* slot_z = nullptr;            // [n] Z_i of far points, by sorted slot
