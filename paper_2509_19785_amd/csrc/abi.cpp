@@ -412,7 +412,7 @@ static int ensure_pools(Problem& P, const float2* X, const PlanParams& pp, bool 
   if (!have) {
     PlanParams p0 = pp;
     for (int k = 0; k < POOL_KINDS; ++k) p0.cap[k] = SIZE_MAX;
-    TSNET_LAUNCH(launch_bbox_plan(P, X, p0, s));
+    TSNET_LAUNCH(launch_bbox_plan(P, X, p0, may_trim, s));
     TSNET_LAUNCH(launch_trim_plan(P, X, p0, may_trim, s));
   }
   TSNET_HIP(hipStreamSynchronize(s));
@@ -450,7 +450,7 @@ static int run_interp(Problem& P, const float2* X, const tsnet_params& prm, int 
   for (int k = 0; k < POOL_KINDS; ++k) pp.cap[k] = P.pool_cap[k];
   {
     StageScope t(c, ST_BBOX, s);
-    TSNET_LAUNCH(launch_bbox_plan(P, X, pp, s));
+    TSNET_LAUNCH(launch_bbox_plan(P, X, pp, may_trim, s));
     TSNET_LAUNCH(launch_trim_plan(P, X, pp, may_trim, s));
   }
   {

@@ -15,9 +15,12 @@ namespace tsnet {
 // ---------------------------------------------------------------------------
 // Bounding box per chunk (k_bbox_part, the bounds of every chunk to
 // part[chunk]); then one wave per graph reduces its chunks and starts the
-// graph's descriptor (k_bbox_join): the box, the bin scales of the far-point
-// rule and whether that rule can apply (t = min(far_trim, n / 64) >= 1 and a
-// positive width). The grid itself is planned by k_trim_plan.
+// graph's descriptor (join_bbox, in k_bbox_join or, for a single graph the
+// far-point rule may apply to, in the blocks of k_trim_hist, which saves a
+// launch; in a batch each such block would wait on its own join): the box,
+// the bin scales of the far-point rule and whether that rule can apply
+// (t = min(far_trim, n / 64) >= 1 and a positive width). The grid itself is
+// planned by k_trim_plan.
 //
 // Partial results pass between blocks through a kernel boundary, never
 // through a last-block counter: on this GPU a device-wide fence writes back
@@ -82,17 +85,15 @@ __global__ __launch_bounds__(kBboxThreads) void k_bbox_part(const float2* __rest
   }
 }
 
-// One wave per graph: the graph's box from its chunks, and the far-point
-// rule's parameters (bins, trimming count).
-__global__ __launch_bounds__(256) void k_bbox_join(const float4* __restrict__ part,
-                                                   const GraphInfo* __restrict__ gi, int G,
-                                                   PlanParams pp, GridDesc* desc) {
-  const int g = blockIdx.x * (256 / kWave) + wave_id();
-  if (g >= G) return;
+// A graph's box from its chunks, and the far-point rule's parameters (bins,
+// trimming count), computed by one whole wave (every lane gets the result;
+// min and max do not depend on the order, so any wave anywhere gets the same).
+__device__ GridDesc join_bbox(const float4* __restrict__ part, const GraphInfo& gg,
+                              const PlanParams& pp) {
   float a = FLT_MAX, b = -FLT_MAX, e = FLT_MAX, f = -FLT_MAX;
   int nonfinite = 0;
-  const int c1 = gi[g].chunk_end;
-  for (int k0 = gi[g].chunk_begin + lane_id(); k0 < c1; k0 += kPartBatch * kWave) {
+  const int c1 = gg.chunk_end;
+  for (int k0 = gg.chunk_begin + lane_id(); k0 < c1; k0 += kPartBatch * kWave) {
     float4 q[kPartBatch];  // the batch's loads in flight together
 #pragma unroll
     for (int j = 0; j < kPartBatch; ++j)
@@ -114,7 +115,6 @@ __global__ __launch_bounds__(256) void k_bbox_join(const float4* __restrict__ pa
   e = wave_min(e);
   f = wave_max(f);
   nonfinite = __any(nonfinite);
-  if (lane_id() != 0) return;
   if (!(b >= a)) {  // no finite point at all
     a = b = e = f = 0.f;
   }
@@ -127,17 +127,30 @@ __global__ __launch_bounds__(256) void k_bbox_join(const float4* __restrict__ pa
   const double wx = (double)b - (double)a, wy = (double)f - (double)e;
   d.s_x = wx > 0.0 ? (double)kTrimBins / wx : 0.0;
   d.s_y = wy > 0.0 ? (double)kTrimBins / wy : 0.0;
-  const int t = min(pp.far_trim, gi[g].n / kTrimMinPoints);
+  const int t = min(pp.far_trim, gg.n / kTrimMinPoints);
   d.trim_t = t;
   d.trimmed = (t >= 1 && fmax(wx, wy) > 0.0 && !nonfinite) ? 1 : 0;
-  desc[g] = d;
+  return d;
 }
 
-hipError_t launch_bbox_plan(Problem& P, const float2* X, const PlanParams& pp, hipStream_t s) {
+// One wave per graph: join_bbox into the graph's descriptor. For a single
+// graph the far-point rule may apply to, k_trim_hist does this itself.
+__global__ __launch_bounds__(256) void k_bbox_join(const float4* __restrict__ part,
+                                                   const GraphInfo* __restrict__ gi, int G,
+                                                   PlanParams pp, GridDesc* desc) {
+  const int g = blockIdx.x * (256 / kWave) + wave_id();
+  if (g >= G) return;
+  const GridDesc d = join_bbox(part, gi[g], pp);
+  if (lane_id() == 0) desc[g] = d;
+}
+
+hipError_t launch_bbox_plan(Problem& P, const float2* X, const PlanParams& pp, bool with_hist,
+                            hipStream_t s) {
   hipLaunchKernelGGL(k_bbox_part, dim3(P.num_chunks), dim3(kBboxThreads), 0, s, X, P.chunk_start,
                      P.chunk_end, P.bbox_part);
-  hipLaunchKernelGGL(k_bbox_join, dim3((P.G + 3) / 4), dim3(256), 0, s, P.bbox_part, P.ginfo, P.G,
-                     pp, P.desc);
+  if (!(with_hist && P.G == 1))  // else the histogram's blocks join the box (one launch fewer)
+    hipLaunchKernelGGL(k_bbox_join, dim3((P.G + 3) / 4), dim3(256), 0, s, P.bbox_part, P.ginfo, P.G,
+                       pp, P.desc);
   return hipGetLastError();
 }
 
@@ -159,11 +172,28 @@ constexpr int kTrimChunksSingle = 4;
 __global__ __launch_bounds__(kTrimThreads) void k_trim_hist(
     const float2* __restrict__ X, const int* __restrict__ chunk_graph,
     const int* __restrict__ chunk_start, const int* __restrict__ chunk_end, int nc, int cpb,
-    const GridDesc* __restrict__ desc, int* hist) {
+    int join, const float4* __restrict__ part, const GraphInfo* __restrict__ gi, PlanParams pp,
+    GridDesc* desc, int* hist) {
   __shared__ int hx[kTrimBins], hy[kTrimBins];
+  __shared__ GridDesc dsh;
   const int c0 = blockIdx.x * cpb, c1 = min(c0 + cpb, nc);
   const int g = chunk_graph[c0];
-  const GridDesc d = desc[g];
+  if (join) {
+    // the graph's box, joined by the first wave of every block (the same in
+    // each); the block of the graph's first chunk starts its descriptor
+    if (wave_id() == 0) {
+      const GraphInfo gg = gi[g];
+      const GridDesc dj = join_bbox(part, gg, pp);
+      if (lane_id() == 0) {
+        dsh = dj;
+        if (c0 == gg.chunk_begin) desc[g] = dj;
+      }
+    }
+  } else if (threadIdx.x == 0) {
+    dsh = desc[g];
+  }
+  __syncthreads();
+  const GridDesc d = dsh;
   if (!d.trimmed) return;
   for (int b = threadIdx.x; b < kTrimBins; b += kTrimThreads) hx[b] = hy[b] = 0;
   __syncthreads();
@@ -425,8 +455,8 @@ hipError_t launch_trim_plan(Problem& P, const float2* X, const PlanParams& pp, b
   if (with_hist) {
     const int cpb = P.G == 1 ? kTrimChunksSingle : 1;
     hipLaunchKernelGGL(k_trim_hist, dim3((P.num_chunks + cpb - 1) / cpb), dim3(kTrimThreads), 0, s, X,
-                       P.chunk_graph, P.chunk_start, P.chunk_end, P.num_chunks, cpb, P.desc,
-                       P.trim_hist);
+                       P.chunk_graph, P.chunk_start, P.chunk_end, P.num_chunks, cpb,
+                       P.G == 1 ? 1 : 0, P.bbox_part, P.ginfo, pp, P.desc, P.trim_hist);
   }
   hipLaunchKernelGGL(k_trim_plan, dim3(P.G), dim3(kPlanThreads), 0, s, P.desc, P.trim_hist, pp,
                      P.ctx->status, P.G == 1 ? P.btotal : nullptr);

@@ -235,7 +235,8 @@ int fail(int code, const std::string& msg);
 // Every launcher enqueues on `s` and returns hipGetLastError().
 
 // per-evaluation path (iter.hip, bin.hip, attract.hip)
-hipError_t launch_bbox_plan(Problem& P, const float2* X, const PlanParams& pp, hipStream_t s);
+hipError_t launch_bbox_plan(Problem& P, const float2* X, const PlanParams& pp, bool with_hist,
+                            hipStream_t s);
 // `pp` carries the pool capacities; the plan writes the uncapped needs to pp.need
 // far-point rule: bin counts (only when some graph may set points apart), then the grid plan
 hipError_t launch_trim_plan(Problem& P, const float2* X, const PlanParams& pp, bool with_hist,
