@@ -493,6 +493,7 @@ def kernel_algorithmic_bytes(kernel: str, n: int, nnz: int, ni: int):
         "k_fft_cols": 3 * ng * Mh * 8 + 4 * Mh * Mh * 4 + 7 * Mh * ng * 8,
         "k_fft_rows_inv": 7 * Mh * ng * 8 + 32 * ng * ng,
         "k_step": 56 * n,
+        "k_step_pairs": 56 * n,
     }.get(kernel)
 
 
@@ -517,7 +518,8 @@ def kernel_table(trace_csv: str, info_path: str):
         if m:
             name = m.group(1) + (" (M <= 3072)" if int(m.group(2)) <= 3072 else " (M 6144)")
         seq[name].append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
-    steps = sorted(seq["k_step"])
+    # the step runs as k_step_pairs where its arrays are 16-byte aligned, else as k_step
+    steps = sorted(seq["k_step"] + seq["k_step_pairs"])
     per = FIXED_GRID_EVALS
     # phase p spans its per-evaluation steps (the last step of the previous phase to its own last)
     ends = [steps[(p + 1) * per - 1][0] for p in range(len(phases))]
