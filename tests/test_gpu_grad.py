@@ -454,6 +454,45 @@ def test_step_matches_oracle(api, ctx, grid_problem):
         assert np.all(np.abs(tX.cpu().numpy() - eX) <= bX)
 
 
+def test_step_odd_n_and_unaligned_arrays(api, ctx):
+    """The step at an odd n (the last vertex outside the pairs of the 16-byte
+    path) and on arrays offset by 8 bytes (the one-vertex path): both against
+    the step oracle, and bit for bit against each other (same arithmetic)."""
+    g = graphs.grid(31, 33)  # n = 1023
+    P = affinities.build_P(g.indptr, g.indices, 40.0, seed=0)
+    prob = _upload(api, ctx, P)
+    n = g.n
+    assert n % 2 == 1
+    rng = np.random.default_rng(6)
+    X = rng.normal(0, 1, (n, 2)).astype(np.float32)
+    U = rng.normal(0, 0.01, (n, 2)).astype(np.float32)
+    K = rng.uniform(0.005, 3, (n, 2)).astype(np.float32)
+    G = rng.normal(0, 1e-3, (n, 2)).astype(np.float32)
+    it, sp = 3, api.StepParams()
+    eX, eU, eK = ostep.step(X, U, K, G, it, ostep.StepParams(eta=sp.eta))
+    out = {}
+    for offset in (0, 1):  # rows of 8 bytes: offset 1 leaves every array 8 mod 16
+        bufs = []
+        for a in (X, U, K, G):
+            t = torch.zeros((n + offset, 2), dtype=torch.float32, device="cuda")
+            t[offset:] = torch.tensor(a, device="cuda")
+            bufs.append(t[offset:])
+        assert all((b.data_ptr() % 16 == 0) == (offset == 0) for b in bufs)
+        tX, tU, tK, tG = bufs
+        prob.step(tX, tU, tK, tG, it, sp)
+        torch.cuda.synchronize()
+        out[offset] = [t.cpu().numpy() for t in (tX, tU, tK)]
+        e32 = 2.0 ** -24
+        bU = 4 * e32 * (np.abs(0.5 * U) + np.abs(200.0 * eK * G))
+        bX = 4 * e32 * (np.abs(X) + np.abs(eU)) + 2 * bU
+        gX, gU, gK = out[offset]
+        assert np.allclose(gK, eK, rtol=2e-7, atol=0)
+        assert np.all(np.abs(gU - eU) <= bU)
+        assert np.all(np.abs(gX - eX) <= bX)
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
 def test_cost_matches_oracle(api, ctx, grid_problem):
     g, P = grid_problem
     prob = _upload(api, ctx, P)
