@@ -467,21 +467,6 @@ hipError_t launch_trim_plan(Problem& P, const float2* X, const PlanParams& pp, b
 }
 
 // ---------------------------------------------------------------------------
-// Gather (Sec. 2.3 / Sec. 3.3): interpolate the 8 node potentials to every
-// point in sorted order (coordinates and box ids come from the binning, so a
-// wave reads few nodes), then form
-//   F_rep = (x - c) phi[K2,1] - phi[K2,x],  F_ent = (x - c) phi[Ke,1] - phi[Ke,x],
-//   Z_i = phi[K1,1] - 1 (the self term K1(0) = 1),
-// and write them at the vertex of the slot (F_rep and F_ent as one 16-byte
-// record, Z_i only when it is asked for). Far points (the last box of their
-// graph) were summed by k_far: their F_rep and F_ent are in place, their Z_i
-// and ln sum come from slot_z and slot_ln.
-// kGatherSplit blocks of kGatherThreads per chunk, each taking one part of
-// its sorted slots (several blocks of a CU keep more points in flight than one
-// large block, which the gather's registers would make the only one). Each
-// block also sums the Z_i of its part (compensated FP32, in sorted order) into
-// zpart[chunk * kGatherSplit + part]; k_zsum then adds every graph's part sums
-// in FP64 (fixed order, so Z is reproducible) into zg and Z_out.
 // phi = the 8 potential channels at x, interpolated from the 3 x 3 nodes of
 // box (bx, by): the Lagrange weights of the point times the node values (the
 // potentials are 4 planes, one per channel pair, of ng^2 float2 nodes).
@@ -512,6 +497,21 @@ __device__ __forceinline__ void gather_box(const float* __restrict__ pg, const G
   }
 }
 
+// Gather (Sec. 2.3 / Sec. 3.3): interpolate the 8 node potentials to every
+// point in sorted order (coordinates and box ids come from the binning, so a
+// wave reads few nodes), then form
+//   F_rep = (x - c) phi[K2,1] - phi[K2,x],  F_ent = (x - c) phi[Ke,1] - phi[Ke,x],
+//   Z_i = phi[K1,1] - 1 (the self term K1(0) = 1),
+// and write them at the vertex of the slot (F_rep and F_ent as one 16-byte
+// record, Z_i only when it is asked for). Far points (the last box of their
+// graph) were summed by k_far: their F_rep and F_ent are in place, their Z_i
+// and ln sum come from slot_z and slot_ln.
+// kGatherSplit blocks of kGatherThreads per chunk, each taking one part of
+// its sorted slots (several blocks of a CU keep more points in flight than one
+// large block, which the gather's registers would make the only one). Each
+// block also sums the Z_i of its part (compensated FP32, in sorted order) into
+// zpart[chunk * kGatherSplit + part]; k_zsum then adds every graph's part sums
+// in FP64 (fixed order, so Z is reproducible) into zg and Z_out.
 constexpr int kGatherThreads = 256;
 static_assert(kGatherSplit * kGatherThreads * 2 == kChunk, "two points per thread");
 
